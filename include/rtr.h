@@ -1,0 +1,210 @@
+/*
+ * rtr.h - C ABI of the gfx950 randomized tensor-ring decomposition library (librtr.so).
+ *
+ * Method: Yuan, Li, Cao, Zhao, "Randomized Tensor Ring Decomposition and Its Application to
+ * Large-scale Data Reconstruction" (arXiv:1901.01652), Algorithm 1 (rTRD).  Problem
+ * statement (Eq. 4): given a dense order-N tensor X, projection sizes K_n and TR-ranks
+ * R_1..R_N, find cores G_n (R_n x I_n x R_{n+1}, R_{N+1} = R_1) minimising
+ * ||X - Psi([G_n])||_F, where Psi evaluates Eq. (1).
+ *
+ * The five entry points are the stages of Algorithm 1:
+ *   rtr_sketch       steps 3-6 (+ power iterations named after Alg. 1): Gaussian sketch
+ *                    Y_n = X_(n) M_n, economy QR -> Q_n
+ *   rtr_compress     step 7 read cumulatively (Eq. 3): P = X x_1 Q_1^T ... x_N Q_N^T
+ *   rtr_decompose    step 9: TR-ALS (or TR-SVD) on the small tensor P -> cores Z_n
+ *   rtr_backproject  steps 10-12: G_n = Z_n x_2 Q_n
+ *   rtr_residual     Sec. 4 error measure: ||X - Psi([G_n])||_F^2 and ||X||_F^2
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Tensors are dense, row-major (last index fastest), 1 <= N <= RTR_MAX_ORDER modes
+ *   (N >= 2 for the decomposition), every dimension >= 1.
+ * - Mode-n unfolding X_(n): row i_n, column = row-major index of the other indices in
+ *   their natural order (i_1..i_{n-1}, i_{n+1}..i_N).  TR unfolding X_<n>: columns are
+ *   row-major over the cyclic order (i_{n+1}, .., i_N, i_1, .., i_{n-1}).
+ * - Packed per-mode buffers: Q holds Q_1..Q_N back to back, Q_n row-major I_n x K'_n with
+ *   K'_n = min(K_n, I_n), at offset sum_{m<n} I_m K'_m.  Core buffers hold cores back to
+ *   back, core n row-major (R_n, D_n, R_{n+1}) with D_n = K'_n (Z) or I_n (G), at offset
+ *   sum_{m<n} R_m D_m R_{m+1}.  P is row-major K'_1 x .. x K'_N.
+ * - K_n >= I_n means mode n is not projected (Q_n = identity, K'_n = I_n).
+ * - Precision: Q, P, Z, G and every scalar output are FP64.  X is FP64 or FP32.  The
+ *   ``compute`` argument picks the arithmetic of the passes over X: RTR_F64 (X FP64),
+ *   RTR_F32 (X FP32, FP32 products and accumulation), RTR_BF16 (X FP32 rounded to bf16 on
+ *   load, bf16 products on the matrix cores, FP32 accumulation; the compression adds the
+ *   FP32 refinement terms X_hi Q_lo + X_lo Q_hi).  QR, power-iteration orthonormalisation
+ *   and the ALS normal-equation solves are always FP64.
+ * - Random numbers: the Gaussian matrix of Alg. 1 step 4 is never stored.  Entry (j, k)
+ *   of M_n is element e = j*K'_n + k of the Philox4x32-10 stream with key (seed mod 2^32,
+ *   seed >> 32) and counter (e>>2 low word, e>>2 high word, 0x01000000 | n << 16,
+ *   tensor_id), Box-Muller on word pairs (w0,w1) -> lanes 0,1 and (w2,w3) -> lanes 2,3,
+ *   uniforms (w + 1/2) 2^-32.
+ *
+ * Memory and execution
+ * --------------------
+ * - Every array argument named "device" is caller-owned device memory; the library reads
+ *   or writes it only inside the work it enqueues and never frees it.  Host arrays
+ *   (dims, K, R, options) are read before the call returns.
+ * - Calls enqueue work on ``stream`` (a hipStream_t; NULL = the legacy default stream) and
+ *   return without waiting, except where a call says it synchronises.
+ * - The handle owns a device workspace grown on demand (growing synchronises the device)
+ *   and released by rtr_destroy.  A handle is not thread-safe, and its workspace is shared
+ *   by all its calls: issue a handle's calls on one stream, or synchronise between streams.
+ * - Errors: argument checks happen before anything is enqueued and return
+ *   RTR_ERR_INVALID_ARG / RTR_ERR_UNSUPPORTED with a message in rtr_last_error(h).  HIP
+ *   failures return RTR_ERR_DEVICE.  No C++ exception crosses the ABI and nothing aborts.
+ *   Numerical trouble found on the device (a Gram matrix that is not positive definite in
+ *   TR-ALS) sets bits of a device status word read by rtr_status_sync.
+ * - Results are deterministic: same inputs, seed and device give bitwise identical outputs
+ *   (fixed-order reductions, no floating-point atomics).
+ */
+#ifndef RTR_H
+#define RTR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RTR_MAX_ORDER 8
+#define RTR_MAX_RANK 32
+
+typedef enum {
+  RTR_OK = 0,
+  RTR_ERR_INVALID_ARG = 1,  /* a size, pointer or option is out of range */
+  RTR_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement */
+  RTR_ERR_OOM = 3,          /* workspace allocation failed */
+  RTR_ERR_DEVICE = 4,       /* a HIP runtime call failed */
+  RTR_ERR_NUMERICAL = 5,    /* device status word reported a numerical failure */
+  RTR_ERR_INTERNAL = 6
+} rtr_status;
+
+typedef enum { RTR_F64 = 0, RTR_F32 = 1, RTR_BF16 = 2 } rtr_dtype;
+
+typedef enum { RTR_METHOD_ALS = 0, RTR_METHOD_SVD = 1 } rtr_method;
+
+/* Device status word bits (rtr_status_sync). */
+#define RTR_STATUS_CHOLESKY_FAILED 0x1u /* an ALS Gram matrix was not positive definite;
+                                           that core update was skipped */
+
+typedef struct rtr_context* rtr_handle;
+
+/* Create a handle bound to HIP device ``device``.  *out is set to NULL on failure. */
+rtr_status rtr_create(int device, rtr_handle* out);
+
+/* Destroy a handle: synchronises the device, frees the workspace.  NULL is accepted. */
+rtr_status rtr_destroy(rtr_handle h);
+
+/* Message of the last failed call on ``h`` ("" if none).  Valid until the next call. */
+const char* rtr_last_error(rtr_handle h);
+
+/* Static name of a status code. */
+const char* rtr_status_string(rtr_status s);
+
+/*
+ * Alg. 1 steps 3-6 for every mode, plus ``power_iters`` rounds of subspace iteration
+ * (Halko, Martinsson, Tropp 2011, Alg. 4.4; named after Alg. 1 as an option).
+ *   X          device, row-major I_1 x .. x I_N, dtype x_dtype (RTR_F64 or RTR_F32)
+ *   dims       host, N entries I_n >= 1
+ *   K          host, N entries K_n >= 1 (K_n >= I_n: identity, no sketch for that mode)
+ *   seed, tensor_id   select the Gaussian stream (see above)
+ *   compute    RTR_F64 (needs X FP64), RTR_F32 or RTR_BF16 (need X FP32)
+ *   Q          device, FP64, packed Q_n (I_n x K'_n, orthonormal columns, R_ii >= 0)
+ * Y_n is formed from the original X for every mode.  With power_iters = q the result is
+ * qr((X_(n) X_(n)^T)^q X_(n) M_n); each round re-orthonormalises once in FP64.
+ */
+rtr_status rtr_sketch(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
+                      const int64_t* dims, const int32_t* K, int32_t power_iters,
+                      uint64_t seed, uint32_t tensor_id, rtr_dtype compute, double* Q,
+                      void* stream);
+
+/*
+ * Alg. 1 step 7 read cumulatively (Eq. 3): P = X x_1 Q_1^T x_2 .. x_N Q_N^T.
+ *   X, x_dtype, order, dims, K, compute   as for rtr_sketch
+ *   Q          device, FP64, packed Q_n from rtr_sketch
+ *   P          device, FP64, row-major K'_1 x .. x K'_N
+ *   p_norm2    device, 1 FP64 (may be NULL): ||P||_F^2
+ */
+rtr_status rtr_compress(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
+                        const int64_t* dims, const int32_t* K, const double* Q,
+                        rtr_dtype compute, double* P, double* p_norm2, void* stream);
+
+typedef struct {
+  rtr_method method;  /* RTR_METHOD_ALS or RTR_METHOD_SVD */
+  int32_t max_sweeps; /* ALS: sweeps over n = 1..N (>= 1) */
+  double tol;         /* ALS: stop after sweep s >= 2 once |e(s) - e(s-1)| < tol; 0 = off */
+  double eps;         /* SVD: relative error bound ||P - Psi(Z)|| <= eps ||P|| */
+} rtr_decompose_opts;
+
+/*
+ * Alg. 1 step 9 on the projected tensor P (row-major K'_1 x .. x K'_N, FP64, device).
+ *   Kp         host, N entries K'_n (the dimensions of P)
+ *   R          host, N ranks R_1..R_N (R_{N+1} = R_1), 1 <= R_n <= RTR_MAX_RANK and
+ *              R_n R_{n+1} <= prod_{m != n} K'_m (each core's least squares is well posed)
+ *   Z_init     device, packed initial cores (R_n, K'_n, R_{n+1}); random N(0,1) init or a
+ *              warm start.  May alias Z.
+ *   Z          device, packed output cores (same layout)
+ *   err_trace  device, max_sweeps FP64: ||P - Psi(Z)||_F / ||P||_F after each sweep
+ *              (entries after the last sweep run are left untouched)
+ *   sweeps_run device, 1 int32: sweeps performed
+ * TR-ALS updates core n by the exact least-squares solution of Eq. (2) restricted to P
+ * (normal equations, FP64 Cholesky).  A Gram matrix that is not positive definite sets
+ * RTR_STATUS_CHOLESKY_FAILED and leaves that core unchanged.
+ * RTR_METHOD_SVD returns RTR_ERR_UNSUPPORTED in this build.
+ */
+rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int32_t* Kp,
+                         const int32_t* R, const rtr_decompose_opts* opts,
+                         const double* Z_init, double* Z, double* err_trace,
+                         int32_t* sweeps_run, void* stream);
+
+/*
+ * Alg. 1 steps 10-12, read as the product over the physical mode: G_n = Z_n x_2 Q_n,
+ * G_n[a, i, b] = sum_k Q_n[i, k] Z_n[a, k, b].
+ *   dims, K, R host;  Z, Q device FP64 packed;  G device FP64 packed (R_n, I_n, R_{n+1}).
+ */
+rtr_status rtr_backproject(rtr_handle h, int32_t order, const int64_t* dims,
+                           const int32_t* K, const int32_t* R, const double* Z,
+                           const double* Q, double* G, void* stream);
+
+/*
+ * Sec. 4 error measure, explicit: out[0] = ||X - Psi([G_n])||_F^2, out[1] = ||X||_F^2,
+ * accumulated in FP64 (RSE = sqrt(out[0] / out[1])).
+ *   X device (x_dtype RTR_F64 / RTR_F32);  G device FP64 packed (R_n, I_n, R_{n+1});
+ *   out device, 2 FP64.
+ */
+rtr_status rtr_residual(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
+                        const int64_t* dims, const int32_t* R, const double* G,
+                        double* out, void* stream);
+
+/*
+ * The Gaussian stream behind the test matrices of Alg. 1 step 4 (see "Random numbers"
+ * above): out[t] = element start + t of stream (seed, stream_word, tensor_id), t < count.
+ * dtype RTR_F64 gives the FP64 Box-Muller values used by the FP64 sketch, RTR_F32 the FP32
+ * values used by the FP32 sketch (the BF16 sketch rounds those to bf16).  The Gaussian
+ * matrix of mode n is stream_word 0x01000000 | n << 16.
+ *   out  device, count values of the given dtype.
+ */
+rtr_status rtr_normals(rtr_handle h, uint64_t seed, uint32_t stream_word, uint32_t tensor_id,
+                       int64_t start, int64_t count, rtr_dtype dtype, void* out, void* stream);
+
+/* Wait for ``stream``, read and clear the device status word.  *bits gets the
+ * RTR_STATUS_* bits; returns RTR_ERR_NUMERICAL if any bit was set. */
+rtr_status rtr_status_sync(rtr_handle h, void* stream, uint32_t* bits);
+
+/*
+ * Kernel timing with HIP events on the launch stream (off by default).  While enabled,
+ * every kernel launch is bracketed by two events.  rtr_profile_read synchronises the
+ * device and returns the summed duration (ms) and launch count of kernel ``name``;
+ * rtr_profile_reset drops all records.
+ */
+rtr_status rtr_profile_enable(rtr_handle h, int32_t on);
+rtr_status rtr_profile_reset(rtr_handle h);
+rtr_status rtr_profile_read(rtr_handle h, const char* name, double* total_ms,
+                            int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTR_H */

@@ -1,0 +1,275 @@
+"""Python binding of librtr.so, the gfx950 randomized tensor-ring decomposition library.
+
+Argument marshalling only: every stage runs in the library's HIP kernels.  torch tensors
+supply device memory and the current HIP stream.  Importing this package fails loudly if
+librtr.so has not been built (``python paper_1901_01652_amd/build.py``); there is no CPU
+fallback.
+
+The functions mirror the C ABI of include/rtr.h (Yuan et al., arXiv:1901.01652, Alg. 1):
+  rtr_sketch       steps 3-6 (+ power iterations)  -> packed Q_n
+  rtr_compress     step 7, Eq. (3)                  -> P
+  rtr_decompose    step 9 (TR-ALS)                  -> packed cores Z_n, error trace
+  rtr_backproject  steps 10-12                      -> packed cores G_n
+  rtr_residual     Sec. 4 error measure             -> [||X - Psi(G)||^2, ||X||^2]
+"""
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librtr.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "rtr.h")
+
+RTR_F64, RTR_F32, RTR_BF16 = 0, 1, 2
+RTR_METHOD_ALS, RTR_METHOD_SVD = 0, 1
+RTR_STATUS_CHOLESKY_FAILED = 0x1
+MAX_ORDER = 8
+
+_DTYPES = {"f64": RTR_F64, "f32": RTR_F32, "bf16": RTR_BF16}
+
+
+class RtrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(msg)
+        self.code = code
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("max_sweeps", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python paper_1901_01652_amd/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64, dp = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                  ctypes.c_uint64, ctypes.c_double)
+    P64 = ctypes.POINTER(i64)
+    P32 = ctypes.POINTER(i32)
+    sig = {
+        "rtr_create": [ctypes.c_int, ctypes.POINTER(vp)],
+        "rtr_destroy": [vp],
+        "rtr_sketch": [vp, vp, ctypes.c_int, i32, P64, P32, i32, u64, u32, ctypes.c_int, vp, vp],
+        "rtr_compress": [vp, vp, ctypes.c_int, i32, P64, P32, vp, ctypes.c_int, vp, vp, vp],
+        "rtr_decompose": [vp, vp, i32, P32, P32, ctypes.POINTER(_Opts), vp, vp, vp, vp, vp],
+        "rtr_backproject": [vp, i32, P64, P32, P32, vp, vp, vp, vp],
+        "rtr_residual": [vp, vp, ctypes.c_int, i32, P64, P32, vp, vp, vp],
+        "rtr_normals": [vp, u64, u32, u32, i64, i64, ctypes.c_int, vp, vp],
+        "rtr_status_sync": [vp, vp, ctypes.POINTER(u32)],
+        "rtr_profile_enable": [vp, i32],
+        "rtr_profile_reset": [vp],
+        "rtr_profile_read": [vp, ctypes.c_char_p, ctypes.POINTER(dp), P64],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.rtr_last_error.argtypes = [vp]
+    lib.rtr_last_error.restype = ctypes.c_char_p
+    lib.rtr_status_string.argtypes = [ctypes.c_int]
+    lib.rtr_status_string.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def header_symbols():
+    """Function names declared in include/rtr.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:rtr_status|const char\*)\s+(rtr_\w+)\s*\(", txt, re.M)))
+
+
+def status_string(code):
+    return lib.rtr_status_string(int(code)).decode()
+
+
+class Handle:
+    """Owns an rtr_handle (device workspace, status word, timing records)."""
+
+    def __init__(self, device=0):
+        self.ptr = ctypes.c_void_p()
+        st = lib.rtr_create(int(device), ctypes.byref(self.ptr))
+        if st != 0:
+            raise RtrError(st, f"rtr_create({device}) failed: {status_string(st)}")
+        self.device = device
+
+    def close(self):
+        if self.ptr:
+            lib.rtr_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self):
+        return lib.rtr_last_error(self.ptr).decode()
+
+    def check(self, st):
+        if st != 0:
+            raise RtrError(st, f"{status_string(st)}: {self.last_error()}")
+
+
+def _i64(vals):
+    return (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
+
+
+def _i32(vals):
+    return (ctypes.c_int32 * len(vals))(*[int(v) for v in vals])
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
+
+
+def _stream(stream, device):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _xdtype(X):
+    if X.dtype == torch.float64:
+        return RTR_F64
+    if X.dtype == torch.float32:
+        return RTR_F32
+    raise TypeError("X must be float64 or float32")
+
+
+def keff(dims, K):
+    return [min(int(k), int(d)) for k, d in zip(K, dims)]
+
+
+def q_size(dims, K):
+    return sum(d * k for d, k in zip(dims, keff(dims, K)))
+
+
+def core_shapes(D, R):
+    N = len(D)
+    return [(int(R[n]), int(D[n]), int(R[(n + 1) % N])) for n in range(N)]
+
+
+def pack(cores, device=None, dtype=torch.float64):
+    """Concatenate cores (or Q_n) into one flat tensor in the packed layout."""
+    parts = [torch.as_tensor(c, dtype=dtype).reshape(-1) for c in cores]
+    out = torch.cat(parts)
+    return out.to(device) if device is not None else out
+
+
+def unpack(flat, shapes):
+    """Views of a packed buffer as tensors of the given shapes."""
+    out, off = [], 0
+    for s in shapes:
+        n = 1
+        for x in s:
+            n *= x
+        out.append(flat[off:off + n].view(*s))
+        off += n
+    return out
+
+
+def q_shapes(dims, K):
+    return [(int(d), k) for d, k in zip(dims, keff(dims, K))]
+
+
+def rtr_sketch(h, X, K, power_iters=0, seed=0, tensor_id=0, compute=None, Q=None, stream=None):
+    """Alg. 1 steps 3-6: packed FP64 Q_n (I_n x K'_n) of tensor X (device)."""
+    dims = list(X.shape)
+    assert X.is_contiguous()
+    xd = _xdtype(X)
+    cd = xd if compute is None else _DTYPES[compute]
+    if Q is None:
+        Q = torch.empty(q_size(dims, K), dtype=torch.float64, device=X.device)
+    h.check(lib.rtr_sketch(h.ptr, _ptr(X), xd, len(dims), _i64(dims), _i32(K), int(power_iters),
+                           int(seed), int(tensor_id), cd, _ptr(Q), _stream(stream, X.device)))
+    return Q
+
+
+def rtr_compress(h, X, K, Q, compute=None, P=None, p_norm2=None, stream=None):
+    """Alg. 1 step 7 / Eq. (3): P (K'_1 x .. x K'_N, FP64) from X and packed Q."""
+    dims = list(X.shape)
+    assert X.is_contiguous()
+    xd = _xdtype(X)
+    cd = xd if compute is None else _DTYPES[compute]
+    if P is None:
+        P = torch.empty(keff(dims, K), dtype=torch.float64, device=X.device)
+    h.check(lib.rtr_compress(h.ptr, _ptr(X), xd, len(dims), _i64(dims), _i32(K), _ptr(Q), cd,
+                             _ptr(P), _ptr(p_norm2), _stream(stream, X.device)))
+    return P
+
+
+def rtr_decompose(h, P, R, Z_init, max_sweeps, tol=0.0, method="als", eps=0.0, Z=None,
+                  err_trace=None, sweeps_run=None, stream=None):
+    """Alg. 1 step 9: TR-ALS on P from packed Z_init; returns (Z, err_trace, sweeps_run)."""
+    Kp = list(P.shape)
+    if Z is None:
+        Z = torch.empty_like(Z_init)
+    if err_trace is None:
+        err_trace = torch.zeros(max_sweeps, dtype=torch.float64, device=P.device)
+    if sweeps_run is None:
+        sweeps_run = torch.zeros(1, dtype=torch.int32, device=P.device)
+    opts = _Opts(RTR_METHOD_ALS if method == "als" else RTR_METHOD_SVD, int(max_sweeps), float(tol),
+                 float(eps))
+    h.check(lib.rtr_decompose(h.ptr, _ptr(P), len(Kp), _i32(Kp), _i32(R), ctypes.byref(opts),
+                              _ptr(Z_init), _ptr(Z), _ptr(err_trace), _ptr(sweeps_run),
+                              _stream(stream, P.device)))
+    return Z, err_trace, sweeps_run
+
+
+def rtr_backproject(h, dims, K, R, Z, Q, G=None, stream=None):
+    """Alg. 1 steps 10-12: packed G_n = Z_n x_2 Q_n."""
+    if G is None:
+        G = torch.empty(sum(a * b * c for a, b, c in core_shapes(dims, R)), dtype=torch.float64,
+                        device=Z.device)
+    h.check(lib.rtr_backproject(h.ptr, len(dims), _i64(dims), _i32(K), _i32(R), _ptr(Z), _ptr(Q),
+                                _ptr(G), _stream(stream, Z.device)))
+    return G
+
+
+def rtr_residual(h, X, R, G, out=None, stream=None):
+    """Sec. 4: [||X - Psi(G)||^2, ||X||^2] (FP64, device)."""
+    dims = list(X.shape)
+    if out is None:
+        out = torch.zeros(2, dtype=torch.float64, device=X.device)
+    h.check(lib.rtr_residual(h.ptr, _ptr(X), _xdtype(X), len(dims), _i64(dims), _i32(R), _ptr(G),
+                             _ptr(out), _stream(stream, X.device)))
+    return out
+
+
+def rtr_normals(h, seed, stream_word, tensor_id, start, count, dtype="f64", device=0, out=None,
+                stream=None):
+    """Elements [start, start+count) of the Gaussian stream of Alg. 1 step 4 (device tensor)."""
+    td = torch.float64 if dtype == "f64" else torch.float32
+    if out is None:
+        out = torch.empty(int(count), dtype=td, device=f"cuda:{device}")
+    h.check(lib.rtr_normals(h.ptr, int(seed), int(stream_word), int(tensor_id), int(start),
+                            int(count), _DTYPES[dtype], _ptr(out), _stream(stream, out.device)))
+    return out
+
+
+def rtr_status_sync(h, stream=None, device=0):
+    bits = ctypes.c_uint32(0)
+    st = lib.rtr_status_sync(h.ptr, _stream(stream, device), ctypes.byref(bits))
+    if st not in (0, 5):
+        h.check(st)
+    return int(bits.value)
+
+
+def rtr_profile_enable(h, on=True):
+    h.check(lib.rtr_profile_enable(h.ptr, 1 if on else 0))
+
+
+def rtr_profile_reset(h):
+    h.check(lib.rtr_profile_reset(h.ptr))
+
+
+def rtr_profile_read(h, name):
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    h.check(lib.rtr_profile_read(h.ptr, name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, int(n.value)

@@ -1,0 +1,121 @@
+// Alg. 1 step 7 read cumulatively (Eq. 3): P = X x_1 Q_1^T ... x_N Q_N^T as a chain of
+// mode products, mode 1 first.  Each product maps in (A x In x B) to out (A x K x B):
+// out[a, k, b] = sum_i in[a, i, b] Q[i, k].  A thread owns one (a, b) fiber, reads it once
+// (coalesced along b) and keeps its K sums in registers; Q is read with uniform
+// (scalar-cache) loads.
+//
+// The first product reads X in the requested arithmetic: FP64, FP32, or bf16 operands with
+// the FP32 refinement X_hi Q_hi + X_hi Q_lo + X_lo Q_hi (X = X_hi + X_lo, Q = Q_hi + Q_lo
+// split into bf16 pairs, FP32 accumulation).  Later products act on the small FP64
+// intermediate.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace rtr {
+
+constexpr int kTtmKMax = 64;
+
+template <int AR, typename Tin>
+__global__ __launch_bounds__(256) void ttm_kernel(const Tin* __restrict__ in, int64_t A,
+                                                  int64_t In, int64_t B, int K,
+                                                  const double* __restrict__ Q,
+                                                  double* __restrict__ out) {
+  using Acc = typename std::conditional<AR == kF64, double, float>::type;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= A * B) return;
+  const int64_t a = p / B, b = p % B;
+  const Tin* src = in + a * In * B + b;
+  Acc acc[kTtmKMax];
+#pragma unroll
+  for (int k = 0; k < kTtmKMax; ++k) acc[k] = 0;
+  for (int64_t i = 0; i < In; ++i) {
+    const double* q = Q + i * K;
+    if constexpr (AR == kBF16) {
+      const float x = (float)src[i * B];
+      const float xh = bf16_round(x);
+      const float xl = bf16_round(x - xh);
+#pragma unroll
+      for (int k = 0; k < kTtmKMax; ++k) {
+        if (k < K) {
+          const float qf = (float)q[k];
+          const float qh = bf16_round(qf);
+          const float ql = bf16_round(qf - qh);
+          acc[k] += xh * qh + (xh * ql + xl * qh);
+        }
+      }
+    } else {
+      const Acc x = (Acc)src[i * B];
+#pragma unroll
+      for (int k = 0; k < kTtmKMax; ++k)
+        if (k < K) acc[k] += x * (Acc)q[k];
+    }
+  }
+  double* dst = out + a * (int64_t)K * B + b;
+#pragma unroll
+  for (int k = 0; k < kTtmKMax; ++k)
+    if (k < K) dst[(int64_t)k * B] = (double)acc[k];
+}
+
+hipError_t launch_ttm(Arith ar, bool first, const void* in, const ModeView& v, int K,
+                      const double* Q, double* out, hipStream_t s) {
+  if (K > kTtmKMax) return hipErrorInvalidValue;
+  const int64_t n = v.A * v.B;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  prof_begin(first ? "ttm_first" : "ttm", s);
+  if (!first || ar == kF64) {
+    hipLaunchKernelGGL((ttm_kernel<kF64, double>), dim3(blocks), dim3(256), 0, s,
+                       (const double*)in, v.A, v.In, v.B, K, Q, out);
+  } else if (ar == kF32) {
+    hipLaunchKernelGGL((ttm_kernel<kF32, float>), dim3(blocks), dim3(256), 0, s,
+                       (const float*)in, v.A, v.In, v.B, K, Q, out);
+  } else {
+    hipLaunchKernelGGL((ttm_kernel<kBF16, float>), dim3(blocks), dim3(256), 0, s,
+                       (const float*)in, v.A, v.In, v.B, K, Q, out);
+  }
+  prof_end(s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Sum of squares, two stages with a fixed summation order.
+// ---------------------------------------------------------------------------------------
+constexpr int kSsBlocks = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_partial_kernel(const T* __restrict__ x, int64_t n,
+                                                            double* __restrict__ partial) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = (double)x[i];
+    s += v * v;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void sum_final_kernel(const double* __restrict__ partial,
+                                                        int count, double* __restrict__ out) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) s += partial[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+hipError_t launch_sumsq(bool f32, const void* x, int64_t n, double* partial, double* out,
+                        hipStream_t s) {
+  prof_begin("sumsq", s);
+  if (f32)
+    hipLaunchKernelGGL(sumsq_partial_kernel<float>, dim3(kSsBlocks), dim3(256), 0, s,
+                       (const float*)x, n, partial);
+  else
+    hipLaunchKernelGGL(sumsq_partial_kernel<double>, dim3(kSsBlocks), dim3(256), 0, s,
+                       (const double*)x, n, partial);
+  hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(256), 0, s, partial, kSsBlocks, out);
+  prof_end(s);
+  return hipGetLastError();
+}
+
+}  // namespace rtr

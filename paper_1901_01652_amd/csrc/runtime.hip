@@ -1,0 +1,655 @@
+// C ABI of librtr.so (include/rtr.h): argument checks, workspace, launch sequences of
+// Algorithm 1's stages, kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "rtr.h"
+
+struct ProfRec {
+  const char* name;
+  hipEvent_t e0, e1;
+};
+
+struct rtr_context {
+  int device = 0;
+  void* ws = nullptr;
+  size_t ws_cap = 0;
+  unsigned* status = nullptr;  // device status word
+  std::string err;
+  bool prof_on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  const char* pending = nullptr;
+  hipEvent_t pending_e0 = nullptr;
+};
+
+namespace {
+
+thread_local rtr_context* g_ctx = nullptr;
+
+struct Guard {  // makes the handle visible to the launchers' timing hooks
+  explicit Guard(rtr_context* h) { g_ctx = h; }
+  ~Guard() { g_ctx = nullptr; }
+};
+
+rtr_status fail(rtr_context* h, rtr_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+rtr_status hip_fail(rtr_context* h, hipError_t e, const char* what) {
+  return fail(h, RTR_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                      \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(h, e_, what); \
+  } while (0)
+
+hipEvent_t get_event(rtr_context* h) {
+  if (!h->pool.empty()) {
+    hipEvent_t e = h->pool.back();
+    h->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Workspace: one device buffer, carved into 256-byte aligned regions per call.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = (T*)(base ? base + off : nullptr);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+rtr_status ensure_ws(rtr_context* h, size_t bytes) {
+  if (bytes <= h->ws_cap) return RTR_OK;
+  size_t cap = bytes + bytes / 8 + (1 << 20);
+  if (h->ws) {
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    (void)hipFree(h->ws);
+    h->ws = nullptr;
+    h->ws_cap = 0;
+  }
+  hipError_t e = hipMalloc(&h->ws, cap);
+  if (e != hipSuccess) {
+    h->ws = nullptr;
+    (void)hipGetLastError();
+    return fail(h, RTR_ERR_OOM, "workspace allocation of " + std::to_string(cap) + " bytes failed");
+  }
+  h->ws_cap = cap;
+  return RTR_OK;
+}
+
+rtr_status check_handle(rtr_context* h) {
+  if (!h) return RTR_ERR_INVALID_ARG;
+  h->err.clear();
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+  return RTR_OK;
+}
+
+rtr_status check_shape(rtr_context* h, int32_t order, const int64_t* dims, const int32_t* K) {
+  if (order < 1 || order > RTR_MAX_ORDER)
+    return fail(h, RTR_ERR_INVALID_ARG, "order must be in [1, " + std::to_string(RTR_MAX_ORDER) + "]");
+  if (!dims) return fail(h, RTR_ERR_INVALID_ARG, "dims is NULL");
+  for (int n = 0; n < order; ++n)
+    if (dims[n] < 1) return fail(h, RTR_ERR_INVALID_ARG, "dims[" + std::to_string(n) + "] < 1");
+  if (K) {
+    for (int n = 0; n < order; ++n)
+      if (K[n] < 1) return fail(h, RTR_ERR_INVALID_ARG, "K[" + std::to_string(n) + "] < 1");
+  }
+  return RTR_OK;
+}
+
+rtr_status check_arith(rtr_context* h, rtr_dtype x_dtype, rtr_dtype compute, rtr::Arith* ar) {
+  if (x_dtype == RTR_F64 && compute == RTR_F64) {
+    *ar = rtr::kF64;
+    return RTR_OK;
+  }
+  if (x_dtype == RTR_F32 && compute == RTR_F32) {
+    *ar = rtr::kF32;
+    return RTR_OK;
+  }
+  if (x_dtype == RTR_F32 && compute == RTR_BF16) {
+    *ar = rtr::kBF16;
+    return RTR_OK;
+  }
+  return fail(h, RTR_ERR_UNSUPPORTED,
+              "supported (x_dtype, compute): (F64, F64), (F32, F32), (F32, BF16)");
+}
+
+int64_t keff(const int64_t* dims, const int32_t* K, int n) {
+  return K[n] < dims[n] ? (int64_t)K[n] : dims[n];
+}
+
+rtr::ModeView mode_view(const int64_t* dims, int order, int n) {
+  rtr::ModeView v{1, dims[n], 1};
+  for (int m = 0; m < n; ++m) v.A *= dims[m];
+  for (int m = n + 1; m < order; ++m) v.B *= dims[m];
+  return v;
+}
+
+}  // namespace
+
+namespace rtr {
+void prof_begin(const char* name, hipStream_t s) {
+  rtr_context* h = g_ctx;
+  if (!h || !h->prof_on) return;
+  hipEvent_t e = get_event(h);
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  h->pending = name;
+  h->pending_e0 = e;
+}
+void prof_end(hipStream_t s) {
+  rtr_context* h = g_ctx;
+  if (!h || !h->prof_on || !h->pending_e0) return;
+  hipEvent_t e = get_event(h);
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  h->recs.push_back(ProfRec{h->pending, h->pending_e0, e});
+  h->pending = nullptr;
+  h->pending_e0 = nullptr;
+}
+}  // namespace rtr
+
+extern "C" {
+
+rtr_status rtr_create(int device, rtr_handle* out) {
+  if (!out) return RTR_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return RTR_ERR_INVALID_ARG;
+  rtr_context* h = new (std::nothrow) rtr_context();
+  if (!h) return RTR_ERR_OOM;
+  h->device = device;
+  if (hipSetDevice(device) != hipSuccess || hipMalloc(&h->status, sizeof(unsigned)) != hipSuccess ||
+      hipMemset(h->status, 0, sizeof(unsigned)) != hipSuccess) {
+    delete h;
+    return RTR_ERR_DEVICE;
+  }
+  *out = h;
+  return RTR_OK;
+}
+
+rtr_status rtr_destroy(rtr_handle h) {
+  if (!h) return RTR_OK;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  for (auto& r : h->recs) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  for (auto e : h->pool) (void)hipEventDestroy(e);
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->status) (void)hipFree(h->status);
+  delete h;
+  return RTR_OK;
+}
+
+const char* rtr_last_error(rtr_handle h) { return h ? h->err.c_str() : "invalid handle"; }
+
+const char* rtr_status_string(rtr_status s) {
+  switch (s) {
+    case RTR_OK: return "RTR_OK";
+    case RTR_ERR_INVALID_ARG: return "RTR_ERR_INVALID_ARG";
+    case RTR_ERR_UNSUPPORTED: return "RTR_ERR_UNSUPPORTED";
+    case RTR_ERR_OOM: return "RTR_ERR_OOM";
+    case RTR_ERR_DEVICE: return "RTR_ERR_DEVICE";
+    case RTR_ERR_NUMERICAL: return "RTR_ERR_NUMERICAL";
+    case RTR_ERR_INTERNAL: return "RTR_ERR_INTERNAL";
+  }
+  return "unknown";
+}
+
+// ---------------------------------------------------------------------------------------
+rtr_status rtr_sketch(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
+                      const int64_t* dims, const int32_t* K, int32_t power_iters,
+                      uint64_t seed, uint32_t tensor_id, rtr_dtype compute, double* Q,
+                      void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if ((st = check_shape(h, order, dims, K))) return st;
+  if (!K) return fail(h, RTR_ERR_INVALID_ARG, "K is NULL");
+  if (!X || !Q) return fail(h, RTR_ERR_INVALID_ARG, "X and Q must be device pointers");
+  if (power_iters < 0 || power_iters > 64)
+    return fail(h, RTR_ERR_INVALID_ARG, "power_iters must be in [0, 64]");
+  rtr::Arith ar;
+  if ((st = check_arith(h, x_dtype, compute, &ar))) return st;
+  hipStream_t s = (hipStream_t)stream;
+
+  // workspace: partial sums (largest mode), then per mode Ycol and Qwork
+  const size_t pelem = (ar == rtr::kF64) ? sizeof(double) : sizeof(float);
+  size_t pmax = 0;
+  for (int n = 0; n < order; ++n) {
+    const int64_t k = keff(dims, K, n);
+    if (k == dims[n]) continue;
+    if (k > 64)
+      return fail(h, RTR_ERR_UNSUPPORTED, "projection size above 64 (mode " + std::to_string(n) + ")");
+    rtr::ModeView v = mode_view(dims, order, n);
+    size_t need = (size_t)rtr::sketch_chunks(v, (int)k) * v.In * k * pelem;
+    if (power_iters > 0) {
+      if (!rtr::power_supported(ar, v, (int)k))
+        return fail(h, RTR_ERR_UNSUPPORTED,
+                    "power iterations need I_n*K_n <= 8192 (mode " + std::to_string(n) + ")");
+      size_t pw = (size_t)rtr::power_chunks(ar, v, (int)k) * v.In * k * pelem;
+      if (pw > need) need = pw;
+    }
+    if (need > pmax) pmax = need;
+  }
+  Carve plan(nullptr);
+  plan.take<char>(pmax);
+  for (int n = 0; n < order; ++n) {
+    plan.take<double>((size_t)dims[n] * keff(dims, K, n));
+    plan.take<double>((size_t)dims[n] * keff(dims, K, n));
+  }
+  if ((st = ensure_ws(h, plan.off + 256))) return st;
+  Carve cv(h->ws);
+  void* partial = cv.take<char>(pmax);
+  double* Ycol[RTR_MAX_ORDER];
+  double* Qw[RTR_MAX_ORDER];
+  double* Qn[RTR_MAX_ORDER];
+  size_t qoff = 0;
+  for (int n = 0; n < order; ++n) {
+    const int64_t k = keff(dims, K, n);
+    Ycol[n] = cv.take<double>((size_t)dims[n] * k);
+    Qw[n] = cv.take<double>((size_t)dims[n] * k);
+    Qn[n] = Q + qoff;
+    qoff += (size_t)dims[n] * k;
+  }
+
+  rtr::QrJobs jobs{};
+  for (int n = 0; n < order; ++n) {
+    const int64_t k = keff(dims, K, n);
+    if (k == dims[n]) {
+      HIP_TRY(rtr::launch_identity(Qn[n], dims[n], s), "identity");
+      continue;
+    }
+    rtr::ModeView v = mode_view(dims, order, n);
+    const int64_t chunks = rtr::sketch_chunks(v, (int)k);
+    HIP_TRY(rtr::launch_sketch_partial(ar, X, v, (int)k, seed, rtr::omega_stream(n), tensor_id,
+                                       partial, chunks, s),
+            "sketch_partial");
+    HIP_TRY(rtr::launch_reduce_partials(ar, partial, chunks, v.In, (int)k, Ycol[n], s),
+            "reduce_partials");
+    const int j = jobs.count++;
+    jobs.A[j] = Ycol[n];
+    jobs.Qwork[j] = Qw[n];
+    jobs.In[j] = dims[n];
+    jobs.K[j] = (int)k;
+    jobs.Q[j] = Qn[n];
+  }
+  HIP_TRY(rtr::launch_householder_qr(jobs, s), "householder_qr");
+  for (int it = 0; it < power_iters; ++it) {
+    for (int n = 0; n < order; ++n) {
+      const int64_t k = keff(dims, K, n);
+      if (k == dims[n]) continue;
+      rtr::ModeView v = mode_view(dims, order, n);
+      const int64_t chunks = rtr::power_chunks(ar, v, (int)k);
+      HIP_TRY(rtr::launch_power_partial(ar, X, v, (int)k, Qn[n], partial, chunks, s),
+              "power_partial");
+      HIP_TRY(rtr::launch_reduce_partials(ar, partial, chunks, v.In, (int)k, Ycol[n], s),
+              "reduce_partials");
+    }
+    HIP_TRY(rtr::launch_householder_qr(jobs, s), "householder_qr");
+  }
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+// ---------------------------------------------------------------------------------------
+rtr_status rtr_compress(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
+                        const int64_t* dims, const int32_t* K, const double* Q,
+                        rtr_dtype compute, double* P, double* p_norm2, void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if ((st = check_shape(h, order, dims, K))) return st;
+  if (!K) return fail(h, RTR_ERR_INVALID_ARG, "K is NULL");
+  if (!X || !Q || !P) return fail(h, RTR_ERR_INVALID_ARG, "X, Q and P must be device pointers");
+  rtr::Arith ar;
+  if ((st = check_arith(h, x_dtype, compute, &ar))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  for (int n = 0; n < order; ++n)
+    if (keff(dims, K, n) > 64)
+      return fail(h, RTR_ERR_UNSUPPORTED, "projection size above 64 (mode " + std::to_string(n) + ")");
+  // intermediate sizes
+  int64_t cur[RTR_MAX_ORDER];
+  for (int n = 0; n < order; ++n) cur[n] = dims[n];
+  size_t maxmid = 1;
+  for (int n = 0; n < order - 1; ++n) {
+    cur[n] = keff(dims, K, n);
+    size_t sz = 1;
+    for (int m = 0; m < order; ++m) sz *= (size_t)cur[m];
+    if (sz > maxmid) maxmid = sz;
+  }
+  Carve plan(nullptr);
+  plan.take<double>(maxmid);
+  plan.take<double>(maxmid);
+  plan.take<double>(1024);
+  if ((st = ensure_ws(h, plan.off + 256))) return st;
+  Carve cv(h->ws);
+  double* buf[2] = {cv.take<double>(maxmid), cv.take<double>(maxmid)};
+  double* red = cv.take<double>(1024);
+
+  for (int n = 0; n < order; ++n) cur[n] = dims[n];
+  const void* in = X;
+  size_t qoff = 0;
+  for (int n = 0; n < order; ++n) {
+    const int64_t k = keff(dims, K, n);
+    rtr::ModeView v = mode_view(cur, order, n);
+    double* out = (n == order - 1) ? P : buf[n & 1];
+    HIP_TRY(rtr::launch_ttm(ar, n == 0, in, v, (int)k, Q + qoff, out, s), "ttm");
+    qoff += (size_t)dims[n] * k;
+    cur[n] = k;
+    in = out;
+  }
+  if (p_norm2) {
+    size_t np = 1;
+    for (int n = 0; n < order; ++n) np *= (size_t)cur[n];
+    HIP_TRY(rtr::launch_sumsq(false, P, (int64_t)np, red, p_norm2, s), "sumsq");
+  }
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+// ---------------------------------------------------------------------------------------
+rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int32_t* Kp,
+                         const int32_t* R, const rtr_decompose_opts* opts,
+                         const double* Z_init, double* Z, double* err_trace,
+                         int32_t* sweeps_run, void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if (!opts) return fail(h, RTR_ERR_INVALID_ARG, "opts is NULL");
+  if (opts->method == RTR_METHOD_SVD)
+    return fail(h, RTR_ERR_UNSUPPORTED, "TR-SVD is not available through rtr_decompose yet");
+  if (opts->method != RTR_METHOD_ALS) return fail(h, RTR_ERR_INVALID_ARG, "unknown method");
+  if (order < 2 || order > RTR_MAX_ORDER)
+    return fail(h, RTR_ERR_INVALID_ARG, "decomposition needs 2 <= order <= 8");
+  if (!Kp || !R) return fail(h, RTR_ERR_INVALID_ARG, "Kp and R must be host arrays");
+  if (!P || !Z_init || !Z || !err_trace || !sweeps_run)
+    return fail(h, RTR_ERR_INVALID_ARG, "P, Z_init, Z, err_trace, sweeps_run must be device pointers");
+  if (opts->max_sweeps < 1) return fail(h, RTR_ERR_INVALID_ARG, "max_sweeps must be >= 1");
+  if (!(opts->tol >= 0.0)) return fail(h, RTR_ERR_INVALID_ARG, "tol must be >= 0");
+  int64_t total = 1;
+  for (int n = 0; n < order; ++n) {
+    if (Kp[n] < 1) return fail(h, RTR_ERR_INVALID_ARG, "Kp entries must be >= 1");
+    if (R[n] < 1 || R[n] > RTR_MAX_RANK)
+      return fail(h, RTR_ERR_INVALID_ARG, "ranks must be in [1, " + std::to_string(RTR_MAX_RANK) + "]");
+    total *= Kp[n];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  size_t zoff[RTR_MAX_ORDER + 1];
+  zoff[0] = 0;
+  int64_t Jmax = 0;
+  int RRmax = 0, noutmax = 0;
+  int64_t chunkmax = 1;
+  rtr::AlsGeom geo[RTR_MAX_ORDER];
+  int64_t strideP[RTR_MAX_ORDER];
+  strideP[order - 1] = 1;
+  for (int n = order - 2; n >= 0; --n) strideP[n] = strideP[n + 1] * Kp[n + 1];
+  for (int n = 0; n < order; ++n) {
+    const int Ra = R[n], Rb = R[(n + 1) % order];
+    zoff[n + 1] = zoff[n] + (size_t)Ra * Kp[n] * Rb;
+    rtr::AlsGeom g{};
+    g.N = order;
+    g.n = n;
+    g.Kn = Kp[n];
+    g.Ra = Ra;
+    g.Rb = Rb;
+    g.RR = Ra * Rb;
+    g.J = total / Kp[n];
+    for (int t = 1; t < order; ++t) {
+      const int m = (n + t) % order;
+      g.cycK[t - 1] = Kp[m];
+      g.cycStride[t - 1] = strideP[m];
+    }
+    g.strideN = strideP[n];
+    if ((int64_t)g.RR > g.J)
+      return fail(h, RTR_ERR_INVALID_ARG,
+                  "R_n R_{n+1} exceeds the number of equations for core " + std::to_string(n));
+    if (!rtr::als_supported(g.Kn, g.RR))
+      return fail(h, RTR_ERR_UNSUPPORTED, "K'_n R_n R_{n+1} + (R_n R_{n+1})^2 above 16384");
+    geo[n] = g;
+    Jmax = std::max(Jmax, g.J);
+    RRmax = std::max(RRmax, g.RR);
+    noutmax = std::max(noutmax, g.Kn * g.RR + g.RR * g.RR);
+    chunkmax = std::max(chunkmax, rtr::als_chunks(g));
+  }
+  Carve plan(nullptr);
+  plan.take<double>((size_t)Jmax * RRmax);
+  plan.take<double>((size_t)chunkmax * noutmax);
+  plan.take<double>(noutmax);
+  plan.take<double>(chunkmax);
+  plan.take<double>(1024);
+  plan.take<double>(1);
+  plan.take<int>(1);
+  if ((st = ensure_ws(h, plan.off + 256))) return st;
+  Carve cv(h->ws);
+  double* Bm = cv.take<double>((size_t)Jmax * RRmax);
+  double* part = cv.take<double>((size_t)chunkmax * noutmax);
+  double* MG = cv.take<double>(noutmax);
+  double* rpart = cv.take<double>(chunkmax);
+  double* red = cv.take<double>(1024);
+  double* pn2 = cv.take<double>(1);
+  int* done = cv.take<int>(1);
+
+  if (Z != Z_init)
+    HIP_TRY(hipMemcpyAsync(Z, Z_init, zoff[order] * sizeof(double), hipMemcpyDeviceToDevice, s),
+            "hipMemcpyAsync");
+  HIP_TRY(rtr::launch_sumsq(false, P, total, red, pn2, s), "sumsq");
+  HIP_TRY(rtr::launch_als_begin(done, sweeps_run, s), "als_begin");
+  for (int sw = 0; sw < opts->max_sweeps; ++sw) {
+    for (int n = 0; n < order; ++n) {
+      const rtr::AlsGeom& g = geo[n];
+      rtr::Chain ch{};
+      ch.L = order - 1;
+      for (int t = 1; t < order; ++t) {
+        const int m = (n + t) % order;
+        ch.core[t - 1] = Z + zoff[m];
+        ch.I[t - 1] = Kp[m];
+        ch.Ra[t - 1] = R[m];
+        ch.Rb[t - 1] = R[(m + 1) % order];
+      }
+      HIP_TRY(rtr::launch_chain(ch, g.J, 1, Bm, done, s), "chain");
+      const int64_t chunks = rtr::als_chunks(g);
+      const int nout = g.Kn * g.RR + g.RR * g.RR;
+      HIP_TRY(rtr::launch_als_partial(P, g, Bm, part, chunks, done, s), "als_partial");
+      HIP_TRY(rtr::launch_als_reduce(part, chunks, nout, MG, done, s), "als_reduce");
+      HIP_TRY(rtr::launch_als_solve(MG, g, Z + zoff[n], h->status, done, s), "als_solve");
+      if (n == order - 1) {
+        HIP_TRY(rtr::launch_als_resid(P, g, Bm, Z + zoff[n], rpart, chunks, done, s), "als_resid");
+        HIP_TRY(rtr::launch_als_err(rpart, chunks, pn2, sw, opts->tol, err_trace, sweeps_run, done, s),
+                "als_err");
+      }
+    }
+  }
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+// ---------------------------------------------------------------------------------------
+rtr_status rtr_backproject(rtr_handle h, int32_t order, const int64_t* dims, const int32_t* K,
+                           const int32_t* R, const double* Z, const double* Q, double* G,
+                           void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if ((st = check_shape(h, order, dims, K))) return st;
+  if (!K || !R) return fail(h, RTR_ERR_INVALID_ARG, "K and R must be host arrays");
+  if (!Z || !Q || !G) return fail(h, RTR_ERR_INVALID_ARG, "Z, Q and G must be device pointers");
+  for (int n = 0; n < order; ++n)
+    if (R[n] < 1 || R[n] > RTR_MAX_RANK) return fail(h, RTR_ERR_INVALID_ARG, "rank out of range");
+  hipStream_t s = (hipStream_t)stream;
+  size_t zo = 0, qo = 0, go = 0;
+  for (int n = 0; n < order; ++n) {
+    const int Ra = R[n], Rb = R[(n + 1) % order];
+    const int64_t k = keff(dims, K, n);
+    HIP_TRY(rtr::launch_backproject(Z + zo, Q + qo, Ra, (int)k, dims[n], Rb, G + go, s),
+            "backproject");
+    zo += (size_t)Ra * k * Rb;
+    qo += (size_t)dims[n] * k;
+    go += (size_t)Ra * dims[n] * Rb;
+  }
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+// ---------------------------------------------------------------------------------------
+rtr_status rtr_residual(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
+                        const int64_t* dims, const int32_t* R, const double* G, double* out,
+                        void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if ((st = check_shape(h, order, dims, nullptr))) return st;
+  if (order < 2) return fail(h, RTR_ERR_INVALID_ARG, "residual needs order >= 2");
+  if (!R) return fail(h, RTR_ERR_INVALID_ARG, "R is NULL");
+  if (!X || !G || !out) return fail(h, RTR_ERR_INVALID_ARG, "X, G and out must be device pointers");
+  if (x_dtype != RTR_F64 && x_dtype != RTR_F32)
+    return fail(h, RTR_ERR_UNSUPPORTED, "X must be FP64 or FP32");
+  for (int n = 0; n < order; ++n)
+    if (R[n] < 1 || R[n] > RTR_MAX_RANK) return fail(h, RTR_ERR_INVALID_ARG, "rank out of range");
+  hipStream_t s = (hipStream_t)stream;
+  const int hm = order / 2;
+  int64_t IL = 1, IR = 1;
+  for (int n = 0; n < hm; ++n) IL *= dims[n];
+  for (int n = hm; n < order; ++n) IR *= dims[n];
+  const int RR = R[0] * R[hm];
+  const int64_t ir_tiles = (IR + 255) / 256;
+  Carve plan(nullptr);
+  plan.take<double>((size_t)IL * RR);
+  plan.take<double>((size_t)IR * RR);
+  plan.take<double>((size_t)2 * (2048 + ir_tiles));
+  if ((st = ensure_ws(h, plan.off + 256))) return st;
+  Carve cv(h->ws);
+  double* L = cv.take<double>((size_t)IL * RR);
+  double* RtT = cv.take<double>((size_t)IR * RR);
+  double* partial = cv.take<double>((size_t)2 * (2048 + ir_tiles));
+  size_t goff[RTR_MAX_ORDER];
+  size_t go = 0;
+  for (int n = 0; n < order; ++n) {
+    goff[n] = go;
+    go += (size_t)R[n] * dims[n] * R[(n + 1) % order];
+  }
+  rtr::Chain cl{}, cr{};
+  cl.L = hm;
+  for (int n = 0; n < hm; ++n) {
+    cl.core[n] = G + goff[n];
+    cl.I[n] = (int)dims[n];
+    cl.Ra[n] = R[n];
+    cl.Rb[n] = R[(n + 1) % order];
+  }
+  cr.L = order - hm;
+  for (int n = hm; n < order; ++n) {
+    cr.core[n - hm] = G + goff[n];
+    cr.I[n - hm] = (int)dims[n];
+    cr.Ra[n - hm] = R[n];
+    cr.Rb[n - hm] = R[(n + 1) % order];
+  }
+  HIP_TRY(rtr::launch_chain(cl, IL, 0, L, nullptr, s), "chain");
+  HIP_TRY(rtr::launch_chain(cr, IR, 1, RtT, nullptr, s), "chain");
+  HIP_TRY(rtr::launch_residual(x_dtype == RTR_F32, X, IL, IR, RR, L, RtT, partial, out, s),
+          "residual");
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+// ---------------------------------------------------------------------------------------
+rtr_status rtr_normals(rtr_handle h, uint64_t seed, uint32_t stream_word, uint32_t tensor_id,
+                       int64_t start, int64_t count, rtr_dtype dtype, void* out,
+                       void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if (start < 0 || count < 0) return fail(h, RTR_ERR_INVALID_ARG, "start and count must be >= 0");
+  if (count > 0 && !out) return fail(h, RTR_ERR_INVALID_ARG, "out must be a device pointer");
+  if (dtype != RTR_F64 && dtype != RTR_F32)
+    return fail(h, RTR_ERR_UNSUPPORTED, "normals are FP64 or FP32");
+  HIP_TRY(rtr::launch_normals(dtype == RTR_F32, seed, stream_word, tensor_id, start, count, out,
+                              (hipStream_t)stream),
+          "normals");
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+// ---------------------------------------------------------------------------------------
+rtr_status rtr_status_sync(rtr_handle h, void* stream, uint32_t* bits) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  unsigned v = 0;
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+  HIP_TRY(hipMemcpy(&v, h->status, sizeof(unsigned), hipMemcpyDeviceToHost), "hipMemcpy");
+  HIP_TRY(hipMemset(h->status, 0, sizeof(unsigned)), "hipMemset");
+  if (bits) *bits = v;
+  return v ? fail(h, RTR_ERR_NUMERICAL, "device status bits set") : RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+rtr_status rtr_profile_enable(rtr_handle h, int32_t on) {
+  if (!h) return RTR_ERR_INVALID_ARG;
+  h->prof_on = on != 0;
+  return RTR_OK;
+}
+
+rtr_status rtr_profile_reset(rtr_handle h) {
+  if (!h) return RTR_ERR_INVALID_ARG;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  for (auto& r : h->recs) {
+    h->pool.push_back(r.e0);
+    h->pool.push_back(r.e1);
+  }
+  h->recs.clear();
+  return RTR_OK;
+}
+
+rtr_status rtr_profile_read(rtr_handle h, const char* name, double* total_ms, int64_t* launches) try {
+  if (!h || !name) return RTR_ERR_INVALID_ARG;
+  HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (auto& r : h->recs) {
+    if (std::strcmp(r.name, name) != 0) continue;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.e0, r.e1), "hipEventElapsedTime");
+    tot += ms;
+    ++cnt;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = cnt;
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+}  // extern "C"

@@ -1,0 +1,265 @@
+"""GPU parity of every stage of Alg. 1 against the FP64 oracle, through the C ABI.
+
+Tolerances (relative Frobenius differences): FP64 path 1e-10, FP32 path 1e-5, BF16 sketch
+path 3e-3.  Q_n is compared directly where Y_n has full column rank (the R_ii >= 0 QR is
+then unique); otherwise the projector Q Q^T is compared.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1901_01652_amd as rt
+from paper_1901_01652_amd import pipeline
+from oracle import philox as oph, rtr as orc, tensor as ot
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def h():
+    hd = rt.Handle(0)
+    yield hd
+    hd.close()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rand_tensor(dims, seed):
+    return np.random.default_rng(seed).standard_normal(dims)
+
+
+def gpu_q(h, X, K, q=0, seed=0, compute=None, tensor_id=0):
+    Xd = torch.as_tensor(X).to(DEV)
+    Q = rt.rtr_sketch(h, Xd, K, q, seed, tensor_id, compute)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in rt.unpack(Q, rt.q_shapes(X.shape, K))], Q, Xd
+
+
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("start,count", [(0, 1000), (3, 37), (1 << 33, 64), (5, 1)])
+def test_normals_match_oracle(h, start, count):
+    say("normals", start, count)
+    sw = oph.stream_word(oph.TAG_OMEGA, 2)
+    ref = oph.normals(12345, sw, 7, start, count)
+    g64 = rt.rtr_normals(h, 12345, sw, 7, start, count, "f64").cpu().numpy()
+    g32 = rt.rtr_normals(h, 12345, sw, 7, start, count, "f32").cpu().numpy()
+    # FP64 Box-Muller: a few ulp (libm and ocml round log/sin/cos independently)
+    assert np.max(np.abs(g64 - ref) / np.maximum(np.abs(ref), 1e-300)) < 1e-14 or \
+        np.max(np.abs(g64 - ref)) < 4 * np.finfo(np.float64).eps * np.max(np.abs(ref))
+    # FP32 transcendental unit: small absolute error
+    assert np.max(np.abs(g32 - ref)) < 2e-5
+
+
+@pytest.mark.parametrize("dims,K,q", [
+    ((20, 20, 20, 20), (8, 8, 8, 8), 0),
+    ((37, 23, 41), (5, 7, 3), 0),
+    ((6, 7, 5, 4, 3), (3, 3, 2, 2, 2), 0),
+    ((70, 9, 33), (64, 1, 33), 0),          # K = I for the last mode, K = 1, K = 64
+    ((30, 20, 25), (6, 5, 4), 1),
+    ((30, 20, 25), (6, 5, 4), 2),
+    ((150, 70), (12, 10), 1),
+])
+def test_sketch_fp64(h, dims, K, q):
+    say("sketch f64", dims, K, q)
+    X = rand_tensor(dims, 1)
+    Qg, _, _ = gpu_q(h, X, K, q, seed=99)
+    for n in range(len(dims)):
+        Qo = orc.range_basis(X, n, K[n], q, seed=99)
+        assert rel(Qg[n], Qo) < 1e-10, (n, rel(Qg[n], Qo))
+        assert np.max(np.abs(Qg[n].T @ Qg[n] - np.eye(Qg[n].shape[1]))) < 1e-13
+
+
+@pytest.mark.parametrize("compute,tol", [("f32", 1e-5), ("bf16", 3e-3)])
+def test_sketch_low_precision_projector(h, compute, tol):
+    dims, K = (40, 30, 20, 10), (8, 7, 6, 5)
+    say("sketch", compute, dims, K)
+    X = rand_tensor(dims, 2).astype(np.float32)
+    Qg, _, _ = gpu_q(h, X, K, 0, seed=5, compute=compute)
+    X64 = X.astype(np.float64)
+    for n in range(4):
+        Qo = orc.range_basis(X64, n, K[n], 0, seed=5)
+        assert rel(Qg[n] @ Qg[n].T, Qo @ Qo.T) < tol * 10
+        assert rel(Qg[n], Qo) < tol * 30
+
+
+@pytest.mark.parametrize("dims,K", [((20, 20, 20, 20), (8, 8, 8, 8)), ((37, 23, 41), (5, 7, 41)),
+                                    ((6, 7, 5, 4, 3), (3, 3, 2, 2, 2)), ((9, 11), (4, 11))])
+def test_compress_fp64(h, dims, K):
+    say("compress f64", dims, K)
+    X = rand_tensor(dims, 3)
+    Qg, Qd, Xd = gpu_q(h, X, K, 0, seed=4)
+    pn2 = torch.zeros(1, dtype=torch.float64, device=DEV)
+    P = rt.rtr_compress(h, Xd, K, Qd, p_norm2=pn2).cpu().numpy()
+    Po = orc.compress(X, Qg)
+    assert rel(P, Po) < 1e-12
+    assert abs(pn2.item() - np.sum(Po ** 2)) < 1e-12 * np.sum(Po ** 2)
+
+
+@pytest.mark.parametrize("compute,tol", [("f32", 1e-5), ("bf16", 3e-3)])
+def test_compress_low_precision(h, compute, tol):
+    dims, K = (33, 20, 17, 12), (8, 7, 6, 5)
+    say("compress", compute, dims, K)
+    X = rand_tensor(dims, 6).astype(np.float32)
+    Qo = [orc.range_basis(X.astype(np.float64), n, K[n], 0, seed=3) for n in range(4)]
+    Qd = rt.pack(Qo, DEV)
+    P = rt.rtr_compress(h, torch.as_tensor(X).to(DEV), K, Qd, compute).cpu().numpy()
+    Po = orc.compress(X.astype(np.float64), Qo)
+    assert rel(P, Po) < tol / 10 if compute == "bf16" else rel(P, Po) < tol
+
+
+def als_case(dims, R, seed, noise=0.05):
+    G = W.tr_cores(seed, dims, [max(2, r) for r in R])
+    P = ot.tr_full(G) + noise * np.random.default_rng(seed).standard_normal(dims) * np.std(ot.tr_full(G))
+    Z0 = W.init_cores(seed + 1, dims, R)
+    return P, Z0
+
+
+@pytest.mark.parametrize("dims,R,sweeps", [((8, 8, 8, 8), (3, 3, 3, 3), 10),
+                                           ((9, 7, 8), (2, 3, 4), 15),
+                                           ((6, 5, 7, 4, 5), (2, 2, 3, 2, 2), 6),
+                                           ((20, 15), (2, 3), 10),
+                                           ((12, 10, 11), (1, 1, 1), 5)])
+def test_als_fp64(h, dims, R, sweeps):
+    say("als f64", dims, R)
+    P, Z0 = als_case(dims, R, 11)
+    Zo, tro = orc.tr_als(P, Z0, sweeps)
+    Z, tr, ns = rt.rtr_decompose(h, torch.as_tensor(P).to(DEV), R, rt.pack(Z0, DEV), sweeps)
+    assert rt.rtr_status_sync(h) == 0
+    assert int(ns.item()) == sweeps
+    Zg = [z.cpu().numpy() for z in rt.unpack(Z, rt.core_shapes(dims, R))]
+    assert rel(tr.cpu().numpy(), tro) < 1e-10
+    assert rel(ot.tr_full(Zg), ot.tr_full(Zo)) < 1e-10
+
+
+def test_als_tolerance_stop(h):
+    dims, R = (7, 6, 8), (2, 2, 2)
+    say("als tol", dims, R)
+    P, Z0 = als_case(dims, R, 13, noise=0.3)
+    Zo, tro = orc.tr_als(P, Z0, 60, tol=1e-4)
+    Z, tr, ns = rt.rtr_decompose(h, torch.as_tensor(P).to(DEV), R, rt.pack(Z0, DEV), 60, tol=1e-4)
+    n = int(ns.item())
+    assert n == len(tro) and n < 60
+    assert rel(tr.cpu().numpy()[:n], tro) < 1e-10
+
+
+def test_backproject_and_residual(h):
+    dims, K, R = (13, 11, 9, 10), (5, 4, 3, 6), (2, 3, 2, 3)
+    say("backproject/residual", dims, K, R)
+    rng = np.random.default_rng(7)
+    Qs = [np.linalg.qr(rng.standard_normal((d, k)))[0] for d, k in zip(dims, K)]
+    Z = W.tr_cores(9, K, R)
+    G = rt.rtr_backproject(h, dims, K, R, rt.pack(Z, DEV), rt.pack(Qs, DEV))
+    Gg = [g.cpu().numpy() for g in rt.unpack(G, rt.core_shapes(dims, R))]
+    Go = orc.backproject(Z, Qs)
+    for a, b in zip(Gg, Go):
+        assert rel(a, b) < 1e-13
+    X = ot.tr_full(Go) + 0.1 * rng.standard_normal(dims)
+    for dt in (torch.float64, torch.float32):
+        Xd = torch.as_tensor(X).to(dt).to(DEV)
+        out = rt.rtr_residual(h, Xd, R, G).cpu().numpy()
+        Xh = Xd.double().cpu().numpy()
+        assert abs(out[1] - np.sum(Xh ** 2)) < 1e-12 * np.sum(Xh ** 2)
+        r2 = ot.frob(Xh - ot.tr_full(Go)) ** 2
+        assert abs(out[0] - r2) < 1e-10 * r2
+
+
+def run_end_to_end(h, w, X, compute=None):
+    Z0 = W.make_init(w)
+    Xd = torch.as_tensor(X).to(DEV)
+    out = pipeline.rtr_als(h, Xd, w.K, w.ranks, Z0, w.sweeps, w.q, w.seed, compute=compute, tol=w.tol)
+    torch.cuda.synchronize()
+    G = [g.cpu().numpy() for g in rt.unpack(out["G"], rt.core_shapes(w.dims, w.ranks))]
+    return out, G, pipeline.rse(h, Xd, w.ranks, out["G"]), Z0
+
+
+def test_end_to_end_small_fp64(h):
+    """The 20^4 FP64 workload (rank 3, 40 dB, K=8, 20 sweeps) against the oracle."""
+    w = W.small_fp64()
+    say("end-to-end", w.name)
+    X, _ = W.make_tensor(w)
+    X = X.numpy()
+    out, G, rse_g, Z0 = run_end_to_end(h, w, X)
+    ref = orc.rtr_als(X, w.K, Z0, w.sweeps, q=w.q, seed=w.seed)
+    Q = [t.cpu().numpy() for t in rt.unpack(out["Q"], rt.q_shapes(w.dims, w.K))]
+    for n in range(4):
+        assert rel(Q[n], ref["Q"][n]) < 1e-10
+    assert rel(out["P"].cpu().numpy(), ref["P"]) < 1e-10
+    assert rel(out["err_trace"].cpu().numpy(), ref["rse_trace"]) < 1e-10
+    assert rel(ot.tr_full(G), ot.tr_full(ref["G"])) < 1e-10
+    assert abs(rse_g - ref["rse"]) / ref["rse"] < 1e-10
+    # Pythagorean identity on the device quantities
+    pn2 = out["p_norm2"].item()
+    e = out["err_trace"].cpu().numpy()[-1]
+    xn2 = float(np.sum(X ** 2))
+    rse_py = np.sqrt((xn2 - pn2 + e * e * pn2) / xn2)
+    assert abs(rse_py - rse_g) / rse_g < 1e-9
+
+
+@pytest.mark.parametrize("compute,tol", [("f32", 1e-5), ("bf16", 3e-3)])
+def test_end_to_end_small_low_precision(h, compute, tol):
+    w = W.small_fp64()
+    say("end-to-end", w.name, compute)
+    X, _ = W.make_tensor(w, dtype=torch.float32)
+    X = X.numpy()
+    out, G, rse_g, Z0 = run_end_to_end(h, w, X, compute)
+    ref = orc.rtr_als(X.astype(np.float64), w.K, Z0, w.sweeps, q=w.q, seed=w.seed)
+    assert abs(rse_g - ref["rse"]) / ref["rse"] < tol
+    assert rel(ot.tr_full(G), ot.tr_full(ref["G"])) < tol * (30 if compute == "bf16" else 10)
+
+
+def test_determinism(h):
+    w = W.Workload("det", [17, 13, 11, 9], [2, 2, 2, 2], [5, 4, 4, 3], 1, 5, 30.0, 3)
+    say("determinism", w.name)
+    X, _ = W.make_tensor(w, dtype=torch.float32)
+    outs = []
+    for _ in range(2):
+        out, G, rse_g, _ = run_end_to_end(h, w, X.numpy(), "f32")
+        outs.append((out["Q"].cpu(), out["P"].cpu(), out["G"].cpu(), rse_g))
+    for a, b in zip(outs[0][:3], outs[1][:3]):
+        assert torch.equal(a, b)
+    assert outs[0][3] == outs[1][3]
+
+
+def test_invalid_arguments(h):
+    say("invalid args")
+    X = torch.zeros((4, 5, 6), dtype=torch.float64, device=DEV)
+    with pytest.raises(rt.RtrError) as e:
+        rt.rtr_sketch(h, X, [0, 2, 2])
+    assert e.value.code == 1
+    with pytest.raises(rt.RtrError) as e:
+        rt.rtr_sketch(h, X, [2, 2, 2], compute="bf16")
+    assert e.value.code == 2
+    with pytest.raises(rt.RtrError) as e:
+        rt.rtr_sketch(h, X, [2, 2, 100])       # K'=I: fine; K>64 on a projected mode is not
+        rt.rtr_sketch(h, torch.zeros((4, 5, 100), dtype=torch.float64, device=DEV), [2, 2, 80])
+    assert e.value.code == 2
+    P = torch.zeros((3, 3, 3), dtype=torch.float64, device=DEV)
+    Z0 = torch.zeros(3 * 3 * 5 * 5, dtype=torch.float64, device=DEV)
+    with pytest.raises(rt.RtrError) as e:
+        rt.rtr_decompose(h, P, [5, 5, 5], Z0, 2)  # R_n R_{n+1} = 25 > 9 equations
+    assert e.value.code == 1
+    with pytest.raises(rt.RtrError) as e:
+        rt.rtr_decompose(h, P, [1, 1, 1], Z0, 2, method="svd")
+    assert e.value.code == 2
+
+
+def test_cholesky_failure_flag(h):
+    """A zero core makes the subchain of the first update vanish, so its Gram matrix is
+    exactly zero: the status bit is set, the update skipped, and no kernel faults."""
+    dims, R = (5, 6, 7), (2, 2, 2)
+    say("cholesky flag")
+    P = torch.as_tensor(rand_tensor(dims, 8)).to(DEV)
+    Z0 = [np.ones((2, 5, 2)), np.zeros((2, 6, 2)), np.ones((2, 7, 2))]
+    rt.rtr_decompose(h, P, R, rt.pack(Z0, DEV), 1)
+    assert rt.rtr_status_sync(h) & rt.RTR_STATUS_CHOLESKY_FAILED
+    assert rt.rtr_status_sync(h) == 0
