@@ -193,10 +193,12 @@ rtr_status rtr_normals(rtr_handle h, uint64_t seed, uint32_t stream_word, uint32
 rtr_status rtr_status_sync(rtr_handle h, void* stream, uint32_t* bits);
 
 /*
- * Kernel timing with HIP events on the launch stream (off by default).  While enabled,
- * every kernel launch is bracketed by two events.  rtr_profile_read synchronises the
- * device and returns the summed duration (ms) and launch count of kernel ``name``;
- * rtr_profile_reset drops all records.
+ * Kernel timing with HIP events on the launch stream (off by default).  rtr_profile_enable
+ * level 1 brackets each launch of the kernels that stream the large tensor X (sketch,
+ * power step, first compression pass, residual) with two events, level 2 every kernel,
+ * level 0 turns timing off.  rtr_profile_read synchronises the device and returns the
+ * summed duration (ms) and launch count of kernel ``name``; rtr_profile_reset drops all
+ * records.
  */
 rtr_status rtr_profile_enable(rtr_handle h, int32_t on);
 rtr_status rtr_profile_reset(rtr_handle h);

@@ -260,8 +260,9 @@ def rtr_status_sync(h, stream=None, device=0):
     return int(bits.value)
 
 
-def rtr_profile_enable(h, on=True):
-    h.check(lib.rtr_profile_enable(h.ptr, 1 if on else 0))
+def rtr_profile_enable(h, level=1):
+    """0 off, 1 kernels that stream X, 2 every kernel."""
+    h.check(lib.rtr_profile_enable(h.ptr, int(level)))
 
 
 def rtr_profile_reset(h):

@@ -23,7 +23,7 @@ struct rtr_context {
   size_t ws_cap = 0;
   unsigned* status = nullptr;  // device status word
   std::string err;
-  bool prof_on = false;
+  int prof_level = 0;  // 0 off, 1 kernels that stream the large tensor, 2 every kernel
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   const char* pending = nullptr;
@@ -150,9 +150,19 @@ rtr::ModeView mode_view(const int64_t* dims, int order, int n) {
 }  // namespace
 
 namespace rtr {
+static bool streams_x(const char* name) {
+  static const char* const kNames[] = {"sketch_partial", "power_partial", "ttm_first",
+                                       "residual", "sketch_fused", "power_fused",
+                                       "compress_fused"};
+  for (const char* k : kNames)
+    if (std::strcmp(k, name) == 0) return true;
+  return false;
+}
+
 void prof_begin(const char* name, hipStream_t s) {
   rtr_context* h = g_ctx;
-  if (!h || !h->prof_on) return;
+  if (!h || h->prof_level == 0) return;
+  if (h->prof_level == 1 && !streams_x(name)) return;
   hipEvent_t e = get_event(h);
   if (!e) return;
   (void)hipEventRecord(e, s);
@@ -161,7 +171,7 @@ void prof_begin(const char* name, hipStream_t s) {
 }
 void prof_end(hipStream_t s) {
   rtr_context* h = g_ctx;
-  if (!h || !h->prof_on || !h->pending_e0) return;
+  if (!h || h->prof_level == 0 || !h->pending_e0) return;
   hipEvent_t e = get_event(h);
   if (!e) return;
   (void)hipEventRecord(e, s);
@@ -616,7 +626,8 @@ rtr_status rtr_status_sync(rtr_handle h, void* stream, uint32_t* bits) try {
 
 rtr_status rtr_profile_enable(rtr_handle h, int32_t on) {
   if (!h) return RTR_ERR_INVALID_ARG;
-  h->prof_on = on != 0;
+  if (on < 0 || on > 2) return RTR_ERR_INVALID_ARG;
+  h->prof_level = on;
   return RTR_OK;
 }
 
