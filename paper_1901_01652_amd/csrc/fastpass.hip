@@ -1,0 +1,355 @@
+// Persistent matrix-core passes over X for one mode n (FP32 input):
+//   sketch  Y_n  += T M      (Alg. 1 steps 4-5; M drawn on the fly, never stored)
+//   power   Y'_n += T (T^T Q_n)   (one round of subspace iteration, fiber form)
+// where T is a tile of 64 consecutive columns of X_(n) with all I_n rows.
+//
+// Tiles: column j of X_(n) is (a, b) with j = a*B + b for X viewed as A x I_n x B, so a
+// tile of consecutive j is one or more contiguous runs of each row.  Three loaders:
+//   cols4   B % 4 == 0: 16-byte loads along b (covers runs that cross an a boundary)
+//   last4   B == 1 (mode N) and I_n % 4 == 0: 16-byte loads along the fiber itself
+//   scalar  anything else.
+// The tile is staged through registers (the next tile's loads are in flight while the
+// matrix cores work on the current one) into LDS as bf16 (BF16 path, round to nearest
+// even) or FP32.  Each work-group keeps its share of Y in accumulators across all its
+// tiles and writes one partial at the end; reduce_partials sums them in a fixed order.
+//
+// LDS (BF16 path, I_n = 200, K = 20): T [I_n][64+8], M^T or W^T [K][64+8], and for the
+// power step T^T [64][I_n+pad] and Q^T [K][I_n+pad].  The contraction index of every
+// operand is contiguous, so each lane reads its 8 bf16 with one 16-byte LDS access.
+#include "common.hpp"
+#include "launch.hpp"
+#include "mfma.hpp"
+
+namespace rtr {
+
+constexpr int kFpTJ = 64;
+constexpr int kFpThreads = 512;   // 8 wavefronts
+constexpr int kFpMaxIn = 256;
+constexpr int kFpMaxK = 64;
+
+struct PassArgs {
+  const float* X;
+  int64_t A, In, B, J;
+  int K;
+  uint64_t seed;
+  uint32_t stream, tid;
+  const double* Q;  // power step: In x K row-major
+  int64_t ntiles;
+  float* partial;   // [gridDim.x][In][K]
+  int loader;       // 0 cols4, 1 last4, 2 scalar
+  int ldT, ldI, kI; // LDS leading dimensions, padded contraction length over i
+};
+
+template <bool BF>
+struct PassLds {
+  using T = typename Mma<BF>::T;
+  static __host__ __device__ int mt_pad(int64_t In) { return (int)((In + 15) / 16) * 16; }
+  static __host__ __device__ int kt_pad(int K) { return ((K + 15) / 16) * 16; }
+};
+
+// Layout of the dynamic LDS block (element offsets in T units, 16-byte aligned).
+template <bool BF, int OP>
+struct PassLayout {
+  using T = typename Mma<BF>::T;
+  int oTij, oOt, oTji, oQt, total;
+  __host__ __device__ PassLayout(int64_t In, int K, int ldT, int ldI) {
+    const int a = 16 / (int)sizeof(T);
+    auto up = [a](int v) { return (v + a - 1) / a * a; };
+    const int MTp = (int)((In + 15) / 16) * 16, KTp = ((K + 15) / 16) * 16;
+    oTij = 0;
+    oOt = up(oTij + MTp * ldT);
+    oTji = up(oOt + KTp * ldT);
+    oQt = up(oTji + (OP == 1 ? kFpTJ * ldI : 0));
+    total = up(oQt + (OP == 1 ? KTp * ldI : 0));
+  }
+};
+
+template <bool BF, int OP, int LD>
+__global__ __launch_bounds__(kFpThreads, 2) void mode_pass_kernel(PassArgs p) {
+  using T = typename Mma<BF>::T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* smem = (T*)smem_raw;
+  const PassLayout<BF, OP> L(p.In, p.K, p.ldT, p.ldI);
+  T* Tij = smem + L.oTij;
+  T* Ot = smem + L.oOt;  // M^T (sketch) or W^T (power), [k][j]
+  T* Tji = smem + L.oTji;
+  T* Qt = smem + L.oQt;
+  const int In = (int)p.In, K = p.K, ldT = p.ldT, ldI = p.ldI;
+  const int MT = (In + 15) / 16, NT = (K + 15) / 16;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;  // 8 waves
+
+  for (int x = tid; x < L.total; x += kFpThreads) smem[x] = Mma<BF>::cvt(0.f);
+  __syncthreads();
+  if (OP == 1) {
+    for (int x = tid; x < In * K; x += kFpThreads) {
+      const int i = x / K, k = x % K;
+      Qt[k * ldI + i] = Mma<BF>::cvt((float)p.Q[x]);
+    }
+  }
+
+  f32x4 acc[8];  // output tiles q = wid + 8 s of the (MT x NT) grid
+#pragma unroll
+  for (int s = 0; s < 8; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  float4 buf[8];
+  auto load = [&](int64_t t) {
+    const int64_t j0 = t * kFpTJ;
+    if constexpr (LD == 0) {
+      const int c4 = tid & 15;
+      const int64_t j = j0 + 4 * c4;
+      const bool ok = j < p.J;
+      const int64_t cb = ok ? (j / p.B) * p.In * p.B + (j % p.B) : 0;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int i = (tid >> 4) + 32 * s;
+        buf[s] = (ok && i < In) ? *(const float4*)(p.X + cb + (int64_t)i * p.B)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    } else if constexpr (LD == 1) {
+      const int q4 = In / 4;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int f = tid + kFpThreads * s;
+        const int al = f / q4, i4 = f % q4;
+        const int64_t j = j0 + al;
+        buf[s] = (al < kFpTJ && j < p.J) ? *(const float4*)(p.X + j * p.In + 4 * i4)
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    } else {
+      const int jl = tid & 63;
+      const int64_t j = j0 + jl;
+      const bool ok = j < p.J;
+      const int64_t cb = ok ? (j / p.B) * p.In * p.B + (j % p.B) : 0;
+#pragma unroll
+      for (int s = 0; s < 32; ++s) {
+        const int i = (tid >> 6) + 8 * s;
+        const float v = (ok && i < In) ? p.X[cb + (int64_t)i * p.B] : 0.f;
+        if ((s & 3) == 0) buf[s >> 2].x = v;
+        if ((s & 3) == 1) buf[s >> 2].y = v;
+        if ((s & 3) == 2) buf[s >> 2].z = v;
+        if ((s & 3) == 3) buf[s >> 2].w = v;
+      }
+    }
+  };
+  auto store = [&]() {
+    if constexpr (LD == 0) {
+      const int c4 = tid & 15;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int i = (tid >> 4) + 32 * s;
+        if (i < In) {
+          const float4 v = buf[s];
+          T* d = Tij + i * ldT + 4 * c4;
+          d[0] = Mma<BF>::cvt(v.x);
+          d[1] = Mma<BF>::cvt(v.y);
+          d[2] = Mma<BF>::cvt(v.z);
+          d[3] = Mma<BF>::cvt(v.w);
+          if (OP == 1) {
+            Tji[(4 * c4 + 0) * ldI + i] = Mma<BF>::cvt(v.x);
+            Tji[(4 * c4 + 1) * ldI + i] = Mma<BF>::cvt(v.y);
+            Tji[(4 * c4 + 2) * ldI + i] = Mma<BF>::cvt(v.z);
+            Tji[(4 * c4 + 3) * ldI + i] = Mma<BF>::cvt(v.w);
+          }
+        }
+      }
+    } else if constexpr (LD == 1) {
+      const int q4 = In / 4;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int f = tid + kFpThreads * s;
+        const int al = f / q4, i4 = f % q4;
+        if (al < kFpTJ) {
+          const float4 v = buf[s];
+          const int i = 4 * i4;
+          Tij[(i + 0) * ldT + al] = Mma<BF>::cvt(v.x);
+          Tij[(i + 1) * ldT + al] = Mma<BF>::cvt(v.y);
+          Tij[(i + 2) * ldT + al] = Mma<BF>::cvt(v.z);
+          Tij[(i + 3) * ldT + al] = Mma<BF>::cvt(v.w);
+          if (OP == 1) {
+            T* d = Tji + al * ldI + i;
+            d[0] = Mma<BF>::cvt(v.x);
+            d[1] = Mma<BF>::cvt(v.y);
+            d[2] = Mma<BF>::cvt(v.z);
+            d[3] = Mma<BF>::cvt(v.w);
+          }
+        }
+      }
+    } else {
+      const int jl = tid & 63;
+#pragma unroll
+      for (int s = 0; s < 32; ++s) {
+        const int i = (tid >> 6) + 8 * s;
+        if (i < In) {
+          const float4 v4 = buf[s >> 2];
+          const float v = (s & 3) == 0 ? v4.x : (s & 3) == 1 ? v4.y : (s & 3) == 2 ? v4.z : v4.w;
+          Tij[i * ldT + jl] = Mma<BF>::cvt(v);
+          if (OP == 1) Tji[jl * ldI + i] = Mma<BF>::cvt(v);
+        }
+      }
+    }
+  };
+  // Rows of M for the tile's columns: stream elements [j0*K, (j0+64)*K), written M^T[k][jl].
+  auto draw = [&](int64_t t) {
+    const int64_t j0 = t * kFpTJ;
+    const int64_t e0 = j0 * K;
+    const int64_t e1 = e0 + (int64_t)kFpTJ * K;
+    for (int64_t c = (e0 >> 2) + tid; c <= ((e1 - 1) >> 2); c += kFpThreads) {
+      float z[4];
+      normals4(p.seed, p.stream, p.tid, (uint64_t)c, z);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const int64_t e = 4 * c + l;
+        if (e >= e0 && e < e1) {
+          const int64_t rel = e - e0;
+          const int jl = (int)(rel / K), k = (int)(rel % K);
+          Ot[k * ldT + jl] = Mma<BF>::cvt((j0 + jl < p.J) ? z[l] : 0.f);
+        }
+      }
+    }
+  };
+
+  int64_t t = blockIdx.x;
+  if (t < p.ntiles) load(t);
+  for (; t < p.ntiles; t += gridDim.x) {
+    store();
+    if (OP == 0) draw(t);
+    __syncthreads();
+    const int64_t tn = t + gridDim.x;
+    if (tn < p.ntiles) load(tn);
+    if (OP == 1) {
+      // W^T [K x 64] = Q^T [K x In] * T [In x 64]  (contraction over i)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int q = wid + 8 * s;
+        if (q < NT * 4) {
+          const int nt = q >> 2, jt = q & 3;
+          f32x4 w = tile_abt(Qt + nt * 16 * ldI, ldI, Tji + jt * 16 * ldI, ldI, p.kI,
+                             f32x4{0.f, 0.f, 0.f, 0.f});
+          const int col = jt * 16 + (lane & 15);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Ot[(nt * 16 + 4 * (lane >> 4) + r) * ldT + col] = Mma<BF>::cvt(w[r]);
+        }
+      }
+      __syncthreads();
+    }
+    // Y [In x K] += T [In x 64] * (M or W) [64 x K]
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int q = wid + 8 * s;
+      if (q < MT * NT) {
+        const int mt = q / NT, nt = q % NT;
+        acc[s] = tile_abt(Tij + mt * 16 * ldT, ldT, Ot + nt * 16 * ldT, ldT, kFpTJ, acc[s]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int q = wid + 8 * s;
+    if (q < MT * NT) {
+      const int mt = q / NT, nt = q % NT;
+      const int n = nt * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = mt * 16 + 4 * (lane >> 4) + r;
+        if (m < In && n < K) p.partial[((int64_t)blockIdx.x * In + m) * K + n] = acc[s][r];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+static int ld_t(bool bf) { return bf ? kFpTJ + 8 : kFpTJ + 2; }
+static int k_i(bool bf, int64_t In) { return bf ? (int)((In + 31) / 32 * 32) : (int)((In + 3) / 4 * 4); }
+static int ld_i(bool bf, int64_t In) { return k_i(bf, In) + (bf ? 8 : 2); }
+
+static size_t pass_lds(bool bf, int op, int64_t In, int K) {
+  const int ldT = ld_t(bf), ldI = ld_i(bf, In);
+  int total;
+  if (bf)
+    total = op ? PassLayout<true, 1>(In, K, ldT, ldI).total : PassLayout<true, 0>(In, K, ldT, ldI).total;
+  else
+    total = op ? PassLayout<false, 1>(In, K, ldT, ldI).total : PassLayout<false, 0>(In, K, ldT, ldI).total;
+  return (size_t)total * (bf ? 2 : 4);
+}
+
+constexpr size_t kFpLdsMax = 160 * 1024;
+
+bool fast_pass_supported(Arith ar, const ModeView& v, int K, int op) {
+  if (ar == kF64) return false;
+  if (v.In > kFpMaxIn || K > kFpMaxK) return false;
+  return pass_lds(ar == kBF16, op, v.In, K) <= kFpLdsMax;
+}
+
+static const void* pass_fn(bool bf, int op, int loader) {
+#define RTR_FP_SEL(B_, O_, L_) \
+  if (bf == B_ && op == O_ && loader == L_) return (const void*)mode_pass_kernel<B_, O_, L_>;
+  RTR_FP_SEL(true, 0, 0) RTR_FP_SEL(true, 0, 1) RTR_FP_SEL(true, 0, 2)
+  RTR_FP_SEL(true, 1, 0) RTR_FP_SEL(true, 1, 1) RTR_FP_SEL(true, 1, 2)
+  RTR_FP_SEL(false, 0, 0) RTR_FP_SEL(false, 0, 1) RTR_FP_SEL(false, 0, 2)
+  RTR_FP_SEL(false, 1, 0) RTR_FP_SEL(false, 1, 1) RTR_FP_SEL(false, 1, 2)
+#undef RTR_FP_SEL
+  return nullptr;
+}
+
+static int pick_loader(const void* X, const ModeView& v) {
+  const bool al16 = ((uintptr_t)X & 15) == 0;
+  if (al16 && v.B % 4 == 0) return 0;
+  if (al16 && v.B == 1 && v.In % 4 == 0) return 1;
+  return 2;
+}
+
+// Work-groups resident per CU (HIP occupancy query) times the CU count.
+int64_t fast_pass_grid(Arith ar, const ModeView& v, int K, int op, const void* X) {
+  const bool bf = ar == kBF16;
+  const int64_t J = v.A * v.B;
+  const int64_t ntiles = (J + kFpTJ - 1) / kFpTJ;
+  const size_t lds = pass_lds(bf, op, v.In, K);
+  const void* fn = pass_fn(bf, op, pick_loader(X, v));
+  int dev = 0, cus = 256, per_cu = 1;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kFpThreads, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  (void)hipGetLastError();
+  const int64_t g = (int64_t)cus * per_cu;
+  return ntiles < g ? ntiles : g;
+}
+
+hipError_t launch_fast_pass(Arith ar, int op, const void* X, const ModeView& v, int K,
+                            uint64_t seed, uint32_t stream_word, uint32_t tensor_id,
+                            const double* Q, void* partial, int64_t grid, hipStream_t s) {
+  const bool bf = ar == kBF16;
+  PassArgs p{};
+  p.X = (const float*)X;
+  p.A = v.A;
+  p.In = v.In;
+  p.B = v.B;
+  p.J = v.A * v.B;
+  p.K = K;
+  p.seed = seed;
+  p.stream = stream_word;
+  p.tid = tensor_id;
+  p.Q = Q;
+  p.ntiles = (p.J + kFpTJ - 1) / kFpTJ;
+  p.partial = (float*)partial;
+  p.loader = pick_loader(X, v);
+  p.ldT = ld_t(bf);
+  p.ldI = ld_i(bf, v.In);
+  p.kI = k_i(bf, v.In);
+  const size_t lds = pass_lds(bf, op, v.In, K);
+  const void* fn = pass_fn(bf, op, p.loader);
+  if (!fn) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  prof_begin(op ? "power_fused" : "sketch_fused", s);
+  void* args[] = {&p};
+  e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kFpThreads), args, lds, s);
+  prof_end(s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+}  // namespace rtr

@@ -41,6 +41,12 @@ int64_t power_chunks(Arith ar, const ModeView& v, int K);
 hipError_t launch_power_partial(Arith ar, const void* X, const ModeView& v, int K,
                                 const double* Q, void* partial, int64_t chunks,
                                 hipStream_t s);
+// ---- fastpass.hip: matrix-core sketch (op 0) / power step (op 1) over FP32 X ----------
+bool fast_pass_supported(Arith ar, const ModeView& v, int K, int op);
+int64_t fast_pass_grid(Arith ar, const ModeView& v, int K, int op, const void* X);
+hipError_t launch_fast_pass(Arith ar, int op, const void* X, const ModeView& v, int K,
+                            uint64_t seed, uint32_t stream_word, uint32_t tensor_id,
+                            const double* Q, void* partial, int64_t grid, hipStream_t s);
 // Fixed-order sum of partials into column-major Ycol (K x In storage, Ycol[k*In+i]).
 hipError_t launch_reduce_partials(Arith ar, const void* partial, int64_t chunks, int64_t In,
                                   int K, double* Ycol, hipStream_t s);
@@ -63,6 +69,11 @@ hipError_t launch_identity(double* Q, int64_t In, hipStream_t s);
 // ``first`` selects the input type: X (F64/F32/BF16-with-refinement) or FP64.
 hipError_t launch_ttm(Arith ar, bool first, const void* in, const ModeView& v, int K,
                       const double* Q, double* out, hipStream_t s);
+// Fused first stage (compress_fast.hip): T[a] = Q1^T X_a Q2 over the last two modes.
+bool compress_slab_supported(Arith ar, int64_t A, int64_t I1, int64_t I2, int K1, int K2);
+hipError_t launch_compress_slab(Arith ar, const void* X, int64_t A, int64_t I1, int64_t I2,
+                                int K1, int K2, const double* Q1, const double* Q2, double* T,
+                                hipStream_t s);
 // Sum of squares of n values (FP64/FP32) into out[0] (FP64); ``partial`` holds 1024 FP64.
 hipError_t launch_sumsq(bool f32, const void* x, int64_t n, double* partial, double* out,
                         hipStream_t s);
@@ -102,6 +113,53 @@ hipError_t launch_als_err(const double* part, int64_t chunks, const double* pn2,
                           double tol, double* trace, int* sweeps_run, int* done,
                           hipStream_t s);
 hipError_t launch_als_begin(int* done, int* sweeps_run, hipStream_t s);
+
+// ---- als2.hip: two kernels per core update -------------------------------------------
+struct AlsArgs2 {
+  const double* P;
+  const double* Z;       // packed cores
+  int N, n, Kn, Ra, Rb, RR;
+  int64_t J;
+  int cycK[8];           // dims of P in the cyclic order after mode n
+  int64_t cycStride[8];  // their strides in P
+  int64_t strideN;
+  int chI[8];            // the same modes seen as the subchain's cores
+  int chRb[8];
+  int64_t chOff[8];      // offsets of those cores in Z
+  int64_t zoffN;         // offset of core n in Z
+  int mode;              // bit 0: accumulate M and Gram; bit 1: residual with core n
+  int64_t tiles_per_wg;
+  double* part;          // [grid][Kn*RR + RR*RR + 1]
+  const int* done;
+};
+struct AlsSolveArgs {
+  const double* part;
+  int nparts, Kn, RR, Rb;
+  double* Zn;
+  unsigned* status;
+  int* done;
+  int report_sweep;  // >= 0: the partials also carry that sweep's residual
+  int report_only;
+  const double* pn2;
+  double* trace;
+  int* sweeps_run;
+  double tol;
+};
+bool als2_supported(int Kn, int RR);
+int64_t als2_grid(int64_t J);
+hipError_t launch_als_accum(AlsArgs2 g, int64_t grid, int rmax, hipStream_t s);
+hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s);
+
+__device__ __forceinline__ int64_t cyc_base_of(int N, const int* cycK, const int64_t* cycStride,
+                                               int64_t j) {
+  int64_t base = 0;
+  for (int t = N - 2; t >= 0; --t) {
+    const int64_t d = cycK[t];
+    base += (j % d) * cycStride[t];
+    j /= d;
+  }
+  return base;
+}
 
 // ---- eval.hip -------------------------------------------------------------------------
 hipError_t launch_backproject(const double* Z, const double* Q, int Ra, int K, int64_t In,

@@ -257,12 +257,19 @@ rtr_status rtr_sketch(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t or
     if (k > 64)
       return fail(h, RTR_ERR_UNSUPPORTED, "projection size above 64 (mode " + std::to_string(n) + ")");
     rtr::ModeView v = mode_view(dims, order, n);
-    size_t need = (size_t)rtr::sketch_chunks(v, (int)k) * v.In * k * pelem;
+    size_t need = rtr::fast_pass_supported(ar, v, (int)k, 0)
+                      ? (size_t)rtr::fast_pass_grid(ar, v, (int)k, 0, X) * v.In * k * sizeof(float)
+                      : (size_t)rtr::sketch_chunks(v, (int)k) * v.In * k * pelem;
     if (power_iters > 0) {
-      if (!rtr::power_supported(ar, v, (int)k))
-        return fail(h, RTR_ERR_UNSUPPORTED,
-                    "power iterations need I_n*K_n <= 8192 (mode " + std::to_string(n) + ")");
-      size_t pw = (size_t)rtr::power_chunks(ar, v, (int)k) * v.In * k * pelem;
+      size_t pw;
+      if (rtr::fast_pass_supported(ar, v, (int)k, 1)) {
+        pw = (size_t)rtr::fast_pass_grid(ar, v, (int)k, 1, X) * v.In * k * sizeof(float);
+      } else {
+        if (!rtr::power_supported(ar, v, (int)k))
+          return fail(h, RTR_ERR_UNSUPPORTED,
+                      "power iterations need I_n*K_n <= 8192 (mode " + std::to_string(n) + ")");
+        pw = (size_t)rtr::power_chunks(ar, v, (int)k) * v.In * k * pelem;
+      }
       if (pw > need) need = pw;
     }
     if (need > pmax) pmax = need;
@@ -296,12 +303,21 @@ rtr_status rtr_sketch(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t or
       continue;
     }
     rtr::ModeView v = mode_view(dims, order, n);
-    const int64_t chunks = rtr::sketch_chunks(v, (int)k);
-    HIP_TRY(rtr::launch_sketch_partial(ar, X, v, (int)k, seed, rtr::omega_stream(n), tensor_id,
-                                       partial, chunks, s),
-            "sketch_partial");
-    HIP_TRY(rtr::launch_reduce_partials(ar, partial, chunks, v.In, (int)k, Ycol[n], s),
-            "reduce_partials");
+    if (rtr::fast_pass_supported(ar, v, (int)k, 0)) {
+      const int64_t grid = rtr::fast_pass_grid(ar, v, (int)k, 0, X);
+      HIP_TRY(rtr::launch_fast_pass(ar, 0, X, v, (int)k, seed, rtr::omega_stream(n), tensor_id,
+                                    nullptr, partial, grid, s),
+              "sketch_fused");
+      HIP_TRY(rtr::launch_reduce_partials(rtr::kF32, partial, grid, v.In, (int)k, Ycol[n], s),
+              "reduce_partials");
+    } else {
+      const int64_t chunks = rtr::sketch_chunks(v, (int)k);
+      HIP_TRY(rtr::launch_sketch_partial(ar, X, v, (int)k, seed, rtr::omega_stream(n), tensor_id,
+                                         partial, chunks, s),
+              "sketch_partial");
+      HIP_TRY(rtr::launch_reduce_partials(ar, partial, chunks, v.In, (int)k, Ycol[n], s),
+              "reduce_partials");
+    }
     const int j = jobs.count++;
     jobs.A[j] = Ycol[n];
     jobs.Qwork[j] = Qw[n];
@@ -315,11 +331,19 @@ rtr_status rtr_sketch(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t or
       const int64_t k = keff(dims, K, n);
       if (k == dims[n]) continue;
       rtr::ModeView v = mode_view(dims, order, n);
-      const int64_t chunks = rtr::power_chunks(ar, v, (int)k);
-      HIP_TRY(rtr::launch_power_partial(ar, X, v, (int)k, Qn[n], partial, chunks, s),
-              "power_partial");
-      HIP_TRY(rtr::launch_reduce_partials(ar, partial, chunks, v.In, (int)k, Ycol[n], s),
-              "reduce_partials");
+      if (rtr::fast_pass_supported(ar, v, (int)k, 1)) {
+        const int64_t grid = rtr::fast_pass_grid(ar, v, (int)k, 1, X);
+        HIP_TRY(rtr::launch_fast_pass(ar, 1, X, v, (int)k, 0, 0, 0, Qn[n], partial, grid, s),
+                "power_fused");
+        HIP_TRY(rtr::launch_reduce_partials(rtr::kF32, partial, grid, v.In, (int)k, Ycol[n], s),
+                "reduce_partials");
+      } else {
+        const int64_t chunks = rtr::power_chunks(ar, v, (int)k);
+        HIP_TRY(rtr::launch_power_partial(ar, X, v, (int)k, Qn[n], partial, chunks, s),
+                "power_partial");
+        HIP_TRY(rtr::launch_reduce_partials(ar, partial, chunks, v.In, (int)k, Ycol[n], s),
+                "reduce_partials");
+      }
     }
     HIP_TRY(rtr::launch_householder_qr(jobs, s), "householder_qr");
   }
@@ -344,15 +368,39 @@ rtr_status rtr_compress(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t 
   for (int n = 0; n < order; ++n)
     if (keff(dims, K, n) > 64)
       return fail(h, RTR_ERR_UNSUPPORTED, "projection size above 64 (mode " + std::to_string(n) + ")");
-  // intermediate sizes
+  size_t qoffs[RTR_MAX_ORDER];
+  {
+    size_t q = 0;
+    for (int n = 0; n < order; ++n) {
+      qoffs[n] = q;
+      q += (size_t)dims[n] * keff(dims, K, n);
+    }
+  }
+  // Plan: optionally the fused product over the last two modes first, then one mode
+  // product per remaining mode (mode 1 first).  Each step maps ``cur`` dims to new dims.
+  int64_t A = 1;
+  for (int n = 0; n < order - 2; ++n) A *= dims[n];
+  const bool fused =
+      order >= 2 && rtr::compress_slab_supported(ar, A, dims[order - 2], dims[order - 1],
+                                                 (int)keff(dims, K, order - 2),
+                                                 (int)keff(dims, K, order - 1));
   int64_t cur[RTR_MAX_ORDER];
   for (int n = 0; n < order; ++n) cur[n] = dims[n];
   size_t maxmid = 1;
-  for (int n = 0; n < order - 1; ++n) {
+  auto numel = [&]() {
+    size_t z = 1;
+    for (int m = 0; m < order; ++m) z *= (size_t)cur[m];
+    return z;
+  };
+  const int nmodes = fused ? order - 2 : order;  // modes left for single mode products
+  if (fused) {
+    cur[order - 2] = keff(dims, K, order - 2);
+    cur[order - 1] = keff(dims, K, order - 1);
+    if (nmodes > 0) maxmid = std::max(maxmid, numel());
+  }
+  for (int n = 0; n < nmodes - 1; ++n) {
     cur[n] = keff(dims, K, n);
-    size_t sz = 1;
-    for (int m = 0; m < order; ++m) sz *= (size_t)cur[m];
-    if (sz > maxmid) maxmid = sz;
+    maxmid = std::max(maxmid, numel());
   }
   Carve plan(nullptr);
   plan.take<double>(maxmid);
@@ -365,15 +413,29 @@ rtr_status rtr_compress(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t 
 
   for (int n = 0; n < order; ++n) cur[n] = dims[n];
   const void* in = X;
-  size_t qoff = 0;
-  for (int n = 0; n < order; ++n) {
+  bool in_is_x = true;
+  int nb = 0;  // next ping-pong buffer
+  if (fused) {
+    const int K1 = (int)keff(dims, K, order - 2), K2 = (int)keff(dims, K, order - 1);
+    double* out = (nmodes == 0) ? P : buf[nb];
+    HIP_TRY(rtr::launch_compress_slab(ar, X, A, dims[order - 2], dims[order - 1], K1, K2,
+                                      Q + qoffs[order - 2], Q + qoffs[order - 1], out, s),
+            "compress_fused");
+    cur[order - 2] = K1;
+    cur[order - 1] = K2;
+    in = out;
+    in_is_x = false;
+    nb ^= 1;
+  }
+  for (int n = 0; n < nmodes; ++n) {
     const int64_t k = keff(dims, K, n);
     rtr::ModeView v = mode_view(cur, order, n);
-    double* out = (n == order - 1) ? P : buf[n & 1];
-    HIP_TRY(rtr::launch_ttm(ar, n == 0, in, v, (int)k, Q + qoff, out, s), "ttm");
-    qoff += (size_t)dims[n] * k;
+    double* out = (n == nmodes - 1) ? P : buf[nb];
+    HIP_TRY(rtr::launch_ttm(ar, in_is_x, in, v, (int)k, Q + qoffs[n], out, s), "ttm");
     cur[n] = k;
     in = out;
+    in_is_x = false;
+    nb ^= 1;
   }
   if (p_norm2) {
     size_t np = 1;
@@ -449,9 +511,17 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
     noutmax = std::max(noutmax, g.Kn * g.RR + g.RR * g.RR);
     chunkmax = std::max(chunkmax, rtr::als_chunks(g));
   }
+  bool use2 = true;
+  int64_t grid2max = 1;
+  for (int n = 0; n < order; ++n) {
+    use2 = use2 && rtr::als2_supported(geo[n].Kn, geo[n].RR);
+    grid2max = std::max(grid2max, rtr::als2_grid(geo[n].J));
+  }
+  int rmax = 0;
+  for (int n = 0; n < order; ++n) rmax = std::max(rmax, (int)R[n]);
   Carve plan(nullptr);
   plan.take<double>((size_t)Jmax * RRmax);
-  plan.take<double>((size_t)chunkmax * noutmax);
+  plan.take<double>((size_t)std::max(chunkmax, grid2max) * (noutmax + 1));
   plan.take<double>(noutmax);
   plan.take<double>(chunkmax);
   plan.take<double>(1024);
@@ -460,7 +530,7 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
   if ((st = ensure_ws(h, plan.off + 256))) return st;
   Carve cv(h->ws);
   double* Bm = cv.take<double>((size_t)Jmax * RRmax);
-  double* part = cv.take<double>((size_t)chunkmax * noutmax);
+  double* part = cv.take<double>((size_t)std::max(chunkmax, grid2max) * (noutmax + 1));
   double* MG = cv.take<double>(noutmax);
   double* rpart = cv.take<double>(chunkmax);
   double* red = cv.take<double>(1024);
@@ -472,6 +542,66 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
             "hipMemcpyAsync");
   HIP_TRY(rtr::launch_sumsq(false, P, total, red, pn2, s), "sumsq");
   HIP_TRY(rtr::launch_als_begin(done, sweeps_run, s), "als_begin");
+  if (use2) {
+    auto args_for = [&](int n, int mode) {
+      const rtr::AlsGeom& g = geo[n];
+      rtr::AlsArgs2 a{};
+      a.P = P;
+      a.Z = Z;
+      a.N = order;
+      a.n = n;
+      a.Kn = g.Kn;
+      a.Ra = g.Ra;
+      a.Rb = g.Rb;
+      a.RR = g.RR;
+      a.J = g.J;
+      for (int t = 0; t < order - 1; ++t) {
+        const int m = (n + 1 + t) % order;
+        a.cycK[t] = g.cycK[t];
+        a.cycStride[t] = g.cycStride[t];
+        a.chI[t] = Kp[m];
+        a.chRb[t] = R[(m + 1) % order];
+        a.chOff[t] = (int64_t)zoff[m];
+      }
+      a.strideN = g.strideN;
+      a.zoffN = (int64_t)zoff[n];
+      a.mode = mode;
+      a.part = part;
+      a.done = done;
+      return a;
+    };
+    auto solve_for = [&](int n, int64_t grid, int report, int report_only) {
+      const rtr::AlsGeom& g = geo[n];
+      rtr::AlsSolveArgs a{};
+      a.part = part;
+      a.nparts = (int)grid;
+      a.Kn = g.Kn;
+      a.RR = g.RR;
+      a.Rb = g.Rb;
+      a.Zn = Z + zoff[n];
+      a.status = h->status;
+      a.done = done;
+      a.report_sweep = report;
+      a.report_only = report_only;
+      a.pn2 = pn2;
+      a.trace = err_trace;
+      a.sweeps_run = sweeps_run;
+      a.tol = opts->tol;
+      return a;
+    };
+    for (int sw = 0; sw < opts->max_sweeps; ++sw) {
+      for (int n = 0; n < order; ++n) {
+        const bool rep = (n == 0 && sw > 0);
+        const int64_t grid = rtr::als2_grid(geo[n].J);
+        HIP_TRY(rtr::launch_als_accum(args_for(n, 1 | (rep ? 2 : 0)), grid, rmax, s), "als_accum");
+        HIP_TRY(rtr::launch_als_solve2(solve_for(n, grid, rep ? sw - 1 : -1, 0), s), "als_solve");
+      }
+    }
+    const int64_t grid = rtr::als2_grid(geo[0].J);
+    HIP_TRY(rtr::launch_als_accum(args_for(0, 2), grid, rmax, s), "als_accum");
+    HIP_TRY(rtr::launch_als_solve2(solve_for(0, grid, opts->max_sweeps - 1, 1), s), "als_solve");
+    return RTR_OK;
+  }
   for (int sw = 0; sw < opts->max_sweeps; ++sw) {
     for (int n = 0; n < order; ++n) {
       const rtr::AlsGeom& g = geo[n];
