@@ -25,85 +25,124 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-constexpr int kA2Acc = 64;
-constexpr int kA2Threads = 256;
+constexpr int kA2Threads = 1024;
 
-// Left operand L = [P_<n>[:, tile] (Kn rows); B_tile^T (RR rows)] and right operand B_tile:
-// [M; Gram] += L B_tile, output (Kn + RR) x RR.  Thread t owns outputs t + 256 q, q < NQ.
-template <int RM, int NQ>
+// Outputs of the per-column accumulation: [M (Kn x RR); Gram (RR x RR) if direct], as the
+// product L B_tile with L = [P_<n>[:, tile]; B_tile^T].  Thread t owns outputs t + 1024 q.
+// TJ columns per tile: 128 when the Gram comes from transfer matrices (every thread then
+// forms a subchain row), 32 when the Gram is accumulated here.
+template <int RM, int NQ, int TJ>
 __global__ __launch_bounds__(kA2Threads) void als_accum_kernel(AlsArgs2 g) {
-  if (*g.done) return;
   extern __shared__ __align__(16) double sm[];
   const int RR = g.RR, Kn = g.Kn, Ra = g.Ra, Rb = g.Rb;
-  double* Bs = sm;                         // [32][RR]
-  double* Ls = sm + kA2TJ * RR;            // [Kn + RR][32]
-  __shared__ int64_t pbase[kA2TJ];
-  __shared__ double red[16];
-  const int nM = Kn * RR, nout = nM + RR * RR;
+  double* Zs = sm;                                          // packed cores (zlds)
+  double* Bs = sm + (g.zlds ? (g.ztotal + 1) / 2 * 2 : 0);  // [TJ][RR]
+  double* Ls = Bs + TJ * RR;                                // [Kn + RR?][TJ]
+  const double* Zsrc = g.zlds ? Zs : g.Z;
+  __shared__ double red[32];
+  const int nM = Kn * RR;
+  const int nout = nM + (g.gram_direct ? RR * RR : 0);
   const bool accum = g.mode & 1, resid = g.mode & 2;
-  const double* Zn = g.Z + g.zoffN;
   const int tid = threadIdx.x;
+  if (g.zlds) {  // cores: all loads issued before any store (at most 6 per thread)
+    double zt[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int64_t x = tid + (int64_t)e * kA2Threads;
+      zt[e] = x < g.ztotal ? g.Z[x] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int64_t x = tid + (int64_t)e * kA2Threads;
+      if (x < g.ztotal) Zs[x] = zt[e];
+    }
+  }
+  if (*g.done) return;
   double acc[NQ];
   int rowoff[NQ], colidx[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     acc[q] = 0.0;
     const int o = tid + q * kA2Threads;
-    rowoff[q] = (o < nout) ? (o / RR) * kA2TJ : -1;
+    rowoff[q] = (o < nout) ? (o / RR) * TJ : -1;
     colidx[q] = o % RR;
   }
   double rsum = 0.0;
-  const int64_t ntiles = (g.J + kA2TJ - 1) / kA2TJ;
+  const int64_t ntiles = (g.J + TJ - 1) / TJ;
   const int64_t t0 = (int64_t)blockIdx.x * g.tiles_per_wg;
   const int64_t t1 = min(ntiles, t0 + g.tiles_per_wg);
+  __syncthreads();
   for (int64_t t = t0; t < t1; ++t) {
-    const int64_t j0 = t * kA2TJ;
-    const int jn = (int)min((int64_t)kA2TJ, g.J - j0);
+    const int j0 = (int)(t * TJ);
+    const int jn = (int)min((int64_t)TJ, g.J - j0);
+    // P_<n>[:, tile] (column bases in int32: P has < 2^31 entries); all loads issued first
+    {
+      constexpr int kPer = (64 * TJ + kA2Threads - 1) / kA2Threads;
+      double pv[kPer];
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) {
+        const int x = tid + e * kA2Threads;
+        const int i = x / TJ, jj = x % TJ;
+        pv[e] = 0.0;
+        if (x < Kn * TJ && jj < jn) {
+          int rem = j0 + jj, base = 0;
+#pragma unroll
+          for (int u = 6; u >= 0; --u) {
+            if (u <= g.N - 2) {
+              const int d = g.cycK[u];
+              const int q = rem / d;
+              base += (rem - q * d) * (int)g.cycStride[u];
+              rem = q;
+            }
+          }
+          pv[e] = g.P[base + i * (int)g.strideN];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) {
+        const int x = tid + e * kA2Threads;
+        if (x < Kn * TJ) Ls[x] = pv[e];
+      }
+    }
     // subchain rows: thread (jl, b) forms row b of S_j
-    for (int x = tid; x < kA2TJ * Rb; x += kA2Threads) {
+    for (int x = tid; x < TJ * Rb; x += kA2Threads) {
       const int jl = x / Rb, b = x % Rb;
       double v[RM], w[RM];
 #pragma unroll
       for (int a = 0; a < RM; ++a) v[a] = (jl < jn && a == b) ? 1.0 : 0.0;
       if (jl < jn) {
-        int64_t rem = j0 + jl;
-        int cur = Rb;
-        int idx0 = 0, idx1 = 0, idx2 = 0, idx3 = 0, idx4 = 0, idx5 = 0, idx6 = 0;
-        {
-          int tmp[7];
-          for (int u = g.N - 2; u >= 0; --u) {
-            tmp[u] = (int)(rem % g.chI[u]);
+        int rem = j0 + jl;
+        int idx[7];
+#pragma unroll
+        for (int u = 6; u >= 0; --u) {
+          if (u <= g.N - 2) {
+            idx[u] = rem % g.chI[u];
             rem /= g.chI[u];
           }
-          idx0 = tmp[0];
-          if (g.N > 2) idx1 = tmp[1];
-          if (g.N > 3) idx2 = tmp[2];
-          if (g.N > 4) idx3 = tmp[3];
-          if (g.N > 5) idx4 = tmp[4];
-          if (g.N > 6) idx5 = tmp[5];
-          if (g.N > 7) idx6 = tmp[6];
         }
-        for (int u = 0; u < g.N - 1; ++u) {
-          const int iu = u == 0 ? idx0 : u == 1 ? idx1 : u == 2 ? idx2 : u == 3 ? idx3
-                       : u == 4 ? idx4 : u == 5 ? idx5 : idx6;
-          const int cRb = g.chRb[u];
-          const double* G = g.Z + g.chOff[u] + (int64_t)iu * cRb;
-          const int64_t rs = (int64_t)g.chI[u] * cRb;
+        int cur = Rb;
 #pragma unroll
-          for (int c = 0; c < RM; ++c) w[c] = 0.0;
+        for (int u = 0; u < 7; ++u) {
+          if (u < g.N - 1) {
+            const int cRb = g.chRb[u];
+            const double* G = Zsrc + g.chOff[u] + (int64_t)idx[u] * cRb;
+            const int rs = g.chI[u] * cRb;
 #pragma unroll
-          for (int a = 0; a < RM; ++a) {
-            if (a < cur) {
-              const double va = v[a];
-              const double* gr = G + a * rs;
+            for (int c = 0; c < RM; ++c) w[c] = 0.0;
 #pragma unroll
-              for (int c = 0; c < RM; ++c)
-                if (c < cRb) w[c] += va * gr[c];
+            for (int a = 0; a < RM; ++a) {
+              if (a < cur) {
+                const double va = v[a];
+                const double* gr = G + a * rs;
+#pragma unroll
+                for (int c = 0; c < RM; ++c)
+                  if (c < cRb) w[c] += va * gr[c];
+              }
             }
-          }
 #pragma unroll
-          for (int c = 0; c < RM; ++c) v[c] = w[c];
-          cur = cRb;
+            for (int c = 0; c < RM; ++c) v[c] = w[c];
+            cur = cRb;
+          }
         }
       }
 #pragma unroll
@@ -111,33 +150,31 @@ __global__ __launch_bounds__(kA2Threads) void als_accum_kernel(AlsArgs2 g) {
         if (a < Ra) {
           const int r = a * Rb + b;
           Bs[jl * RR + r] = v[a];
-          Ls[(Kn + r) * kA2TJ + jl] = v[a];
+          if (g.gram_direct) Ls[(Kn + r) * TJ + jl] = v[a];
         }
       }
     }
-    if (tid < kA2TJ) pbase[tid] = (tid < jn) ? cyc_base_of(g.N, g.cycK, g.cycStride, j0 + tid) : (int64_t)-1;
-    __syncthreads();
-    for (int x = tid; x < Kn * kA2TJ; x += kA2Threads) {
-      const int i = x / kA2TJ, jj = x % kA2TJ;
-      const int64_t pb = pbase[jj];
-      Ls[x] = (pb >= 0) ? g.P[pb + (int64_t)i * g.strideN] : 0.0;
-    }
     __syncthreads();
     if (accum) {
-      for (int jj = 0; jj < kA2TJ; ++jj) {
+#pragma unroll 8
+      for (int jj = 0; jj < TJ; ++jj) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
           if (rowoff[q] >= 0) acc[q] += Ls[rowoff[q] + jj] * Bs[jj * RR + colidx[q]];
       }
     }
     if (resid) {
-      for (int x = tid; x < Kn * kA2TJ; x += kA2Threads) {
-        const int i = x / kA2TJ, jj = x % kA2TJ;
+      const double* Zn = Zsrc + g.zoffN;
+      for (int x = tid; x < Kn * TJ; x += kA2Threads) {
+        const int i = x / TJ, jj = x % TJ;
         if (jj < jn) {
           double psi = 0.0;
-          for (int a = 0; a < Ra; ++a)
-            for (int b = 0; b < Rb; ++b)
-              psi += Zn[((int64_t)a * Kn + i) * Rb + b] * Bs[jj * RR + a * Rb + b];
+          for (int a = 0; a < Ra; ++a) {
+            const double* zr = Zn + (a * Kn + i) * Rb;
+            const double* br = Bs + jj * RR + a * Rb;
+#pragma unroll 8
+            for (int b = 0; b < Rb; ++b) psi += zr[b] * br[b];
+          }
           const double d = Ls[x] - psi;
           rsum += d * d;
         }
@@ -155,8 +192,107 @@ __global__ __launch_bounds__(kA2Threads) void als_accum_kernel(AlsArgs2 g) {
   if (tid == 0) out[nout] = rsum;
 }
 
+
+// Cholesky of the RR x RR matrix G (LDS, row-major) by one wavefront, RR <= RMAX <= 64:
+// lane i keeps row i in registers (loops unrolled to RMAX so every index is static); at
+// step j the pivot and column j are read from the owning lanes with readlane.  The lower
+// factor is written back to G.  Sets *failed when a pivot is not positive.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int2 p = __builtin_bit_cast(int2, v);
+  int2 q;
+  q.x = __builtin_amdgcn_readlane(p.x, lane);
+  q.y = __builtin_amdgcn_readlane(p.y, lane);
+  return __builtin_bit_cast(double, q);
+}
+
+template <int RMAX>
+__device__ void chol_wave(double* G, int RR, int* failed) {
+  const int i = threadIdx.x & 63;
+  double row[RMAX];
+#pragma unroll
+  for (int c = 0; c < RMAX; ++c) row[c] = (i < RR && c < RR) ? G[i * RR + c] : 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j) {
+    if (j < RR && ok) {
+      const double d = readlane_f64(row[j], j);
+      if (!(d > 0.0)) {
+        ok = false;
+      } else {
+        const double ljj = sqrt(d);
+        const double inv = 1.0 / ljj;
+        if (i == j) row[j] = ljj;
+        if (i > j) row[j] *= inv;
+#pragma unroll
+        for (int k = j + 1; k < RMAX; ++k) {
+          if (k < RR) {
+            const double lkj = readlane_f64(row[j], k);
+            if (i >= k) row[k] -= row[j] * lkj;
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep each step's loads and readlanes local
+  }
+  if (!ok) {
+    if (i == 0) *failed = 1;
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < RMAX; ++c)
+    if (i < RR && c <= i && c < RR) G[i * RR + c] = row[c];
+}
+
+// Forward and back substitution with the factor L (lower part of G) for every row of M
+// (Kn x RR, LDS): lane/thread r owns row r in registers; L is read with uniform addresses.
+template <int RMAX>
+__device__ void subst_rows(double* M, const double* G, int RR, int Kn) {
+  for (int row = threadIdx.x; row < Kn; row += blockDim.x) {
+    double m[RMAX];
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) m[c] = c < RR ? M[row * RR + c] : 0.0;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      if (r < RR) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < r; ++k) {
+          if (k & 1)
+            s1 += G[r * RR + k] * m[k];
+          else
+            s0 += G[r * RR + k] * m[k];
+        }
+        m[r] = (m[r] - (s0 + s1)) / G[r * RR + r];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int r = RMAX - 1; r >= 0; --r) {
+      if (r < RR) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int k = r + 1; k < RMAX; ++k) {
+          if (k < RR) {
+            if (k & 1)
+              s1 += G[k * RR + r] * m[k];
+            else
+              s0 += G[k * RR + r] * m[k];
+          }
+        }
+        m[r] = (m[r] - (s0 + s1)) / G[r * RR + r];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c)
+      if (c < RR) M[row * RR + c] = m[c];
+  }
+}
+
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void als_solve2_kernel(AlsSolveArgs g) {
+// RMAX: register bound of the Cholesky and substitutions (16, 36, 64); 0 = LDS fallback.
+template <int RMAX>
+__global__ __launch_bounds__(512) void als_solve2_kernel(AlsSolveArgs g) {
   if (*g.done) return;
   extern __shared__ __align__(16) double sm[];
   const int RR = g.RR, Kn = g.Kn, nM = Kn * RR, nout = nM + RR * RR;
@@ -166,9 +302,10 @@ __global__ __launch_bounds__(1024) void als_solve2_kernel(AlsSolveArgs g) {
   __shared__ int failed;
   const int tid = threadIdx.x, nth = blockDim.x;
   // close the previous sweep: its error was accumulated by the partials of this update
+  const int nstore = g.gram_direct ? nout : nM;  // partial record length (+1 residual)
   if (g.report_sweep >= 0) {
     double s = 0.0;
-    for (int c = tid; c < g.nparts; c += nth) s += g.part[(int64_t)c * (nout + 1) + nout];
+    for (int c = tid; c < g.nparts; c += nth) s += g.part[(int64_t)c * (nstore + 1) + nstore];
     s = block_sum(s, red);
     if (tid == 0) {
       const double e = sqrt(s / g.pn2[0]);
@@ -180,38 +317,91 @@ __global__ __launch_bounds__(1024) void als_solve2_kernel(AlsSolveArgs g) {
     __syncthreads();
     if (*g.done || g.report_only) return;
   }
-  for (int o = tid; o < nout; o += nth) {
+  const int nred = g.gram_direct ? nout : nM;  // outputs summed from the partials
+  for (int o = tid; o < nred; o += nth) {
+    const double* src = g.part + o;
+    const int64_t st = nred + 1;
     double s = 0.0;
-    for (int c = 0; c < g.nparts; ++c) s += g.part[(int64_t)c * (nout + 1) + o];
+    int c = 0;
+    for (; c + 16 <= g.nparts; c += 16) {  // sixteen loads in flight, summed in order
+      double v[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = src[(c + e) * st];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) s += v[e];
+    }
+    for (; c < g.nparts; ++c) s += src[c * st];
     sm[o] = s;
   }
   if (tid == 0) failed = 0;
-  __syncthreads();
-  if (RR <= 64) {
-    // one wavefront: lane i owns row i of the factor
-    if (tid < 64) {
-      const int i = tid;
-      for (int j = 0; j < RR; ++j) {
-        double d = 0.0;
-        if (i == j) {
-          d = G[j * RR + j];
-          for (int k = 0; k < j; ++k) d -= G[j * RR + k] * G[j * RR + k];
-          G[j * RR + j] = (d > 0.0) ? sqrt(d) : 0.0;
-        }
-        const double djj = __shfl(d, j, 64);
-        if (!(djj > 0.0)) {
-          if (i == 0) failed = 1;
-          break;
-        }
-        wave_sync();
-        if (i > j && i < RR) {
-          double s = G[i * RR + j];
-          for (int k = 0; k < j; ++k) s -= G[i * RR + k] * G[j * RR + k];
-          G[i * RR + j] = s / G[j * RR + j];
-        }
-        wave_sync();
+  if (!g.gram_direct) {
+    // Gram from transfer matrices: sum_j S_j (x) S_j = E_{n+1} E_{n+2} ... E_{n-1},
+    // E_m[(p,p'),(q,q')] = sum_i Z_m[p,i,q] Z_m[p',i,q']; then Gram[(a,b),(a',b')] is the
+    // entry [(b,b'),(a,a')] of that product.
+    double* Tm = sm + nout;            // running product, R_{n+1}^2 x R_cur^2
+    double* Em = Tm + g.tsz;           // next transfer matrix
+    double* Tn = Em + g.tsz;           // product buffer
+    double* Zs = Tn + g.tsz;           // cores (one batch of loads)
+    {
+      double zt[12];
+#pragma unroll
+      for (int e = 0; e < 12; ++e) {
+        const int64_t x = tid + (int64_t)e * nth;
+        zt[e] = x < g.ztotal ? g.Z[x] : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < 12; ++e) {
+        const int64_t x = tid + (int64_t)e * nth;
+        if (x < g.ztotal) Zs[x] = zt[e];
       }
     }
+    __syncthreads();
+    const int Rn1 = g.Rc[(g.n + 1) % g.N];
+    int rcur = Rn1;
+    for (int t = 1; t < g.N; ++t) {
+      const int m = (g.n + t) % g.N;
+      const int Rp = g.Rc[m], Rq = g.Rc[(m + 1) % g.N], Km = g.Kc[m];
+      const double* Zm = Zs + g.zoff[m];
+      double* dst = (t == 1) ? Tm : Em;
+      const int ne = Rp * Rp * Rq * Rq;
+      for (int x = tid; x < ne; x += nth) {
+        const int col = x % (Rq * Rq), row = x / (Rq * Rq);
+        const int p = row / Rp, pp = row % Rp, q = col / Rq, qq = col % Rq;
+        const double* za = Zm + p * Km * Rq + q;
+        const double* zb = Zm + pp * Km * Rq + qq;
+        double s = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < Km; ++i) s += za[i * Rq] * zb[i * Rq];
+        dst[x] = s;
+      }
+      __syncthreads();
+      if (t > 1) {
+        const int nr = Rn1 * Rn1, nk = Rp * Rp, nc = Rq * Rq;
+        for (int x = tid; x < nr * nc; x += nth) {
+          const int r = x / nc, c = x % nc;
+          double s = 0.0;
+#pragma unroll 8
+          for (int k = 0; k < nk; ++k) s += Tm[r * nk + k] * Em[k * nc + c];
+          Tn[x] = s;
+        }
+        __syncthreads();
+        for (int x = tid; x < nr * nc; x += nth) Tm[x] = Tn[x];
+        __syncthreads();
+      }
+      rcur = Rq;
+    }
+    (void)rcur;
+    // here rcur == R_n: Tm is R_{n+1}^2 x R_n^2
+    const int Rb2 = g.Rb, Ra2 = g.Ra;
+    for (int x = tid; x < RR * RR; x += nth) {
+      const int r1 = x / RR, r2 = x % RR;           // (a,b), (a',b')
+      const int a = r1 / Rb2, b = r1 % Rb2, a2 = r2 / Rb2, b2 = r2 % Rb2;
+      sm[nM + x] = Tm[(b * Rb2 + b2) * (Ra2 * Ra2) + (a * Ra2 + a2)];
+    }
+  }
+  __syncthreads();
+  if constexpr (RMAX > 0) {
+    if (tid < 64) chol_wave<RMAX>(G, RR, &failed);
   } else {
     for (int j = 0; j < RR; ++j) {
       if (tid == 0) {
@@ -239,25 +429,22 @@ __global__ __launch_bounds__(1024) void als_solve2_kernel(AlsSolveArgs g) {
     if (tid == 0) atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
     return;
   }
-  // 16 lanes per right-hand side: L y = m, then L^T w = y
-  const int grp = tid >> 4, l16 = tid & 15, ngrp = nth >> 4;
-  for (int row = grp; row < Kn; row += ngrp) {
-    double* m = M + (int64_t)row * RR;
-    for (int r = 0; r < RR; ++r) {
-      double s = 0.0;
-      for (int k = l16; k < r; k += 16) s -= G[r * RR + k] * m[k];
-#pragma unroll
-      for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
-      if (l16 == 0) m[r] = (m[r] + s) / G[r * RR + r];
-      wave_sync();
-    }
-    for (int r = RR - 1; r >= 0; --r) {
-      double s = 0.0;
-      for (int k = r + 1 + l16; k < RR; k += 16) s -= G[k * RR + r] * m[k];
-#pragma unroll
-      for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
-      if (l16 == 0) m[r] = (m[r] + s) / G[r * RR + r];
-      wave_sync();
+  // one lane per right-hand side (a row m of M): L y = m, then L^T w = y
+  if constexpr (RMAX > 0) {
+    subst_rows<RMAX>(M, G, RR, Kn);
+  } else {
+    for (int row = tid; row < Kn; row += nth) {
+      double* m = M + (int64_t)row * RR;
+      for (int r = 0; r < RR; ++r) {
+        double sacc = 0.0;
+        for (int k = 0; k < r; ++k) sacc += G[r * RR + k] * m[k];
+        m[r] = (m[r] - sacc) / G[r * RR + r];
+      }
+      for (int r = RR - 1; r >= 0; --r) {
+        double sacc = 0.0;
+        for (int k = r + 1; k < RR; ++k) sacc += G[k * RR + r] * m[k];
+        m[r] = (m[r] - sacc) / G[r * RR + r];
+      }
     }
   }
   __syncthreads();
@@ -269,38 +456,62 @@ __global__ __launch_bounds__(1024) void als_solve2_kernel(AlsSolveArgs g) {
 }
 
 // ---------------------------------------------------------------------------------------
-size_t als2_accum_lds(int Kn, int RR) { return (size_t)(kA2TJ * RR + (Kn + RR) * kA2TJ) * sizeof(double); }
-size_t als2_solve_lds(int Kn, int RR) { return (size_t)(Kn * RR + RR * RR) * sizeof(double); }
+static int64_t zlds_words(int64_t ztotal) { return (ztotal + 1) / 2 * 2; }
+constexpr int64_t kZldsMax = 6144;  // cores staged in LDS up to 48 KB (6 loads per thread)
 
-bool als2_supported(int Kn, int RR) {
-  return Kn <= 64 && (int64_t)Kn * RR + (int64_t)RR * RR <= (int64_t)kA2Threads * kA2Acc &&
-         als2_accum_lds(Kn, RR) <= 150 * 1024 && als2_solve_lds(Kn, RR) <= 150 * 1024;
+static int accum_tj(int gram_direct) { return gram_direct ? 32 : 128; }
+
+size_t als2_accum_lds(int Kn, int RR, int64_t ztotal, int gram_direct) {
+  const int TJ = accum_tj(gram_direct);
+  const int64_t z = ztotal <= kZldsMax ? zlds_words(ztotal) : 0;
+  return (size_t)(z + TJ * RR + (Kn + (gram_direct ? RR : 0)) * TJ) * sizeof(double);
+}
+size_t als2_solve_lds(int Kn, int RR, int tsz, int gram_direct, int64_t ztotal) {
+  return (size_t)(Kn * RR + RR * RR + (gram_direct ? 0 : 3 * tsz + ztotal)) * sizeof(double);
 }
 
-int64_t als2_grid(int64_t J) {
-  const int64_t ntiles = (J + kA2TJ - 1) / kA2TJ;
-  int64_t g = ntiles / 4;
+bool als2_supported(int Kn, int RR, int Rb, int64_t J, int64_t ztotal, int gram_direct, int tsz) {
+  const int64_t nout = (int64_t)Kn * RR + (gram_direct ? (int64_t)RR * RR : 0);
+  return Kn <= 64 && J < (1LL << 31) &&
+         nout <= 16LL * kA2Threads &&
+         als2_accum_lds(Kn, RR, ztotal, gram_direct) <= 150 * 1024 &&
+         als2_solve_lds(Kn, RR, tsz, gram_direct, ztotal) <= 150 * 1024;
+}
+
+int64_t als2_grid(int64_t J, int gram_direct) {
+  const int TJ = accum_tj(gram_direct);
+  const int64_t ntiles = (J + TJ - 1) / TJ;
+  int64_t g = gram_direct ? ntiles / 4 : ntiles;
   if (g < 1) g = 1;
-  if (g > 64) g = 64;
+  if (g > 32) g = 32;
   const int64_t per = (ntiles + g - 1) / g;
   return (ntiles + per - 1) / per;
 }
 
-template <int RM>
+template <int RM, int TJ>
 static const void* accum_fn(int nq) {
-  if (nq <= 8) return (const void*)als_accum_kernel<RM, 8>;
-  if (nq <= 16) return (const void*)als_accum_kernel<RM, 16>;
-  if (nq <= 32) return (const void*)als_accum_kernel<RM, 32>;
-  return (const void*)als_accum_kernel<RM, 64>;
+  if (nq <= 1) return (const void*)als_accum_kernel<RM, 1, TJ>;
+  if (nq <= 2) return (const void*)als_accum_kernel<RM, 2, TJ>;
+  if (nq <= 4) return (const void*)als_accum_kernel<RM, 4, TJ>;
+  if (nq <= 8) return (const void*)als_accum_kernel<RM, 8, TJ>;
+  return (const void*)als_accum_kernel<RM, 16, TJ>;
+}
+
+template <int TJ>
+static const void* accum_pick(int rmax, int nq) {
+  return rmax <= 8 ? accum_fn<8, TJ>(nq) : rmax <= 16 ? accum_fn<16, TJ>(nq)
+                                                      : accum_fn<RTR_MAX_RANK, TJ>(nq);
 }
 
 hipError_t launch_als_accum(AlsArgs2 g, int64_t grid, int rmax, hipStream_t s) {
-  const int64_t ntiles = (g.J + kA2TJ - 1) / kA2TJ;
+  const int TJ = accum_tj(g.gram_direct);
+  const int64_t ntiles = (g.J + TJ - 1) / TJ;
   g.tiles_per_wg = (ntiles + grid - 1) / grid;
-  const size_t lds = als2_accum_lds(g.Kn, g.RR);
-  const int nout = g.Kn * g.RR + g.RR * g.RR;
+  g.zlds = g.ztotal <= kZldsMax;
+  const size_t lds = als2_accum_lds(g.Kn, g.RR, g.ztotal, g.gram_direct);
+  const int nout = g.Kn * g.RR + (g.gram_direct ? g.RR * g.RR : 0);
   const int nq = (nout + kA2Threads - 1) / kA2Threads;
-  const void* fn = rmax <= 8 ? accum_fn<8>(nq) : rmax <= 16 ? accum_fn<16>(nq) : accum_fn<RTR_MAX_RANK>(nq);
+  const void* fn = g.gram_direct ? accum_pick<32>(rmax, nq) : accum_pick<128>(rmax, nq);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   prof_begin("als_accum", s);
@@ -312,13 +523,16 @@ hipError_t launch_als_accum(AlsArgs2 g, int64_t grid, int rmax, hipStream_t s) {
 }
 
 hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s) {
-  const size_t lds = als2_solve_lds(g.Kn, g.RR);
-  hipError_t e = hipFuncSetAttribute((const void*)als_solve2_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const size_t lds = als2_solve_lds(g.Kn, g.RR, g.tsz, g.gram_direct, g.ztotal);
+  const void* fn = g.RR <= 16 ? (const void*)als_solve2_kernel<16>
+                 : g.RR <= 36 ? (const void*)als_solve2_kernel<36>
+                 : g.RR <= 64 ? (const void*)als_solve2_kernel<64>
+                              : (const void*)als_solve2_kernel<0>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   prof_begin("als_solve", s);
   void* args[] = {&g};
-  e = hipLaunchKernel((const void*)als_solve2_kernel, dim3(1), dim3(1024), args, lds, s);
+  e = hipLaunchKernel(fn, dim3(1), dim3(512), args, lds, s);
   prof_end(s);
   if (e != hipSuccess) return e;
   return hipGetLastError();

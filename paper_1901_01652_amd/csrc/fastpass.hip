@@ -192,17 +192,26 @@ __global__ __launch_bounds__(kFpThreads, 2) void mode_pass_kernel(PassArgs p) {
   auto draw = [&](int64_t t) {
     const int64_t j0 = t * kFpTJ;
     const int64_t e0 = j0 * K;
-    const int64_t e1 = e0 + (int64_t)kFpTJ * K;
-    for (int64_t c = (e0 >> 2) + tid; c <= ((e1 - 1) >> 2); c += kFpThreads) {
+    const int span = kFpTJ * K;  // stream elements of the tile, < 2^12
+    const int jvalid = (int)min((int64_t)kFpTJ, p.J - j0);
+    const int64_t c0 = e0 >> 2;
+    const int off = (int)(e0 - 4 * c0);  // position of e0 inside its call (0..3)
+    const int ncalls = (off + span + 3) >> 2;
+    for (int ci = tid; ci < ncalls; ci += kFpThreads) {
       float z[4];
-      normals4(p.seed, p.stream, p.tid, (uint64_t)c, z);
+      normals4(p.seed, p.stream, p.tid, (uint64_t)(c0 + ci), z);
+      const int rel = 4 * ci - off;        // offset of lane 0 from e0 (negative only for ci = 0)
+      const int l0 = rel < 0 ? -rel : 0;   // first lane inside the tile
+      int jl = (rel + l0) / K;
+      int k = (rel + l0) - jl * K;
 #pragma unroll
       for (int l = 0; l < 4; ++l) {
-        const int64_t e = 4 * c + l;
-        if (e >= e0 && e < e1) {
-          const int64_t rel = e - e0;
-          const int jl = (int)(rel / K), k = (int)(rel % K);
-          Ot[k * ldT + jl] = Mma<BF>::cvt((j0 + jl < p.J) ? z[l] : 0.f);
+        if (l >= l0) {
+          if (rel + l < span) Ot[k * ldT + jl] = Mma<BF>::cvt(jl < jvalid ? z[l] : 0.f);
+          if (++k == K) {
+            k = 0;
+            ++jl;
+          }
         }
       }
     }

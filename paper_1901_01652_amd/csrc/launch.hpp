@@ -127,14 +127,24 @@ struct AlsArgs2 {
   int chRb[8];
   int64_t chOff[8];      // offsets of those cores in Z
   int64_t zoffN;         // offset of core n in Z
-  int mode;              // bit 0: accumulate M and Gram; bit 1: residual with core n
+  int mode;              // bit 0: accumulate M; bit 1: residual with core n
+  int gram_direct;       // 1: Gram = B^T B accumulated here; 0: formed in the solve
+  int64_t ztotal;        // packed core count (staged in LDS when zlds)
+  int zlds;
   int64_t tiles_per_wg;
-  double* part;          // [grid][Kn*RR + RR*RR + 1]
+  double* part;          // [grid][nout + 1], nout = Kn*RR (+ RR*RR if gram_direct)
   const int* done;
 };
 struct AlsSolveArgs {
   const double* part;
-  int nparts, Kn, RR, Rb;
+  int nparts, Kn, RR, Rb, Ra;
+  int gram_direct;
+  int N, n;
+  const double* Z;        // packed cores (transfer-matrix Gram)
+  int64_t zoff[8];
+  int Kc[8], Rc[8];       // dims of the cores and ranks R_1..R_N
+  int tsz;                // entries of one transfer-matrix buffer (max R^4)
+  int64_t ztotal;         // packed core count
   double* Zn;
   unsigned* status;
   int* done;
@@ -145,8 +155,8 @@ struct AlsSolveArgs {
   int* sweeps_run;
   double tol;
 };
-bool als2_supported(int Kn, int RR);
-int64_t als2_grid(int64_t J);
+bool als2_supported(int Kn, int RR, int Rb, int64_t J, int64_t ztotal, int gram_direct, int tsz);
+int64_t als2_grid(int64_t J, int gram_direct);
 hipError_t launch_als_accum(AlsArgs2 g, int64_t grid, int rmax, hipStream_t s);
 hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s);
 

@@ -511,14 +511,19 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
     noutmax = std::max(noutmax, g.Kn * g.RR + g.RR * g.RR);
     chunkmax = std::max(chunkmax, rtr::als_chunks(g));
   }
-  bool use2 = true;
-  int64_t grid2max = 1;
-  for (int n = 0; n < order; ++n) {
-    use2 = use2 && rtr::als2_supported(geo[n].Kn, geo[n].RR);
-    grid2max = std::max(grid2max, rtr::als2_grid(geo[n].J));
-  }
   int rmax = 0;
   for (int n = 0; n < order; ++n) rmax = std::max(rmax, (int)R[n]);
+  // Gram from transfer matrices when every rank is small (R^4 buffers in LDS)
+  // (the solve stages every core in LDS: at most 6 x 1024 values)
+  const int gram_direct = (rmax > 7 || zoff[order] > 6144) ? 1 : 0;
+  const int tsz = rmax * rmax * rmax * rmax;
+  bool use2 = total < (1LL << 31);
+  int64_t grid2max = 1;
+  for (int n = 0; n < order; ++n) {
+    use2 = use2 && rtr::als2_supported(geo[n].Kn, geo[n].RR, geo[n].Rb, geo[n].J,
+                                       (int64_t)zoff[order], gram_direct, tsz);
+    grid2max = std::max(grid2max, rtr::als2_grid(geo[n].J, gram_direct));
+  }
   Carve plan(nullptr);
   plan.take<double>((size_t)Jmax * RRmax);
   plan.take<double>((size_t)std::max(chunkmax, grid2max) * (noutmax + 1));
@@ -566,6 +571,8 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
       a.strideN = g.strideN;
       a.zoffN = (int64_t)zoff[n];
       a.mode = mode;
+      a.gram_direct = gram_direct;
+      a.ztotal = (int64_t)zoff[order];
       a.part = part;
       a.done = done;
       return a;
@@ -578,6 +585,18 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
       a.Kn = g.Kn;
       a.RR = g.RR;
       a.Rb = g.Rb;
+      a.Ra = g.Ra;
+      a.gram_direct = gram_direct;
+      a.N = order;
+      a.n = n;
+      a.Z = Z;
+      for (int m = 0; m < order; ++m) {
+        a.zoff[m] = (int64_t)zoff[m];
+        a.Kc[m] = Kp[m];
+        a.Rc[m] = R[m];
+      }
+      a.tsz = tsz;
+      a.ztotal = (int64_t)zoff[order];
       a.Zn = Z + zoff[n];
       a.status = h->status;
       a.done = done;
@@ -592,12 +611,12 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
     for (int sw = 0; sw < opts->max_sweeps; ++sw) {
       for (int n = 0; n < order; ++n) {
         const bool rep = (n == 0 && sw > 0);
-        const int64_t grid = rtr::als2_grid(geo[n].J);
+        const int64_t grid = rtr::als2_grid(geo[n].J, gram_direct);
         HIP_TRY(rtr::launch_als_accum(args_for(n, 1 | (rep ? 2 : 0)), grid, rmax, s), "als_accum");
         HIP_TRY(rtr::launch_als_solve2(solve_for(n, grid, rep ? sw - 1 : -1, 0), s), "als_solve");
       }
     }
-    const int64_t grid = rtr::als2_grid(geo[0].J);
+    const int64_t grid = rtr::als2_grid(geo[0].J, gram_direct);
     HIP_TRY(rtr::launch_als_accum(args_for(0, 2), grid, rmax, s), "als_accum");
     HIP_TRY(rtr::launch_als_solve2(solve_for(0, grid, opts->max_sweeps - 1, 1), s), "als_solve");
     return RTR_OK;
