@@ -1,90 +1,95 @@
 // TR-ALS (Alg. 1 step 9) with two kernels per core update.
 //
-// als_accum   columns j of P_<n> in tiles of 32: each tile's subchain rows
-//             B[j, a*R_{n+1} + b] = S_j[b, a] are formed in LDS from the current cores
-//             (one row b of S_j per thread, a vector-matrix product per core), then
-//             M += P_<n>[:, tile] B_tile and Gram += B_tile^T B_tile accumulate in
-//             registers.  Optionally the same tile also gives ||P - Psi(Z)||^2 with the
-//             current core n (Psi_<n> = Z_{n,(2)} B^T): the first update of a sweep reports
-//             the error of the sweep before it at no extra pass.
-// als_solve   one work-group: fixed-order sum of the partials into LDS, FP64 Cholesky of
-//             the Gram matrix (one wavefront when R_n R_{n+1} <= 64), forward and back
-//             substitution for every row of M (16 lanes per right-hand side), new core.
-//             It also closes the previous sweep: error = sqrt(residual / ||P||^2), the
-//             stopping test, and the device flag that turns every later kernel into a no-op.
+// Core n is the least-squares solution of Eq. (2) restricted to P:
+//   P_<n> ~ Z_{n,(2)} B^T,  B[j, a*R_{n+1} + b] = S_j[b, a],
+//   S_j = Z_{n+1}(i_{n+1}) ... Z_N(i_N) Z_1(i_1) ... Z_{n-1}(i_{n-1}),
+// through the normal equations Gram * Z_{n,(2)}^T = M^T with M = P_<n> B, Gram = B^T B.
+//
+// als_accum  one tile of TJ columns j per pass: the tile's subchain rows are formed in LDS
+//            (one row b of S_j per thread: the first slice row is copied, the other cores
+//            are vector-matrix products), then M += P_<n>[:, tile] B_tile (and B^T B when the
+//            Gram is accumulated directly) on the FP64 matrix cores.  Optionally the same
+//            tile gives ||P - Psi(Z)||^2 with the current core n, so the first update of a
+//            sweep reports the error of the sweep before it without another pass.
+// als_solve  one work-group: fixed-order sum of the partials; Gram from transfer matrices
+//            E_m = sum_i Z_m(i) (x) Z_m(i) multiplied around the ring (FP64 matrix cores)
+//            when every rank is small; FP64 Cholesky (rows in lane registers, each column
+//            passed through LDS once); forward and back substitution for every row of M;
+//            the new core.  It also closes the previous sweep (error, stopping test, and
+//            the device flag that turns every later kernel of the decomposition into a no-op).
+#include <algorithm>
+
 #include "common.hpp"
 #include "launch.hpp"
+#include "mfma.hpp"
 
 namespace rtr {
 
-constexpr int kA2TJ = 32;
+constexpr int kAcThreads = 1024;  // 16 wavefronts
+constexpr int kAcTilesMax = 8;    // 16x16 output tiles per wavefront, at most
+constexpr int64_t kZldsMax = 6144;
 
-// Orders the LDS accesses of one wavefront (the lanes of a wave run in lockstep).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-constexpr int kA2Threads = 1024;
 
-// Outputs of the per-column accumulation: [M (Kn x RR); Gram (RR x RR) if direct], as the
-// product L B_tile with L = [P_<n>[:, tile]; B_tile^T].  Thread t owns outputs t + 1024 q.
-// TJ columns per tile: 128 when the Gram comes from transfer matrices (every thread then
-// forms a subchain row), 32 when the Gram is accumulated here.
-template <int RM, int NQ, int TJ>
-__global__ __launch_bounds__(kA2Threads) void als_accum_kernel(AlsArgs2 g) {
+static __host__ __device__ inline int pad16(int v) { return (v + 15) / 16 * 16; }
+static __host__ __device__ inline int64_t zwords(int64_t z) { return (z + 1) / 2 * 2; }
+
+// ---------------------------------------------------------------------------------------
+template <int RM, int TJ, int kAcTiles>
+__global__ __launch_bounds__(kAcThreads) void als_accum_kernel(AlsArgs2 g) {
   extern __shared__ __align__(16) double sm[];
   const int RR = g.RR, Kn = g.Kn, Ra = g.Ra, Rb = g.Rb;
-  double* Zs = sm;                                          // packed cores (zlds)
-  double* Bs = sm + (g.zlds ? (g.ztotal + 1) / 2 * 2 : 0);  // [TJ][RR]
-  double* Ls = Bs + TJ * RR;                                // [Kn + RR?][TJ]
+  const int NT = pad16(RR) / 16, MT = pad16(Kn) / 16;
+  const int ldB = pad16(RR) + 1, ldL = TJ + 1;
+  double* Zs = sm;
+  double* Bs = sm + (g.zlds ? zwords(g.ztotal) : 0);  // [TJ][ldB]
+  double* Ls = Bs + TJ * ldB;                          // [pad16(Kn)][ldL]
   const double* Zsrc = g.zlds ? Zs : g.Z;
   __shared__ double red[32];
-  const int nM = Kn * RR;
-  const int nout = nM + (g.gram_direct ? RR * RR : 0);
-  const bool accum = g.mode & 1, resid = g.mode & 2;
-  const int tid = threadIdx.x;
-  if (g.zlds) {  // cores: all loads issued before any store (at most 6 per thread)
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (g.zlds) {  // cores: every load issued before any store
     double zt[6];
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
-      const int64_t x = tid + (int64_t)e * kA2Threads;
+      const int64_t x = tid + (int64_t)e * kAcThreads;
       zt[e] = x < g.ztotal ? g.Z[x] : 0.0;
     }
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
-      const int64_t x = tid + (int64_t)e * kA2Threads;
+      const int64_t x = tid + (int64_t)e * kAcThreads;
       if (x < g.ztotal) Zs[x] = zt[e];
     }
   }
+  for (int x = tid; x < TJ * ldB; x += kAcThreads) Bs[x] = 0.0;  // padding columns stay 0
   if (*g.done) return;
-  double acc[NQ];
-  int rowoff[NQ], colidx[NQ];
+  const int nM = Kn * RR;
+  const int ntM = MT * NT, ntot = ntM + (g.gram_direct ? NT * NT : 0);
+  const bool accum = g.mode & 1, resid = g.mode & 2;
+  f64x4 acc[kAcTiles];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    acc[q] = 0.0;
-    const int o = tid + q * kA2Threads;
-    rowoff[q] = (o < nout) ? (o / RR) * TJ : -1;
-    colidx[q] = o % RR;
-  }
+  for (int s = 0; s < kAcTiles; ++s) acc[s] = f64x4{0.0, 0.0, 0.0, 0.0};
   double rsum = 0.0;
   const int64_t ntiles = (g.J + TJ - 1) / TJ;
   const int64_t t0 = (int64_t)blockIdx.x * g.tiles_per_wg;
   const int64_t t1 = min(ntiles, t0 + g.tiles_per_wg);
-  __syncthreads();
   for (int64_t t = t0; t < t1; ++t) {
     const int j0 = (int)(t * TJ);
     const int jn = (int)min((int64_t)TJ, g.J - j0);
-    // P_<n>[:, tile] (column bases in int32: P has < 2^31 entries); all loads issued first
+    __syncthreads();
+    // P_<n>[:, tile] into Ls (rows padded to a multiple of 16 with zeros)
     {
-      constexpr int kPer = (64 * TJ + kA2Threads - 1) / kA2Threads;
+      constexpr int kPer = (64 * TJ + kAcThreads - 1) / kAcThreads;
       double pv[kPer];
 #pragma unroll
       for (int e = 0; e < kPer; ++e) {
-        const int x = tid + e * kA2Threads;
+        const int x = tid + e * kAcThreads;
         const int i = x / TJ, jj = x % TJ;
         pv[e] = 0.0;
-        if (x < Kn * TJ && jj < jn) {
+        if (i < Kn && jj < jn) {
           int rem = j0 + jj, base = 0;
 #pragma unroll
           for (int u = 6; u >= 0; --u) {
@@ -100,16 +105,17 @@ __global__ __launch_bounds__(kA2Threads) void als_accum_kernel(AlsArgs2 g) {
       }
 #pragma unroll
       for (int e = 0; e < kPer; ++e) {
-        const int x = tid + e * kA2Threads;
-        if (x < Kn * TJ) Ls[x] = pv[e];
+        const int x = tid + e * kAcThreads;
+        const int i = x / TJ, jj = x % TJ;
+        if (i < MT * 16) Ls[i * ldL + jj] = pv[e];
       }
     }
     // subchain rows: thread (jl, b) forms row b of S_j
-    for (int x = tid; x < TJ * Rb; x += kA2Threads) {
+    for (int x = tid; x < TJ * Rb; x += kAcThreads) {
       const int jl = x / Rb, b = x % Rb;
       double v[RM], w[RM];
 #pragma unroll
-      for (int a = 0; a < RM; ++a) v[a] = (jl < jn && a == b) ? 1.0 : 0.0;
+      for (int a = 0; a < RM; ++a) v[a] = 0.0;
       if (jl < jn) {
         int rem = j0 + jl;
         int idx[7];
@@ -120,9 +126,16 @@ __global__ __launch_bounds__(kA2Threads) void als_accum_kernel(AlsArgs2 g) {
             rem /= g.chI[u];
           }
         }
-        int cur = Rb;
+        // first core: row b of its slice
+        {
+          const int cRb = g.chRb[0];
+          const double* G0 = Zsrc + g.chOff[0] + ((int64_t)b * g.chI[0] + idx[0]) * cRb;
 #pragma unroll
-        for (int u = 0; u < 7; ++u) {
+          for (int c = 0; c < RM; ++c) v[c] = c < cRb ? G0[c] : 0.0;
+        }
+        int cur = g.chRb[0];
+#pragma unroll
+        for (int u = 1; u < 7; ++u) {
           if (u < g.N - 1) {
             const int cRb = g.chRb[u];
             const double* G = Zsrc + g.chOff[u] + (int64_t)idx[u] * cRb;
@@ -146,163 +159,168 @@ __global__ __launch_bounds__(kA2Threads) void als_accum_kernel(AlsArgs2 g) {
         }
       }
 #pragma unroll
-      for (int a = 0; a < RM; ++a) {
-        if (a < Ra) {
-          const int r = a * Rb + b;
-          Bs[jl * RR + r] = v[a];
-          if (g.gram_direct) Ls[(Kn + r) * TJ + jl] = v[a];
-        }
-      }
+      for (int a = 0; a < RM; ++a)
+        if (a < Ra) Bs[jl * ldB + a * Rb + b] = v[a];
     }
     __syncthreads();
     if (accum) {
-#pragma unroll 8
-      for (int jj = 0; jj < TJ; ++jj) {
+      const int r16 = lane & 15, g4 = lane >> 4;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-          if (rowoff[q] >= 0) acc[q] += Ls[rowoff[q] + jj] * Bs[jj * RR + colidx[q]];
+      for (int s = 0; s < kAcTiles; ++s) {
+        const int q = wid + 16 * s;
+        if (q < ntot) {
+          const double* ap;
+          int ast;  // A(m, k) = ap[k * ast] for this lane's row m
+          int nt;
+          if (q < ntM) {
+            const int mt = q / NT;
+            nt = q % NT;
+            ap = Ls + (mt * 16 + r16) * ldL + g4;  // A = P tile (rows i, contraction j)
+            ast = 1;
+          } else {
+            const int qq = q - ntM;
+            const int mt = qq / NT;
+            nt = qq % NT;
+            ap = Bs + g4 * ldB + mt * 16 + r16;  // A = B^T (rows r1, contraction j)
+            ast = ldB;
+          }
+          const double* bp = Bs + g4 * ldB + nt * 16 + r16;
+          f64x4 c = acc[s];
+#pragma unroll 8
+          for (int k0 = 0; k0 < TJ; k0 += 4) c = mma_f64(ap[k0 * ast], bp[k0 * ldB], c);
+          acc[s] = c;
+        }
       }
     }
     if (resid) {
       const double* Zn = Zsrc + g.zoffN;
-      for (int x = tid; x < Kn * TJ; x += kA2Threads) {
+      for (int x = tid; x < Kn * TJ; x += kAcThreads) {
         const int i = x / TJ, jj = x % TJ;
         if (jj < jn) {
           double psi = 0.0;
           for (int a = 0; a < Ra; ++a) {
-            const double* zr = Zn + (a * Kn + i) * Rb;
-            const double* br = Bs + jj * RR + a * Rb;
+            const double* zr = Zn + ((int64_t)a * Kn + i) * Rb;
+            const double* br = Bs + jj * ldB + a * Rb;
 #pragma unroll 8
             for (int b = 0; b < Rb; ++b) psi += zr[b] * br[b];
           }
-          const double d = Ls[x] - psi;
+          const double d = Ls[i * ldL + jj] - psi;
           rsum += d * d;
         }
       }
     }
-    __syncthreads();
   }
+  const int nout = nM + (g.gram_direct ? RR * RR : 0);
   double* out = g.part + (int64_t)blockIdx.x * (nout + 1);
   if (accum) {
+    const int r16 = lane & 15, g4 = lane >> 4;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q)
-      if (rowoff[q] >= 0) out[tid + q * kA2Threads] = acc[q];
+    for (int s = 0; s < kAcTiles; ++s) {
+      const int q = wid + 16 * s;
+      if (q < ntot) {
+        const bool isM = q < ntM;
+        const int qq = isM ? q : q - ntM;
+        const int mt = qq / NT, nt = qq % NT;
+        const int col = nt * 16 + r16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = mt * 16 + 4 * r + g4;
+          if (isM) {
+            if (row < Kn && col < RR) out[row * RR + col] = acc[s][r];
+          } else {
+            if (row < RR && col < RR) out[nM + row * RR + col] = acc[s][r];
+          }
+        }
+      }
+    }
   }
   rsum = block_sum(rsum, red);
   if (tid == 0) out[nout] = rsum;
 }
 
-
-// Cholesky of the RR x RR matrix G (LDS, row-major) by one wavefront, RR <= RMAX <= 64:
-// lane i keeps row i in registers (loops unrolled to RMAX so every index is static); at
-// step j the pivot and column j are read from the owning lanes with readlane.  The lower
-// factor is written back to G.  Sets *failed when a pivot is not positive.
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  const int2 p = __builtin_bit_cast(int2, v);
-  int2 q;
-  q.x = __builtin_amdgcn_readlane(p.x, lane);
-  q.y = __builtin_amdgcn_readlane(p.y, lane);
-  return __builtin_bit_cast(double, q);
-}
-
-template <int RMAX>
-__device__ void chol_wave(double* G, int RR, int* failed) {
-  const int i = threadIdx.x & 63;
-  double row[RMAX];
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c) row[c] = (i < RR && c < RR) ? G[i * RR + c] : 0.0;
-  bool ok = true;
-#pragma unroll
-  for (int j = 0; j < RMAX; ++j) {
-    if (j < RR && ok) {
-      const double d = readlane_f64(row[j], j);
-      if (!(d > 0.0)) {
-        ok = false;
-      } else {
-        const double ljj = sqrt(d);
-        const double inv = 1.0 / ljj;
-        if (i == j) row[j] = ljj;
-        if (i > j) row[j] *= inv;
-#pragma unroll
-        for (int k = j + 1; k < RMAX; ++k) {
-          if (k < RR) {
-            const double lkj = readlane_f64(row[j], k);
-            if (i >= k) row[k] -= row[j] * lkj;
-          }
-        }
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);  // keep each step's loads and readlanes local
-  }
-  if (!ok) {
-    if (i == 0) *failed = 1;
-    return;
-  }
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c)
-    if (i < RR && c <= i && c < RR) G[i * RR + c] = row[c];
-}
-
-// Forward and back substitution with the factor L (lower part of G) for every row of M
-// (Kn x RR, LDS): lane/thread r owns row r in registers; L is read with uniform addresses.
-template <int RMAX>
-__device__ void subst_rows(double* M, const double* G, int RR, int Kn) {
-  for (int row = threadIdx.x; row < Kn; row += blockDim.x) {
-    double m[RMAX];
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c) m[c] = c < RR ? M[row * RR + c] : 0.0;
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      if (r < RR) {
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int k = 0; k < r; ++k) {
-          if (k & 1)
-            s1 += G[r * RR + k] * m[k];
-          else
-            s0 += G[r * RR + k] * m[k];
-        }
-        m[r] = (m[r] - (s0 + s1)) / G[r * RR + r];
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int r = RMAX - 1; r >= 0; --r) {
-      if (r < RR) {
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int k = r + 1; k < RMAX; ++k) {
-          if (k < RR) {
-            if (k & 1)
-              s1 += G[k * RR + r] * m[k];
-            else
-              s0 += G[k * RR + r] * m[k];
-          }
-        }
-        m[r] = (m[r] - (s0 + s1)) / G[r * RR + r];
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c)
-      if (c < RR) M[row * RR + c] = m[c];
-  }
-}
-
 // ---------------------------------------------------------------------------------------
-// RMAX: register bound of the Cholesky and substitutions (16, 36, 64); 0 = LDS fallback.
+// C = A B on the FP64 matrix cores for an (Mp x Kp) by (Kp x Np) product, Mp and Np
+// multiples of 16, Kp of 4; A(m, k) = A[m * lda + k * ska], B(k, n) = B[k * ldb + n],
+// C row-major with ldc.  Output tiles are spread over the block's wavefronts.
+__device__ void gemm_f64(const double* A, int lda, int ska, const double* B, int ldb, double* C,
+                         int ldc, int Mp, int Np, int Kp) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int r16 = lane & 15, g4 = lane >> 4;
+  const int MT = Mp / 16, NT = Np / 16;
+  for (int q = wid; q < MT * NT; q += nw) {
+    const int mt = q / NT, nt = q % NT;
+    f64x4 c = {0.0, 0.0, 0.0, 0.0};
+    const double* ap = A + (mt * 16 + r16) * lda + g4 * ska;
+    const double* bp = B + g4 * ldb + nt * 16 + r16;
+    for (int k0 = 0; k0 < Kp; k0 += 4) c = mma_f64(ap[k0 * ska], bp[k0 * ldb], c);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) C[(mt * 16 + 4 * r + g4) * ldc + nt * 16 + r16] = c[r];
+  }
+}
+
+// Gauss-Jordan elimination on the augmented matrix [Gram | M^T] (RR x (RR + Kn)), without
+// pivoting (the Gram is symmetric positive definite, every pivot is a Schur-complement
+// diagonal).  Thread t owns elements e = t + nth*q, q < QMAX, in registers.  Step k: the
+// owners of row k and column k publish them to LDS (double-buffered), one barrier, then every
+// element is updated.  Leaves [I | Gram^-1 M^T]; returns false on a non-positive pivot.
+template <int QMAX>
+__device__ bool gauss_jordan(const double* G, const double* M, double* X, double* rowbuf,
+                             double* colbuf, int RR, int Kn, int* failed) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int W = RR + Kn, ne = RR * W;
+  double a[QMAX];
+  int rr[QMAX], cc[QMAX];
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    const int e = tid + nth * q;
+    rr[q] = e < ne ? e / W : -1;
+    cc[q] = e % W;
+    a[q] = 0.0;
+    if (e < ne) a[q] = cc[q] < RR ? G[rr[q] * RR + cc[q]] : M[(cc[q] - RR) * RR + rr[q]];
+  }
+  for (int k = 0; k < RR; ++k) {
+    double* rb = rowbuf + (k & 1) * 256;
+    double* cb = colbuf + (k & 1) * 256;
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      if (rr[q] == k) rb[cc[q]] = a[q];
+      if (cc[q] == k && rr[q] >= 0) cb[rr[q]] = a[q];
+    }
+    __syncthreads();
+    const double piv = rb[k];
+    if (!(piv > 0.0)) {
+      if (tid == 0) *failed = 1;
+      return false;
+    }
+    const double inv = 1.0 / piv;
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      if (rr[q] >= 0) {
+        const double rk = rb[cc[q]] * inv;  // new row k entry
+        a[q] = (rr[q] == k) ? rk : a[q] - cb[rr[q]] * rk;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q)
+    if (rr[q] >= 0 && cc[q] >= RR) X[rr[q] * Kn + (cc[q] - RR)] = a[q];
+  return true;
+}
+
 template <int RMAX>
 __global__ __launch_bounds__(512) void als_solve2_kernel(AlsSolveArgs g) {
   if (*g.done) return;
   extern __shared__ __align__(16) double sm[];
-  const int RR = g.RR, Kn = g.Kn, nM = Kn * RR, nout = nM + RR * RR;
-  double* M = sm;        // Kn x RR, overwritten by the solution rows
-  double* G = sm + nM;   // RR x RR, lower Cholesky factor in place
+  const int RR = g.RR, Kn = g.Kn, nM = Kn * RR;
+  double* M = sm;               // Kn x RR, overwritten by the new core rows
+  double* G = sm + nM;          // RR x RR, lower Cholesky factor in place
+  double* invd = G + RR * RR;   // RR
+  double* cvec = invd + RR;     // 64
+  double* xt = cvec + 64 + 1024;  // transfer-matrix workspace / Gauss-Jordan solution
   __shared__ double red[16];
   __shared__ int failed;
   const int tid = threadIdx.x, nth = blockDim.x;
-  // close the previous sweep: its error was accumulated by the partials of this update
-  const int nstore = g.gram_direct ? nout : nM;  // partial record length (+1 residual)
+  const int nstore = nM + (g.gram_direct ? RR * RR : 0);  // partial record length (+1)
   if (g.report_sweep >= 0) {
     double s = 0.0;
     for (int c = tid; c < g.nparts; c += nth) s += g.part[(int64_t)c * (nstore + 1) + nstore];
@@ -317,13 +335,13 @@ __global__ __launch_bounds__(512) void als_solve2_kernel(AlsSolveArgs g) {
     __syncthreads();
     if (*g.done || g.report_only) return;
   }
-  const int nred = g.gram_direct ? nout : nM;  // outputs summed from the partials
-  for (int o = tid; o < nred; o += nth) {
+  // fixed-order sum of the partials, sixteen loads in flight
+  for (int o = tid; o < nstore; o += nth) {
     const double* src = g.part + o;
-    const int64_t st = nred + 1;
+    const int64_t st = nstore + 1;
     double s = 0.0;
     int c = 0;
-    for (; c + 16 <= g.nparts; c += 16) {  // sixteen loads in flight, summed in order
+    for (; c + 16 <= g.nparts; c += 16) {
       double v[16];
 #pragma unroll
       for (int e = 0; e < 16; ++e) v[e] = src[(c + e) * st];
@@ -336,12 +354,14 @@ __global__ __launch_bounds__(512) void als_solve2_kernel(AlsSolveArgs g) {
   if (tid == 0) failed = 0;
   if (!g.gram_direct) {
     // Gram from transfer matrices: sum_j S_j (x) S_j = E_{n+1} E_{n+2} ... E_{n-1},
-    // E_m[(p,p'),(q,q')] = sum_i Z_m[p,i,q] Z_m[p',i,q']; then Gram[(a,b),(a',b')] is the
-    // entry [(b,b'),(a,a')] of that product.
-    double* Tm = sm + nout;            // running product, R_{n+1}^2 x R_cur^2
-    double* Em = Tm + g.tsz;           // next transfer matrix
-    double* Tn = Em + g.tsz;           // product buffer
-    double* Zs = Tn + g.tsz;           // cores (one batch of loads)
+    // E_m[(p,p'),(q,q')] = sum_i Z_m[p,i,q] Z_m[p',i,q']; entry [(b,b'),(a,a')] of the
+    // product is Gram[(a,b),(a',b')].  Buffers are D x D (D = pad16(max R^2)), zero padded.
+    const int D = g.tdim;
+    double* Tm = xt;
+    double* Em = Tm + D * D;
+    double* Tn = Em + D * D;
+    double* Fz = Tn + D * D;   // Kp x W slice matrix, Kp <= 64
+    double* Zs = Fz + 64 * D;  // cores
     {
       double zt[12];
 #pragma unroll
@@ -355,53 +375,71 @@ __global__ __launch_bounds__(512) void als_solve2_kernel(AlsSolveArgs g) {
         if (x < g.ztotal) Zs[x] = zt[e];
       }
     }
+    for (int x = tid; x < 3 * D * D; x += nth) Tm[x] = 0.0;
     __syncthreads();
     const int Rn1 = g.Rc[(g.n + 1) % g.N];
-    int rcur = Rn1;
     for (int t = 1; t < g.N; ++t) {
       const int m = (g.n + t) % g.N;
       const int Rp = g.Rc[m], Rq = g.Rc[(m + 1) % g.N], Km = g.Kc[m];
+      const int Kp = (Km + 3) / 4 * 4, W = pad16(Rp * Rq);
       const double* Zm = Zs + g.zoff[m];
+      // Fz[i][(p,q)] = Z_m[p,i,q], zero padded
+      for (int x = tid; x < Kp * W; x += nth) {
+        const int i = x / W, c = x % W;
+        const int p = c / Rq, q = c % Rq;
+        Fz[x] = (i < Km && c < Rp * Rq) ? Zm[(p * Km + i) * Rq + q] : 0.0;
+      }
+      __syncthreads();
+      // F = Fz^T Fz (W x W) into Tn, then scattered into the E layout
+      gemm_f64(Fz, 1, W, Fz, W, Tn, D, W, W, Kp);
+      __syncthreads();
       double* dst = (t == 1) ? Tm : Em;
-      const int ne = Rp * Rp * Rq * Rq;
-      for (int x = tid; x < ne; x += nth) {
-        const int col = x % (Rq * Rq), row = x / (Rq * Rq);
-        const int p = row / Rp, pp = row % Rp, q = col / Rq, qq = col % Rq;
-        const double* za = Zm + p * Km * Rq + q;
-        const double* zb = Zm + pp * Km * Rq + qq;
-        double s = 0.0;
-#pragma unroll 8
-        for (int i = 0; i < Km; ++i) s += za[i * Rq] * zb[i * Rq];
-        dst[x] = s;
+      for (int x = tid; x < D * D; x += nth) {  // whole buffer: zero outside the block
+        const int row = x / D, col = x % D;
+        double v = 0.0;
+        if (row < Rp * Rp && col < Rq * Rq) {
+          const int p = row / Rp, pp = row % Rp, q = col / Rq, qq = col % Rq;
+          v = Tn[(p * Rq + q) * D + pp * Rq + qq];
+        }
+        dst[x] = v;
       }
       __syncthreads();
       if (t > 1) {
-        const int nr = Rn1 * Rn1, nk = Rp * Rp, nc = Rq * Rq;
-        for (int x = tid; x < nr * nc; x += nth) {
-          const int r = x / nc, c = x % nc;
-          double s = 0.0;
-#pragma unroll 8
-          for (int k = 0; k < nk; ++k) s += Tm[r * nk + k] * Em[k * nc + c];
-          Tn[x] = s;
+        const int mp = pad16(Rn1 * Rn1), np = pad16(Rq * Rq);
+        gemm_f64(Tm, D, 1, Em, D, Tn, D, mp, np, pad16(Rp * Rp));
+        __syncthreads();
+        for (int x = tid; x < D * D; x += nth) {
+          const int row = x / D, col = x % D;
+          Tm[x] = (row < mp && col < np) ? Tn[x] : 0.0;
         }
         __syncthreads();
-        for (int x = tid; x < nr * nc; x += nth) Tm[x] = Tn[x];
-        __syncthreads();
       }
-      rcur = Rq;
     }
-    (void)rcur;
-    // here rcur == R_n: Tm is R_{n+1}^2 x R_n^2
+    // Tm is R_{n+1}^2 x R_n^2
     const int Rb2 = g.Rb, Ra2 = g.Ra;
     for (int x = tid; x < RR * RR; x += nth) {
-      const int r1 = x / RR, r2 = x % RR;           // (a,b), (a',b')
+      const int r1 = x / RR, r2 = x % RR;
       const int a = r1 / Rb2, b = r1 % Rb2, a2 = r2 / Rb2, b2 = r2 % Rb2;
-      sm[nM + x] = Tm[(b * Rb2 + b2) * (Ra2 * Ra2) + (a * Ra2 + a2)];
+      G[x] = Tm[(b * Rb2 + b2) * D + (a * Ra2 + a2)];
     }
   }
   __syncthreads();
   if constexpr (RMAX > 0) {
-    if (tid < 64) chol_wave<RMAX>(G, RR, &failed);
+    // RMAX here is the number of augmented-matrix elements per thread
+    double* X = xt;                 // RR x Kn solution, reuses the transfer workspace
+    double* rowbuf = cvec + 64;     // 2 x 256
+    double* colbuf = rowbuf + 512;  // 2 x 256
+    if (!gauss_jordan<RMAX>(G, M, X, rowbuf, colbuf, RR, Kn, &failed)) {
+      if (tid == 0) atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
+      return;
+    }
+    __syncthreads();
+    for (int x = tid; x < nM; x += nth) {
+      const int i = x / RR, r = x % RR;
+      const int a = r / g.Rb, b = r % g.Rb;
+      g.Zn[((int64_t)a * Kn + i) * g.Rb + b] = X[r * Kn + i];
+    }
+    return;
   } else {
     for (int j = 0; j < RR; ++j) {
       if (tid == 0) {
@@ -423,110 +461,124 @@ __global__ __launch_bounds__(512) void als_solve2_kernel(AlsSolveArgs g) {
       }
       __syncthreads();
     }
-  }
-  __syncthreads();
-  if (failed) {
-    if (tid == 0) atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
-    return;
-  }
-  // one lane per right-hand side (a row m of M): L y = m, then L^T w = y
-  if constexpr (RMAX > 0) {
-    subst_rows<RMAX>(M, G, RR, Kn);
-  } else {
+    __syncthreads();
+    if (failed) {
+      if (tid == 0) atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
+      return;
+    }
+    for (int r = tid; r < RR; r += nth) invd[r] = 1.0 / G[r * RR + r];
+    __syncthreads();
     for (int row = tid; row < Kn; row += nth) {
       double* m = M + (int64_t)row * RR;
       for (int r = 0; r < RR; ++r) {
         double sacc = 0.0;
         for (int k = 0; k < r; ++k) sacc += G[r * RR + k] * m[k];
-        m[r] = (m[r] - sacc) / G[r * RR + r];
+        m[r] = (m[r] - sacc) * invd[r];
       }
       for (int r = RR - 1; r >= 0; --r) {
         double sacc = 0.0;
         for (int k = r + 1; k < RR; ++k) sacc += G[k * RR + r] * m[k];
-        m[r] = (m[r] - sacc) / G[r * RR + r];
+        m[r] = (m[r] - sacc) * invd[r];
       }
     }
-  }
-  __syncthreads();
-  for (int x = tid; x < nM; x += nth) {
-    const int i = x / RR, r = x % RR;
-    const int a = r / g.Rb, b = r % g.Rb;
-    g.Zn[((int64_t)a * Kn + i) * g.Rb + b] = M[x];
+    __syncthreads();
+    for (int x = tid; x < nM; x += nth) {
+      const int i = x / RR, r = x % RR;
+      const int a = r / g.Rb, b = r % g.Rb;
+      g.Zn[((int64_t)a * Kn + i) * g.Rb + b] = M[x];
+    }
   }
 }
 
 // ---------------------------------------------------------------------------------------
-static int64_t zlds_words(int64_t ztotal) { return (ztotal + 1) / 2 * 2; }
-constexpr int64_t kZldsMax = 6144;  // cores staged in LDS up to 48 KB (6 loads per thread)
-
-static int accum_tj(int gram_direct) { return gram_direct ? 32 : 128; }
-
-size_t als2_accum_lds(int Kn, int RR, int64_t ztotal, int gram_direct) {
-  const int TJ = accum_tj(gram_direct);
-  const int64_t z = ztotal <= kZldsMax ? zlds_words(ztotal) : 0;
-  return (size_t)(z + TJ * RR + (Kn + (gram_direct ? RR : 0)) * TJ) * sizeof(double);
-}
-size_t als2_solve_lds(int Kn, int RR, int tsz, int gram_direct, int64_t ztotal) {
-  return (size_t)(Kn * RR + RR * RR + (gram_direct ? 0 : 3 * tsz + ztotal)) * sizeof(double);
+static int64_t accum_words(int Kn, int RR, int64_t ztotal, int tj) {
+  const int64_t z = ztotal <= kZldsMax ? zwords(ztotal) : 0;
+  return z + (int64_t)tj * (pad16(RR) + 1) + (int64_t)pad16(Kn) * (tj + 1);
 }
 
-bool als2_supported(int Kn, int RR, int Rb, int64_t J, int64_t ztotal, int gram_direct, int tsz) {
-  const int64_t nout = (int64_t)Kn * RR + (gram_direct ? (int64_t)RR * RR : 0);
-  return Kn <= 64 && J < (1LL << 31) &&
-         nout <= 16LL * kA2Threads &&
-         als2_accum_lds(Kn, RR, ztotal, gram_direct) <= 150 * 1024 &&
-         als2_solve_lds(Kn, RR, tsz, gram_direct, ztotal) <= 150 * 1024;
+static int accum_tj(int Kn, int RR, int64_t ztotal) {
+  for (int tj = 128; tj >= 32; tj /= 2)
+    if (accum_words(Kn, RR, ztotal, tj) * 8 <= 150 * 1024) return tj;
+  return 0;
 }
 
-int64_t als2_grid(int64_t J, int gram_direct) {
-  const int TJ = accum_tj(gram_direct);
-  const int64_t ntiles = (J + TJ - 1) / TJ;
-  int64_t g = gram_direct ? ntiles / 4 : ntiles;
-  if (g < 1) g = 1;
-  if (g > 32) g = 32;
-  const int64_t per = (ntiles + g - 1) / g;
+static size_t solve_lds(int Kn, int RR, int gram_direct, int tdim, int64_t ztotal) {
+  int64_t w = (int64_t)Kn * RR + (int64_t)RR * RR + RR + 64 + 1024;  // + row/column buffers
+  int64_t xt = (int64_t)RR * Kn;                                      // Gauss-Jordan solution
+  if (!gram_direct) xt = std::max(xt, 3 * (int64_t)tdim * tdim + 64 * (int64_t)tdim + ztotal);
+  return (size_t)(w + xt) * 8;
+}
+
+int als2_tdim(int rmax) { return pad16(rmax * rmax); }
+
+bool als2_supported(int Kn, int RR, int64_t J, int64_t ztotal, int gram_direct, int tdim,
+                    int maxK) {
+  const int tj = accum_tj(Kn, RR, ztotal);
+  const int NT = pad16(RR) / 16, MT = pad16(Kn) / 16;
+  const int tiles = MT * NT + (gram_direct ? NT * NT : 0);
+  return tj > 0 && Kn <= 64 && J < (1LL << 31) && tiles <= 16 * kAcTilesMax &&
+         solve_lds(Kn, RR, gram_direct, tdim, ztotal) <= 150 * 1024 &&
+         (gram_direct || (ztotal <= 12 * 512 && maxK <= 64));
+}
+
+// Number of partial records the accumulation writes (its grid).
+int64_t als2_parts(int Kn, int RR, int64_t J, int64_t ztotal) {
+  const int tj = accum_tj(Kn, RR, ztotal);
+  const int64_t ntiles = (J + tj - 1) / tj;
+  const int64_t grid = ntiles < 64 ? ntiles : 64;
+  const int64_t per = (ntiles + grid - 1) / grid;
   return (ntiles + per - 1) / per;
 }
 
-template <int RM, int TJ>
-static const void* accum_fn(int nq) {
-  if (nq <= 1) return (const void*)als_accum_kernel<RM, 1, TJ>;
-  if (nq <= 2) return (const void*)als_accum_kernel<RM, 2, TJ>;
-  if (nq <= 4) return (const void*)als_accum_kernel<RM, 4, TJ>;
-  if (nq <= 8) return (const void*)als_accum_kernel<RM, 8, TJ>;
-  return (const void*)als_accum_kernel<RM, 16, TJ>;
+template <int TJ, int NTW>
+static const void* accum_fn(int rmax) {
+  if (rmax <= 4) return (const void*)als_accum_kernel<4, TJ, NTW>;
+  if (rmax <= 8) return (const void*)als_accum_kernel<8, TJ, NTW>;
+  if (rmax <= 16) return (const void*)als_accum_kernel<16, TJ, NTW>;
+  return (const void*)als_accum_kernel<RTR_MAX_RANK, TJ, NTW>;
 }
 
 template <int TJ>
-static const void* accum_pick(int rmax, int nq) {
-  return rmax <= 8 ? accum_fn<8, TJ>(nq) : rmax <= 16 ? accum_fn<16, TJ>(nq)
-                                                      : accum_fn<RTR_MAX_RANK, TJ>(nq);
+static const void* accum_pick(int rmax, int ntw) {
+  if (ntw <= 1) return accum_fn<TJ, 1>(rmax);
+  if (ntw <= 2) return accum_fn<TJ, 2>(rmax);
+  return accum_fn<TJ, kAcTilesMax>(rmax);
 }
 
-hipError_t launch_als_accum(AlsArgs2 g, int64_t grid, int rmax, hipStream_t s) {
-  const int TJ = accum_tj(g.gram_direct);
-  const int64_t ntiles = (g.J + TJ - 1) / TJ;
+hipError_t launch_als_accum(AlsArgs2 g, int rmax, hipStream_t s) {
+  const int tj = accum_tj(g.Kn, g.RR, g.ztotal);
+  const int64_t ntiles = (g.J + tj - 1) / tj;
+  const int64_t grid = als2_parts(g.Kn, g.RR, g.J, g.ztotal);
   g.tiles_per_wg = (ntiles + grid - 1) / grid;
   g.zlds = g.ztotal <= kZldsMax;
-  const size_t lds = als2_accum_lds(g.Kn, g.RR, g.ztotal, g.gram_direct);
-  const int nout = g.Kn * g.RR + (g.gram_direct ? g.RR * g.RR : 0);
-  const int nq = (nout + kA2Threads - 1) / kA2Threads;
-  const void* fn = g.gram_direct ? accum_pick<32>(rmax, nq) : accum_pick<128>(rmax, nq);
+  const size_t lds = (size_t)accum_words(g.Kn, g.RR, g.ztotal, tj) * 8;
+  const int NT = pad16(g.RR) / 16, MT = pad16(g.Kn) / 16;
+  const int ntot = MT * NT + (g.gram_direct ? NT * NT : 0);
+  const int ntw = (ntot + 15) / 16;  // output tiles per wavefront
+  const void* fn = tj == 128 ? accum_pick<128>(rmax, ntw)
+                 : tj == 64  ? accum_pick<64>(rmax, ntw)
+                             : accum_pick<32>(rmax, ntw);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   prof_begin("als_accum", s);
   void* args[] = {&g};
-  e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kA2Threads), args, lds, s);
+  e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kAcThreads), args, lds, s);
   prof_end(s);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
 hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s) {
-  const size_t lds = als2_solve_lds(g.Kn, g.RR, g.tsz, g.gram_direct, g.ztotal);
-  const void* fn = g.RR <= 16 ? (const void*)als_solve2_kernel<16>
-                 : g.RR <= 36 ? (const void*)als_solve2_kernel<36>
-                 : g.RR <= 64 ? (const void*)als_solve2_kernel<64>
+  const size_t lds = solve_lds(g.Kn, g.RR, g.gram_direct, g.tdim, g.ztotal);
+  // Gauss-Jordan path: augmented rows of at most 256 entries (the LDS row/column buffers),
+  // elements spread over 512 threads
+  const int ne = (g.RR + g.Kn <= 256) ? g.RR * (g.RR + g.Kn) : (1 << 30);
+  const void* fn = ne <= 512 ? (const void*)als_solve2_kernel<1>
+                 : ne <= 1024 ? (const void*)als_solve2_kernel<2>
+                 : ne <= 2048 ? (const void*)als_solve2_kernel<4>
+                 : ne <= 4096 ? (const void*)als_solve2_kernel<8>
+                 : ne <= 8192 ? (const void*)als_solve2_kernel<16>
+                 : ne <= 16384 ? (const void*)als_solve2_kernel<32>
                               : (const void*)als_solve2_kernel<0>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

@@ -143,7 +143,7 @@ struct AlsSolveArgs {
   const double* Z;        // packed cores (transfer-matrix Gram)
   int64_t zoff[8];
   int Kc[8], Rc[8];       // dims of the cores and ranks R_1..R_N
-  int tsz;                // entries of one transfer-matrix buffer (max R^4)
+  int tdim;               // transfer-matrix buffers are tdim x tdim (pad16(max R^2))
   int64_t ztotal;         // packed core count
   double* Zn;
   unsigned* status;
@@ -155,9 +155,11 @@ struct AlsSolveArgs {
   int* sweeps_run;
   double tol;
 };
-bool als2_supported(int Kn, int RR, int Rb, int64_t J, int64_t ztotal, int gram_direct, int tsz);
-int64_t als2_grid(int64_t J, int gram_direct);
-hipError_t launch_als_accum(AlsArgs2 g, int64_t grid, int rmax, hipStream_t s);
+int als2_tdim(int rmax);
+bool als2_supported(int Kn, int RR, int64_t J, int64_t ztotal, int gram_direct, int tdim,
+                    int maxK);
+int64_t als2_parts(int Kn, int RR, int64_t J, int64_t ztotal);
+hipError_t launch_als_accum(AlsArgs2 g, int rmax, hipStream_t s);
 hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s);
 
 __device__ __forceinline__ int64_t cyc_base_of(int N, const int* cycK, const int64_t* cycStride,

@@ -55,4 +55,13 @@ struct Mma<false> {
   static __device__ __forceinline__ float cvt(float v) { return v; }
 };
 
+// FP64 matrix cores, v_mfma_f64_16x16x4_f64: lane l supplies A[l & 15][l >> 4] and
+// B[l >> 4][l & 15]; the accumulator holds C[4 r + (l >> 4)][l & 15] for r = 0..3 (rows are
+// interleaved across lane groups, unlike the FP32 and bf16 forms).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4 mma_f64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 }  // namespace rtr

@@ -513,16 +513,19 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
   }
   int rmax = 0;
   for (int n = 0; n < order; ++n) rmax = std::max(rmax, (int)R[n]);
-  // Gram from transfer matrices when every rank is small (R^4 buffers in LDS)
-  // (the solve stages every core in LDS: at most 6 x 1024 values)
-  const int gram_direct = (rmax > 7 || zoff[order] > 6144) ? 1 : 0;
-  const int tsz = rmax * rmax * rmax * rmax;
+  // Gram from transfer matrices when every rank is at most 7 and the cores fit the solve's
+  // LDS staging; otherwise accumulated directly as B^T B
+  int maxK = 0;
+  for (int n = 0; n < order; ++n) maxK = std::max(maxK, (int)Kp[n]);
+  const int gram_direct = (rmax > 7 || zoff[order] > 6144 || maxK > 64) ? 1 : 0;
+  const int tdim = rtr::als2_tdim(rmax);
   bool use2 = total < (1LL << 31);
   int64_t grid2max = 1;
   for (int n = 0; n < order; ++n) {
-    use2 = use2 && rtr::als2_supported(geo[n].Kn, geo[n].RR, geo[n].Rb, geo[n].J,
-                                       (int64_t)zoff[order], gram_direct, tsz);
-    grid2max = std::max(grid2max, rtr::als2_grid(geo[n].J, gram_direct));
+    use2 = use2 && rtr::als2_supported(geo[n].Kn, geo[n].RR, geo[n].J, (int64_t)zoff[order],
+                                       gram_direct, tdim, maxK);
+    grid2max = std::max(grid2max, rtr::als2_parts(geo[n].Kn, geo[n].RR, geo[n].J,
+                                                  (int64_t)zoff[order]));
   }
   Carve plan(nullptr);
   plan.take<double>((size_t)Jmax * RRmax);
@@ -595,7 +598,7 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
         a.Kc[m] = Kp[m];
         a.Rc[m] = R[m];
       }
-      a.tsz = tsz;
+      a.tdim = tdim;
       a.ztotal = (int64_t)zoff[order];
       a.Zn = Z + zoff[n];
       a.status = h->status;
@@ -611,13 +614,13 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
     for (int sw = 0; sw < opts->max_sweeps; ++sw) {
       for (int n = 0; n < order; ++n) {
         const bool rep = (n == 0 && sw > 0);
-        const int64_t grid = rtr::als2_grid(geo[n].J, gram_direct);
-        HIP_TRY(rtr::launch_als_accum(args_for(n, 1 | (rep ? 2 : 0)), grid, rmax, s), "als_accum");
+        const int64_t grid = rtr::als2_parts(geo[n].Kn, geo[n].RR, geo[n].J, (int64_t)zoff[order]);
+        HIP_TRY(rtr::launch_als_accum(args_for(n, 1 | (rep ? 2 : 0)), rmax, s), "als_accum");
         HIP_TRY(rtr::launch_als_solve2(solve_for(n, grid, rep ? sw - 1 : -1, 0), s), "als_solve");
       }
     }
-    const int64_t grid = rtr::als2_grid(geo[0].J, gram_direct);
-    HIP_TRY(rtr::launch_als_accum(args_for(0, 2), grid, rmax, s), "als_accum");
+    const int64_t grid = rtr::als2_parts(geo[0].Kn, geo[0].RR, geo[0].J, (int64_t)zoff[order]);
+    HIP_TRY(rtr::launch_als_accum(args_for(0, 2), rmax, s), "als_accum");
     HIP_TRY(rtr::launch_als_solve2(solve_for(0, grid, opts->max_sweeps - 1, 1), s), "als_solve");
     return RTR_OK;
   }
