@@ -150,6 +150,17 @@ def _trunc_rank(s, delta):
     return len(s)
 
 
+def _svd_fixed_sign(C):
+    """Economy SVD with a fixed sign per singular pair: each left singular vector is
+    negated (with its right partner) unless its entry of largest magnitude (the first such
+    on ties) is positive.  TR-SVD needs this because the first rank is split over both
+    ends of the ring, which makes the result depend on these signs."""
+    U, s, Vt = np.linalg.svd(C, full_matrices=False)
+    idx = np.argmax(np.abs(U), axis=0)          # first index of the largest |entry|
+    sign = np.where(U[idx, np.arange(U.shape[1])] < 0, -1.0, 1.0)
+    return U * sign, s, Vt * sign[:, None]
+
+
 def tr_svd(P, eps):
     """Alg. 1 step 9 with TR-SVD (sequential truncated SVDs, Zhao et al. 2016):
     per-step budget delta = eps ||P|| / sqrt(N), the first step sqrt(2) delta; the first
@@ -157,13 +168,15 @@ def tr_svd(P, eps):
     closes the ring through R_1.  Returns (cores, ranks [R_1..R_N]).
 
     Parity: pinned by the error bound ||P - Psi(Z)|| <= eps ||P|| and per-step minimality;
-    the exact cores are partly unpinned (the rank split is a reading)."""
+    the exact cores are partly unpinned (the rank split is a reading).  Singular vectors
+    follow the sign rule of ``_svd_fixed_sign`` (a reading: the split first rank makes the
+    later truncations depend on those signs)."""
     shape = P.shape
     N = len(shape)
     nP = frob(P)
     delta = eps * nP / np.sqrt(N)
     C = P.reshape(shape[0], -1)
-    U, s, Vt = np.linalg.svd(C, full_matrices=False)
+    U, s, Vt = _svd_fixed_sign(C)
     r = _trunc_rank(s, np.sqrt(2.0) * delta)
     R1, R2 = _split_rank(r)
     Z = [np.transpose(U[:, :r].reshape(shape[0], R1, R2), (1, 0, 2))]
@@ -173,7 +186,7 @@ def tr_svd(P, eps):
     for k in range(1, N - 1):
         Rk = ranks[-1]
         C = C.reshape(Rk * shape[k], -1)
-        U, s, Vt = np.linalg.svd(C, full_matrices=False)
+        U, s, Vt = _svd_fixed_sign(C)
         r = _trunc_rank(s, delta)
         Z.append(U[:, :r].reshape(Rk, shape[k], r))
         C = s[:r, None] * Vt[:r]

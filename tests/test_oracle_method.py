@@ -230,6 +230,43 @@ def test_tr_svd_error_bound_and_minimal_ranks(eps):
         assert np.sqrt(np.sum(s[r1 - 1:] ** 2)) > d1
 
 
+def test_tr_svd_independent_of_lapack_signs(monkeypatch):
+    """The split first rank makes TR-SVD depend on singular-vector signs; with the fixed
+    sign rule the result is a function of P alone: random sign flips of every SVD that
+    LAPACK returns change nothing, while without the rule they change the error."""
+    rng = np.random.default_rng(31)
+    P = T.tr_full(cores([12, 10, 11], [3, 3, 3], seed=32)) + 0.1 * rng.standard_normal((12, 10, 11))
+    Z, ranks = rtr.tr_svd(P, 0.1)
+    base = T.tr_full(Z)
+    svd = np.linalg.svd
+    flips = np.random.default_rng(33)
+
+    def flipped_svd(C, full_matrices=False):
+        U, s, Vt = svd(C, full_matrices=full_matrices)
+        sg = flips.choice([-1.0, 1.0], size=len(s))
+        return U * sg, s, Vt * sg[:, None]
+
+    monkeypatch.setattr(rtr.np.linalg, "svd", flipped_svd)
+    for _ in range(4):
+        Z2, ranks2 = rtr.tr_svd(P, 0.1)
+        assert ranks2 == ranks
+        np.testing.assert_allclose(T.tr_full(Z2), base, rtol=0, atol=1e-12 * np.abs(base).max())
+    # the dependence the rule removes: flip one pair of the first SVD by hand
+    monkeypatch.setattr(rtr.np.linalg, "svd", svd)
+    C = P.reshape(12, -1)
+    U, s, Vt = rtr._svd_fixed_sign(C)
+    r = ranks[0] * ranks[1]
+    assert ranks[0] > 1 and r > 1
+    U2, Vt2 = U.copy(), Vt.copy()
+    U2[:, 1] *= -1
+    Vt2[1] *= -1
+    C2a = np.transpose((s[:r, None] * Vt[:r]).reshape(ranks[0], ranks[1], -1), (1, 2, 0))
+    C2b = np.transpose((s[:r, None] * Vt2[:r]).reshape(ranks[0], ranks[1], -1), (1, 2, 0))
+    sa = np.linalg.svd(C2a.reshape(ranks[1] * 10, -1), compute_uv=False)
+    sb = np.linalg.svd(C2b.reshape(ranks[1] * 10, -1), compute_uv=False)
+    assert np.max(np.abs(sa - sb)) > 1e-6 * sa[0]
+
+
 def test_tr_svd_exact_for_tr_tensor():
     P = T.tr_full(cores([5, 6, 5, 4], [2, 2, 2, 2], seed=30))
     Z, ranks = rtr.tr_svd(P, 1e-10)
