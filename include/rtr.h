@@ -87,6 +87,8 @@ typedef enum { RTR_METHOD_ALS = 0, RTR_METHOD_SVD = 1 } rtr_method;
 /* Device status word bits (rtr_status_sync). */
 #define RTR_STATUS_CHOLESKY_FAILED 0x1u /* an ALS Gram matrix was not positive definite;
                                            that core update was skipped */
+#define RTR_STATUS_RANK_CAPPED 0x2u     /* TR-SVD: a rank was lowered to its cap, so the
+                                           error bound eps may not hold */
 
 typedef struct rtr_context* rtr_handle;
 
@@ -151,12 +153,37 @@ typedef struct {
  * TR-ALS updates core n by the exact least-squares solution of Eq. (2) restricted to P
  * (normal equations, FP64 Cholesky).  A Gram matrix that is not positive definite sets
  * RTR_STATUS_CHOLESKY_FAILED and leaves that core unchanged.
- * RTR_METHOD_SVD returns RTR_ERR_UNSUPPORTED in this build.
+ * RTR_METHOD_SVD is rejected with RTR_ERR_INVALID_ARG: TR-SVD chooses the ranks, so it has
+ * its own entry point, rtr_decompose_svd.
  */
 rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int32_t* Kp,
                          const int32_t* R, const rtr_decompose_opts* opts,
                          const double* Z_init, double* Z, double* err_trace,
                          int32_t* sweeps_run, void* stream);
+
+/*
+ * Alg. 1 step 9 with TR-SVD (the rTR-SVD variant of Sec. 4): sequential truncated SVDs of
+ * P (TT-SVD style, Zhao et al. 2016) with the ranks chosen from the error bound.
+ *   P, order, Kp  as for rtr_decompose (FP64 device, row-major K'_1 x .. x K'_N)
+ *   Rcap       host, N rank caps, 1 <= Rcap_n <= 512; they size the slots of Z
+ *   eps        > 0: target ||P - Psi(Z)||_F <= eps ||P||_F
+ *   Z          device FP64: N slots of Rcap_n * K'_n * Rcap_{n+1} doubles, in mode order;
+ *              core n is stored packed (R_n, K'_n, R_{n+1}) at the start of its slot
+ *   ranks      device, N int32: the chosen R_1..R_N
+ *   err        device, 1 FP64: ||P - Psi(Z)||_F / ||P||_F, from the discarded singular
+ *              energy (the truncations are orthogonal projections, so this is exact up to
+ *              rounding)
+ * Budget: every truncation keeps the smallest rank whose discarded singular values have
+ * 2-norm <= delta = eps ||P|| / sqrt(N), the first one sqrt(2) delta; the first rank r is
+ * split as R_1 R_2 = r with R_1 <= R_2 and R_2 - R_1 minimal; the last core closes the ring
+ * through R_1.  A rank above its cap is lowered to the cap (the first, to the largest r whose
+ * split fits R_1 <= Rcap_1, R_2 <= Rcap_2) and sets RTR_STATUS_RANK_CAPPED.
+ * Every step diagonalises the Gram matrix of its shorter side; the host bounds these sizes
+ * from the caps and returns RTR_ERR_UNSUPPORTED if one may exceed 512.
+ */
+rtr_status rtr_decompose_svd(rtr_handle h, const double* P, int32_t order, const int32_t* Kp,
+                             const int32_t* Rcap, double eps, double* Z, int32_t* ranks,
+                             double* err, void* stream);
 
 /*
  * Alg. 1 steps 10-12, read as the product over the physical mode: G_n = Z_n x_2 Q_n,

@@ -25,6 +25,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "rtr.h")
 RTR_F64, RTR_F32, RTR_BF16 = 0, 1, 2
 RTR_METHOD_ALS, RTR_METHOD_SVD = 0, 1
 RTR_STATUS_CHOLESKY_FAILED = 0x1
+RTR_STATUS_RANK_CAPPED = 0x2
 MAX_ORDER = 8
 
 _DTYPES = {"f64": RTR_F64, "f32": RTR_F32, "bf16": RTR_BF16}
@@ -55,6 +56,7 @@ def _load():
         "rtr_sketch": [vp, vp, ctypes.c_int, i32, P64, P32, i32, u64, u32, ctypes.c_int, vp, vp],
         "rtr_compress": [vp, vp, ctypes.c_int, i32, P64, P32, vp, ctypes.c_int, vp, vp, vp],
         "rtr_decompose": [vp, vp, i32, P32, P32, ctypes.POINTER(_Opts), vp, vp, vp, vp, vp],
+        "rtr_decompose_svd": [vp, vp, i32, P32, P32, dp, vp, vp, vp, vp],
         "rtr_backproject": [vp, i32, P64, P32, P32, vp, vp, vp, vp],
         "rtr_residual": [vp, vp, ctypes.c_int, i32, P64, P32, vp, vp, vp],
         "rtr_normals": [vp, u64, u32, u32, i64, i64, ctypes.c_int, vp, vp],
@@ -219,6 +221,40 @@ def rtr_decompose(h, P, R, Z_init, max_sweeps, tol=0.0, method="als", eps=0.0, Z
                               _ptr(Z_init), _ptr(Z), _ptr(err_trace), _ptr(sweeps_run),
                               _stream(stream, P.device)))
     return Z, err_trace, sweeps_run
+
+
+def svd_slots(Kp, Rcap):
+    """Slot sizes (doubles) of the TR-SVD core buffer: Rcap_n * K'_n * Rcap_{n+1}."""
+    N = len(Kp)
+    return [int(Rcap[n]) * int(Kp[n]) * int(Rcap[(n + 1) % N]) for n in range(N)]
+
+
+def rtr_decompose_svd(h, P, Rcap, eps, Z=None, ranks=None, err=None, stream=None):
+    """Alg. 1 step 9 with TR-SVD.  Returns the device outputs (Z slots, ranks, err); use
+    ``svd_cores`` to read the cores out."""
+    Kp = list(P.shape)
+    if Z is None:
+        Z = torch.zeros(sum(svd_slots(Kp, Rcap)), dtype=torch.float64, device=P.device)
+    if ranks is None:
+        ranks = torch.zeros(len(Kp), dtype=torch.int32, device=P.device)
+    if err is None:
+        err = torch.zeros(1, dtype=torch.float64, device=P.device)
+    h.check(lib.rtr_decompose_svd(h.ptr, _ptr(P), len(Kp), _i32(Kp), _i32(Rcap), float(eps),
+                                  _ptr(Z), _ptr(ranks), _ptr(err), _stream(stream, P.device)))
+    return Z, ranks, err
+
+
+def svd_cores(Z, ranks, Kp, Rcap):
+    """The cores (R_n, K'_n, R_{n+1}) stored at the start of each TR-SVD slot."""
+    N = len(Kp)
+    R = [int(r) for r in ranks]
+    out, off = [], 0
+    for n, size in enumerate(svd_slots(Kp, Rcap)):
+        shape = (R[n], int(Kp[n]), R[(n + 1) % N])
+        cnt = shape[0] * shape[1] * shape[2]
+        out.append(Z[off:off + cnt].view(*shape))
+        off += size
+    return out
 
 
 def rtr_backproject(h, dims, K, R, Z, Q, G=None, stream=None):

@@ -181,4 +181,25 @@ hipError_t launch_residual(bool f32, const void* X, int64_t IL, int64_t IR, int 
                            const double* L, const double* RtT, double* partial, double* out,
                            hipStream_t s);
 
+// ---- svd.hip --------------------------------------------------------------------------
+constexpr int kSvdMaxDim = 512;  // largest Gram size min(m, n) of a TR-SVD step
+constexpr int kSvdLdsDim = 88;   // Gram sizes up to this are diagonalised in LDS
+struct SvdState {                // device-resident shape and bookkeeping of the sequence
+  int m, n, d, rows, r, capped;
+  int ranks[8];
+  double pn2, delta2, err2;
+};
+struct SvdCaps {
+  int N;
+  int c[8];
+};
+hipError_t launch_svd_init(SvdState* st, const double* pn2, double eps, int N, int m, int n,
+                           hipStream_t s);
+// One truncated-SVD step: C (device dims) -> core written at Z, next matrix at Cn.
+hipError_t launch_svd_step(SvdState* st, const double* C, double* A, double* V, double* W,
+                           double* sv, const SvdCaps& caps, int step, int dmax, double* Z,
+                           double* Cn, int Knext, hipStream_t s);
+hipError_t launch_svd_last(const SvdState* st, const double* C, double* Zlast, int N,
+                           int* ranks_out, double* err_out, unsigned* status, hipStream_t s);
+
 }  // namespace rtr

@@ -457,7 +457,7 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
   Guard guard(h);
   if (!opts) return fail(h, RTR_ERR_INVALID_ARG, "opts is NULL");
   if (opts->method == RTR_METHOD_SVD)
-    return fail(h, RTR_ERR_UNSUPPORTED, "TR-SVD is not available through rtr_decompose yet");
+    return fail(h, RTR_ERR_INVALID_ARG, "TR-SVD chooses the ranks: call rtr_decompose_svd");
   if (opts->method != RTR_METHOD_ALS) return fail(h, RTR_ERR_INVALID_ARG, "unknown method");
   if (order < 2 || order > RTR_MAX_ORDER)
     return fail(h, RTR_ERR_INVALID_ARG, "decomposition needs 2 <= order <= 8");
@@ -649,6 +649,101 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
       }
     }
   }
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+// ---------------------------------------------------------------------------------------
+rtr_status rtr_decompose_svd(rtr_handle h, const double* P, int32_t order, const int32_t* Kp,
+                             const int32_t* Rcap, double eps, double* Z, int32_t* ranks,
+                             double* err, void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if (order < 2 || order > RTR_MAX_ORDER)
+    return fail(h, RTR_ERR_INVALID_ARG, "decomposition needs 2 <= order <= 8");
+  if (!Kp || !Rcap) return fail(h, RTR_ERR_INVALID_ARG, "Kp and Rcap must be host arrays");
+  if (!P || !Z || !ranks || !err)
+    return fail(h, RTR_ERR_INVALID_ARG, "P, Z, ranks, err must be device pointers");
+  if (!(eps > 0.0) || !(eps < 1e300)) return fail(h, RTR_ERR_INVALID_ARG, "eps must be > 0");
+  int64_t total = 1;
+  for (int n = 0; n < order; ++n) {
+    if (Kp[n] < 1) return fail(h, RTR_ERR_INVALID_ARG, "Kp entries must be >= 1");
+    if (Rcap[n] < 1 || Rcap[n] > rtr::kSvdMaxDim)
+      return fail(h, RTR_ERR_INVALID_ARG, "rank caps must be in [1, 512]");
+    total *= Kp[n];
+    if (total > ((int64_t)1 << 31)) return fail(h, RTR_ERR_UNSUPPORTED, "P above 2^31 entries");
+  }
+  // Bounds of the Gram sizes: step 0 has d_0 = min(K_1, prod K / K_1); R_1 <= R_2 and
+  // R_1 R_2 <= d_0; step k >= 1 works on (R_{k+1} K_k) x (K_{k+1} .. K_N R_1) with
+  // R_{k+1} <= min(cap, d_{k-1}).
+  int dmax[RTR_MAX_ORDER];
+  int dall = 0;
+  int64_t rb[RTR_MAX_ORDER];
+  for (int k = 0; k + 1 < order; ++k) {
+    int64_t rest = 1;
+    for (int j = k + 1; j < order; ++j) rest *= Kp[j];
+    int64_t d;
+    if (k == 0) {
+      d = std::min((int64_t)Kp[0], rest);
+      int64_t sq = 1;
+      while ((sq + 1) * (sq + 1) <= d) ++sq;
+      rb[0] = std::min((int64_t)Rcap[0], sq);
+      rb[1] = std::min((int64_t)Rcap[1], d);
+    } else {
+      d = std::min(rb[k] * Kp[k], rest * rb[0]);
+      if (k + 1 < order) rb[k + 1] = std::min((int64_t)Rcap[k + 1], d);
+    }
+    if (d > rtr::kSvdMaxDim)
+      return fail(h, RTR_ERR_UNSUPPORTED,
+                  "TR-SVD step " + std::to_string(k) + " may need a Gram of size " +
+                      std::to_string(d) + " > 512 (lower the rank caps)");
+    dmax[k] = (int)d;
+    dall = std::max(dall, (int)d);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Carve plan(nullptr);
+  plan.take<double>(1024);
+  plan.take<double>(1);
+  plan.take<rtr::SvdState>(1);
+  plan.take<double>((size_t)dall * dall);
+  plan.take<double>((size_t)dall * dall);
+  plan.take<double>((size_t)dall * dall);
+  plan.take<double>(dall);
+  plan.take<double>(total);
+  plan.take<double>(total);
+  st = ensure_ws(h, plan.off);
+  if (st) return st;
+  Carve c(h->ws);
+  double* red = c.take<double>(1024);
+  double* pn2 = c.take<double>(1);
+  rtr::SvdState* state = c.take<rtr::SvdState>(1);
+  double* A = c.take<double>((size_t)dall * dall);
+  double* V = c.take<double>((size_t)dall * dall);
+  double* W = c.take<double>((size_t)dall * dall);
+  double* sv = c.take<double>(dall);
+  double* buf[2] = {c.take<double>(total), c.take<double>(total)};
+  rtr::SvdCaps caps{};
+  caps.N = order;
+  for (int n = 0; n < order; ++n) caps.c[n] = Rcap[n];
+  size_t slot[RTR_MAX_ORDER];
+  slot[0] = 0;
+  for (int n = 0; n + 1 < order; ++n)
+    slot[n + 1] = slot[n] + (size_t)Rcap[n] * Kp[n] * Rcap[(n + 1) % order];
+  HIP_TRY(rtr::launch_sumsq(false, P, total, red, pn2, s), "sumsq");
+  HIP_TRY(rtr::launch_svd_init(state, pn2, eps, order, Kp[0], (int)(total / Kp[0]), s),
+          "svd init");
+  const double* C = P;
+  for (int k = 0; k + 1 < order; ++k) {
+    double* Cn = buf[k & 1];
+    HIP_TRY(rtr::launch_svd_step(state, C, A, V, W, sv, caps, k, dmax[k], Z + slot[k], Cn,
+                                 Kp[k + 1], s),
+            "svd step");
+    C = Cn;
+  }
+  HIP_TRY(rtr::launch_svd_last(state, C, Z + slot[order - 1], order, ranks, err, h->status, s),
+          "svd last");
   return RTR_OK;
 } catch (...) {
   return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
