@@ -186,6 +186,62 @@ rtr_status rtr_decompose_svd(rtr_handle h, const double* P, int32_t order, const
                              double* err, void* stream);
 
 /*
+ * Batched Alg. 1 step 9: TR-ALS on many small projected tensors in ONE persistent launch
+ * (one work-group per tensor runs all of that tensor's sweeps with its cores in LDS).
+ * The per-tensor arithmetic is that of rtr_decompose (RTR_METHOD_ALS): exact least-squares
+ * core updates by the normal equations in FP64; err_trace[s] = ||P - Psi(Z)|| / ||P|| after
+ * sweep s (computed from the Gram: ||P||^2 - 2 <M, W> + <W, G W>), stopping rule as there.
+ * A Gram that is not positive definite skips that update and sets RTR_STATUS_CHOLESKY_FAILED.
+ *   items      host array of count entries; every pointer in it is a device pointer
+ *   Limits: 2 <= order <= 8, K'_n <= 64, R_n <= 6, R_n R_{n+1} <= prod_{m != n} K'_m, and the
+ *   largest tensor's cores and tiles must fit one work-group's LDS (else UNSUPPORTED).
+ */
+typedef struct {
+  const double* P;        /* device, row-major K'_1 x .. x K'_N */
+  const double* Z_init;   /* device, packed initial cores (R_n, K'_n, R_{n+1}); may alias Z */
+  double* Z;              /* device, packed output cores */
+  double* err_trace;      /* device, max_sweeps FP64 */
+  int32_t* sweeps_run;    /* device, 1 int32 */
+  int32_t order;
+  int32_t Kp[RTR_MAX_ORDER];
+  int32_t R[RTR_MAX_ORDER];
+} rtr_als_item;
+
+rtr_status rtr_decompose_batch(rtr_handle h, const rtr_als_item* items, int32_t count,
+                               int32_t max_sweeps, double tol, void* stream);
+
+/*
+ * Alg. 1 steps 3-12 for a batch of tensors: per-tensor sketch (rtr_sketch) and compression
+ * (rtr_compress), one batched TR-ALS launch (rtr_decompose_batch), per-tensor back-projection
+ * (rtr_backproject, skipped where G is NULL).  With use_graph != 0 the whole sequence is
+ * captured into a HIP graph the first time a given item array is seen (that call runs
+ * eagerly) and later calls with an identical item array and parameters replay the graph
+ * with one launch.  The handle keeps one such graph; a workspace reallocation invalidates it.
+ *   items      host array; all pointers are device pointers, dims/K/R/seed as for the
+ *              single-tensor calls (K'_n = min(K_n, I_n) sizes P, Z, Z_init)
+ */
+typedef struct {
+  const void* X;          /* device, row-major I_1 x .. x I_N (x_dtype) */
+  int32_t order;
+  int64_t dims[RTR_MAX_ORDER];
+  int32_t K[RTR_MAX_ORDER];
+  int32_t R[RTR_MAX_ORDER];
+  uint64_t seed;
+  uint32_t tensor_id;
+  const double* Z_init;   /* device, packed initial cores */
+  double* Q;              /* device, packed Q_n (output) */
+  double* P;              /* device, K'_1 x .. x K'_N (output) */
+  double* Z;              /* device, packed cores (output) */
+  double* G;              /* device, packed back-projected cores (output) or NULL */
+  double* err_trace;      /* device, max_sweeps FP64 */
+  int32_t* sweeps_run;    /* device, 1 int32 */
+} rtr_batch_item;
+
+rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t count,
+                         rtr_dtype x_dtype, rtr_dtype compute, int32_t power_iters,
+                         int32_t max_sweeps, double tol, int32_t use_graph, void* stream);
+
+/*
  * Alg. 1 steps 10-12, read as the product over the physical mode: G_n = Z_n x_2 Q_n,
  * G_n[a, i, b] = sum_k Q_n[i, k] Z_n[a, k, b].
  *   dims, K, R host;  Z, Q device FP64 packed;  G device FP64 packed (R_n, I_n, R_{n+1}).

@@ -42,6 +42,20 @@ class _Opts(ctypes.Structure):
                 ("tol", ctypes.c_double), ("eps", ctypes.c_double)]
 
 
+class _AlsItem(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_void_p), ("Z_init", ctypes.c_void_p), ("Z", ctypes.c_void_p),
+                ("err_trace", ctypes.c_void_p), ("sweeps_run", ctypes.c_void_p),
+                ("order", ctypes.c_int32), ("Kp", ctypes.c_int32 * 8), ("R", ctypes.c_int32 * 8)]
+
+
+class _BatchItem(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("order", ctypes.c_int32), ("dims", ctypes.c_int64 * 8),
+                ("K", ctypes.c_int32 * 8), ("R", ctypes.c_int32 * 8), ("seed", ctypes.c_uint64),
+                ("tensor_id", ctypes.c_uint32), ("Z_init", ctypes.c_void_p), ("Q", ctypes.c_void_p),
+                ("P", ctypes.c_void_p), ("Z", ctypes.c_void_p), ("G", ctypes.c_void_p),
+                ("err_trace", ctypes.c_void_p), ("sweeps_run", ctypes.c_void_p)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python paper_1901_01652_amd/build.py`")
@@ -57,6 +71,9 @@ def _load():
         "rtr_compress": [vp, vp, ctypes.c_int, i32, P64, P32, vp, ctypes.c_int, vp, vp, vp],
         "rtr_decompose": [vp, vp, i32, P32, P32, ctypes.POINTER(_Opts), vp, vp, vp, vp, vp],
         "rtr_decompose_svd": [vp, vp, i32, P32, P32, dp, vp, vp, vp, vp],
+        "rtr_decompose_batch": [vp, ctypes.POINTER(_AlsItem), i32, i32, dp, vp],
+        "rtr_batch_run": [vp, ctypes.POINTER(_BatchItem), i32, ctypes.c_int, ctypes.c_int, i32, i32,
+                          dp, i32, vp],
         "rtr_backproject": [vp, i32, P64, P32, P32, vp, vp, vp, vp],
         "rtr_residual": [vp, vp, ctypes.c_int, i32, P64, P32, vp, vp, vp],
         "rtr_normals": [vp, u64, u32, u32, i64, i64, ctypes.c_int, vp, vp],
@@ -255,6 +272,70 @@ def svd_cores(Z, ranks, Kp, Rcap):
         out.append(Z[off:off + cnt].view(*shape))
         off += size
     return out
+
+
+def _arr8(ctype, vals):
+    a = (ctype * 8)()
+    for i, v in enumerate(vals):
+        a[i] = int(v)
+    return a
+
+
+def rtr_decompose_batch(h, items, max_sweeps, tol=0.0, stream=None):
+    """Batched TR-ALS in one launch.  ``items``: dicts with P (device FP64 tensor), R, Z_init
+    (packed, device); optional Z, err_trace, sweeps_run.  Fills and returns the dicts."""
+    arr = (_AlsItem * len(items))()
+    for t, it in enumerate(items):
+        P = it["P"]
+        dev = P.device
+        it.setdefault("Z", torch.empty_like(it["Z_init"]))
+        it.setdefault("err_trace", torch.zeros(max_sweeps, dtype=torch.float64, device=dev))
+        it.setdefault("sweeps_run", torch.zeros(1, dtype=torch.int32, device=dev))
+        a = arr[t]
+        a.P, a.Z_init, a.Z = P.data_ptr(), it["Z_init"].data_ptr(), it["Z"].data_ptr()
+        a.err_trace, a.sweeps_run = it["err_trace"].data_ptr(), it["sweeps_run"].data_ptr()
+        a.order = P.dim()
+        a.Kp = _arr8(ctypes.c_int32, P.shape)
+        a.R = _arr8(ctypes.c_int32, it["R"])
+    dev = items[0]["P"].device
+    h.check(lib.rtr_decompose_batch(h.ptr, arr, len(items), int(max_sweeps), float(tol),
+                                    _stream(stream, dev)))
+    return items
+
+
+def rtr_batch_run(h, items, max_sweeps, compute=None, power_iters=0, tol=0.0, use_graph=False,
+                  stream=None):
+    """Alg. 1 steps 3-12 for a batch.  ``items``: dicts with X (device), K, R, Z_init (packed,
+    device), seed, tensor_id; outputs Q, P, Z, G, err_trace, sweeps_run are allocated when
+    missing (keep the dicts to replay the same batch as a graph)."""
+    arr = (_BatchItem * len(items))()
+    xdt = _xdtype(items[0]["X"])
+    if compute is None:
+        compute = "f64" if xdt == RTR_F64 else "f32"
+    for t, it in enumerate(items):
+        X = it["X"]
+        dev = X.device
+        dims = list(X.shape)
+        K, R = list(it["K"]), list(it["R"])
+        Kp = [min(k, d) for k, d in zip(K, dims)]
+        f64 = dict(dtype=torch.float64, device=dev)
+        it.setdefault("Q", torch.empty(sum(d * k for d, k in zip(dims, Kp)), **f64))
+        it.setdefault("P", torch.empty(Kp, **f64))
+        it.setdefault("Z", torch.empty_like(it["Z_init"]))
+        it.setdefault("G", torch.empty(sum(a * b * c for a, b, c in core_shapes(dims, R)), **f64))
+        it.setdefault("err_trace", torch.zeros(max_sweeps, **f64))
+        it.setdefault("sweeps_run", torch.zeros(1, dtype=torch.int32, device=dev))
+        a = arr[t]
+        a.X, a.order = X.data_ptr(), len(dims)
+        a.dims, a.K, a.R = _arr8(ctypes.c_int64, dims), _arr8(ctypes.c_int32, K), _arr8(ctypes.c_int32, R)
+        a.seed, a.tensor_id = int(it.get("seed", 0)), int(it.get("tensor_id", 0))
+        a.Z_init = it["Z_init"].data_ptr()
+        for name in ("Q", "P", "Z", "G", "err_trace", "sweeps_run"):
+            setattr(a, name, it[name].data_ptr() if it[name] is not None else None)
+    dev = items[0]["X"].device
+    h.check(lib.rtr_batch_run(h.ptr, arr, len(items), xdt, _DTYPES[compute], int(power_iters),
+                              int(max_sweeps), float(tol), int(bool(use_graph)), _stream(stream, dev)))
+    return items
 
 
 def rtr_backproject(h, dims, K, R, Z, Q, G=None, stream=None):

@@ -202,4 +202,25 @@ hipError_t launch_svd_step(SvdState* st, const double* C, double* A, double* V, 
 hipError_t launch_svd_last(const SvdState* st, const double* C, double* Zlast, int N,
                            int* ranks_out, double* err_out, unsigned* status, hipStream_t s);
 
+// ---- batch.hip ------------------------------------------------------------------------
+struct AlsItem {  // one tensor of a batched TR-ALS (device array of these)
+  const double* P;
+  const double* Zinit;
+  double* Z;
+  double* err;
+  int* sweeps;
+  int N;
+  int K[8];
+  int R[8];
+};
+struct BatchLayout {  // dynamic-LDS offsets (doubles) shared by every work-group
+  int kpad, tj, rrpad, tsz, ps, pre, bs, buf, total;
+};
+// Layout for the batch maxima (K'_n <= 64, R_n <= 6); false if unsupported.
+bool batch_layout(int maxK, int maxRR, int maxR, int64_t maxZ, int minKl, BatchLayout* lay,
+                  int* mq, int* gq);
+hipError_t launch_als_batch(const AlsItem* items, int count, int max_sweeps, double tol,
+                            unsigned* status, const BatchLayout& lay, int mq, int gq,
+                            hipStream_t s);
+
 }  // namespace rtr

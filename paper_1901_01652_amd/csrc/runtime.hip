@@ -28,6 +28,20 @@ struct rtr_context {
   std::vector<hipEvent_t> pool;
   const char* pending = nullptr;
   hipEvent_t pending_e0 = nullptr;
+  int ws_epoch = 0;  // bumped whenever the workspace moves (cached graphs point into it)
+  // batched TR-ALS: device item array, pinned staging for its upload
+  void* items_dev = nullptr;
+  size_t items_cap = 0;
+  void* items_host = nullptr;
+  size_t host_cap = 0;
+  hipEvent_t items_copied = nullptr;
+  // batched pipeline replayed as one graph
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  uint64_t gkey = 0;
+  int gepoch = -1;
+  void* gitems_dev = nullptr;
+  size_t gitems_cap = 0;
 };
 
 namespace {
@@ -88,6 +102,7 @@ rtr_status ensure_ws(rtr_context* h, size_t bytes) {
     h->ws = nullptr;
     h->ws_cap = 0;
   }
+  ++h->ws_epoch;
   hipError_t e = hipMalloc(&h->ws, cap);
   if (e != hipSuccess) {
     h->ws = nullptr;
@@ -210,6 +225,12 @@ rtr_status rtr_destroy(rtr_handle h) {
     (void)hipEventDestroy(r.e1);
   }
   for (auto e : h->pool) (void)hipEventDestroy(e);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->items_copied) (void)hipEventDestroy(h->items_copied);
+  if (h->items_dev) (void)hipFree(h->items_dev);
+  if (h->gitems_dev) (void)hipFree(h->gitems_dev);
+  if (h->items_host) (void)hipHostFree(h->items_host);
   if (h->ws) (void)hipFree(h->ws);
   if (h->status) (void)hipFree(h->status);
   delete h;
@@ -744,6 +765,251 @@ rtr_status rtr_decompose_svd(rtr_handle h, const double* P, int32_t order, const
   }
   HIP_TRY(rtr::launch_svd_last(state, C, Z + slot[order - 1], order, ranks, err, h->status, s),
           "svd last");
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+// ---------------------------------------------------------------------------------------
+namespace {
+
+struct BatchPlan {
+  std::vector<rtr::AlsItem> items;
+  rtr::BatchLayout lay{};
+  int mq = 1, gq = 4;
+};
+
+rtr_status plan_batch(rtr_context* h, const rtr_als_item* items, int32_t count,
+                      int32_t max_sweeps, double tol, BatchPlan* plan) {
+  if (!items || count < 1) return fail(h, RTR_ERR_INVALID_ARG, "items must hold count >= 1 entries");
+  if (count > 65535) return fail(h, RTR_ERR_UNSUPPORTED, "at most 65535 tensors per batch");
+  if (max_sweeps < 1) return fail(h, RTR_ERR_INVALID_ARG, "max_sweeps must be >= 1");
+  if (!(tol >= 0.0)) return fail(h, RTR_ERR_INVALID_ARG, "tol must be >= 0");
+  int maxK = 1, maxRR = 1, maxR = 1, minK = 1 << 30;
+  int64_t maxZ = 1;
+  plan->items.resize(count);
+  for (int t = 0; t < count; ++t) {
+    const rtr_als_item& it = items[t];
+    const std::string where = "item " + std::to_string(t) + ": ";
+    if (it.order < 2 || it.order > RTR_MAX_ORDER)
+      return fail(h, RTR_ERR_INVALID_ARG, where + "order must be in [2, 8]");
+    if (!it.P || !it.Z_init || !it.Z || !it.err_trace || !it.sweeps_run)
+      return fail(h, RTR_ERR_INVALID_ARG, where + "P, Z_init, Z, err_trace, sweeps_run must be device pointers");
+    rtr::AlsItem a{};
+    a.P = it.P;
+    a.Zinit = it.Z_init;
+    a.Z = it.Z;
+    a.err = it.err_trace;
+    a.sweeps = it.sweeps_run;
+    a.N = it.order;
+    int64_t total = 1, ztot = 0;
+    for (int n = 0; n < it.order; ++n) {
+      if (it.Kp[n] < 1) return fail(h, RTR_ERR_INVALID_ARG, where + "Kp entries must be >= 1");
+      if (it.R[n] < 1) return fail(h, RTR_ERR_INVALID_ARG, where + "ranks must be >= 1");
+      if (it.Kp[n] > 64 || it.R[n] > 6)
+        return fail(h, RTR_ERR_UNSUPPORTED, where + "the batched TR-ALS takes K'_n <= 64 and R_n <= 6");
+      total *= it.Kp[n];
+      if (total > ((int64_t)1 << 31)) return fail(h, RTR_ERR_UNSUPPORTED, where + "P above 2^31 entries");
+      a.K[n] = it.Kp[n];
+      a.R[n] = it.R[n];
+    }
+    for (int n = 0; n < it.order; ++n) {
+      const int rb = it.R[(n + 1) % it.order];
+      if ((int64_t)it.R[n] * rb > total / it.Kp[n])
+        return fail(h, RTR_ERR_INVALID_ARG, where + "R_n R_{n+1} exceeds the number of equations of core " + std::to_string(n));
+      ztot += (int64_t)it.R[n] * it.Kp[n] * rb;
+      maxK = std::max(maxK, (int)it.Kp[n]);
+      minK = std::min(minK, (int)it.Kp[n]);
+      maxR = std::max(maxR, (int)it.R[n]);
+      maxRR = std::max(maxRR, (int)(it.R[n] * rb));
+    }
+    maxZ = std::max(maxZ, ztot);
+    plan->items[t] = a;
+  }
+  if (!rtr::batch_layout(maxK, maxRR, maxR, maxZ, minK, &plan->lay, &plan->mq, &plan->gq))
+    return fail(h, RTR_ERR_UNSUPPORTED, "batch does not fit the work-group's LDS (cores too large)");
+  return RTR_OK;
+}
+
+// Copy the item array to the device through pinned staging (stream-ordered).
+rtr_status upload_items(rtr_context* h, const std::vector<rtr::AlsItem>& v, hipStream_t s,
+                        rtr::AlsItem** out) {
+  const size_t bytes = v.size() * sizeof(rtr::AlsItem);
+  if (h->items_copied) HIP_TRY(hipEventSynchronize(h->items_copied), "hipEventSynchronize");
+  else HIP_TRY(hipEventCreateWithFlags(&h->items_copied, hipEventDisableTiming), "hipEventCreate");
+  if (bytes > h->host_cap) {
+    if (h->items_host) (void)hipHostFree(h->items_host);
+    h->items_host = nullptr;
+    h->host_cap = 0;
+    HIP_TRY(hipHostMalloc(&h->items_host, bytes, hipHostMallocDefault), "hipHostMalloc");
+    h->host_cap = bytes;
+  }
+  if (bytes > h->items_cap) {
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (h->items_dev) (void)hipFree(h->items_dev);
+    h->items_dev = nullptr;
+    h->items_cap = 0;
+    HIP_TRY(hipMalloc(&h->items_dev, bytes), "hipMalloc");
+    h->items_cap = bytes;
+  }
+  std::memcpy(h->items_host, v.data(), bytes);
+  HIP_TRY(hipMemcpyAsync(h->items_dev, h->items_host, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+  HIP_TRY(hipEventRecord(h->items_copied, s), "hipEventRecord");
+  *out = (rtr::AlsItem*)h->items_dev;
+  return RTR_OK;
+}
+
+uint64_t fnv(uint64_t hsh, const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) hsh = (hsh ^ b[i]) * 1099511628211ull;
+  return hsh;
+}
+
+}  // namespace
+
+rtr_status rtr_decompose_batch(rtr_handle h, const rtr_als_item* items, int32_t count,
+                               int32_t max_sweeps, double tol, void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  BatchPlan plan;
+  st = plan_batch(h, items, count, max_sweeps, tol, &plan);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  rtr::AlsItem* dev = nullptr;
+  st = upload_items(h, plan.items, s, &dev);
+  if (st) return st;
+  HIP_TRY(rtr::launch_als_batch(dev, count, max_sweeps, tol, h->status, plan.lay, plan.mq, plan.gq, s),
+          "batched TR-ALS");
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+namespace {
+
+// Alg. 1 steps 3-12 for every item: per-tensor sketch and compression, one batched TR-ALS
+// launch over the item array ``dev``, per-tensor back-projection.
+rtr_status batch_sequence(rtr_context* h, const rtr_batch_item* items, int32_t count,
+                          rtr_dtype x_dtype, rtr_dtype compute, int32_t power_iters,
+                          int32_t max_sweeps, double tol, const BatchPlan& plan,
+                          const rtr::AlsItem* dev, hipStream_t s) {
+  for (int t = 0; t < count; ++t) {
+    const rtr_batch_item& it = items[t];
+    rtr_status st = rtr_sketch(h, it.X, x_dtype, it.order, it.dims, it.K, power_iters, it.seed,
+                               it.tensor_id, compute, it.Q, s);
+    if (st) return st;
+    st = rtr_compress(h, it.X, x_dtype, it.order, it.dims, it.K, it.Q, compute, it.P, nullptr, s);
+    if (st) return st;
+  }
+  Guard guard(h);
+  HIP_TRY(rtr::launch_als_batch(dev, count, max_sweeps, tol, h->status, plan.lay, plan.mq, plan.gq, s),
+          "batched TR-ALS");
+  for (int t = 0; t < count; ++t) {
+    const rtr_batch_item& it = items[t];
+    if (!it.G) continue;
+    rtr_status st = rtr_backproject(h, it.order, it.dims, it.K, it.R, it.Z, it.Q, it.G, s);
+    if (st) return st;
+  }
+  return RTR_OK;
+}
+
+}  // namespace
+
+rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t count,
+                         rtr_dtype x_dtype, rtr_dtype compute, int32_t power_iters,
+                         int32_t max_sweeps, double tol, int32_t use_graph, void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  if (!items || count < 1) return fail(h, RTR_ERR_INVALID_ARG, "items must hold count >= 1 entries");
+  std::vector<rtr_als_item> als(count);
+  for (int t = 0; t < count; ++t) {
+    const rtr_batch_item& it = items[t];
+    if (it.order < 2 || it.order > RTR_MAX_ORDER)
+      return fail(h, RTR_ERR_INVALID_ARG, "item " + std::to_string(t) + ": order must be in [2, 8]");
+    if (!it.X || !it.Q || !it.P)
+      return fail(h, RTR_ERR_INVALID_ARG, "item " + std::to_string(t) + ": X, Q, P must be device pointers");
+    rtr_als_item a{};
+    a.P = it.P;
+    a.Z_init = it.Z_init;
+    a.Z = it.Z;
+    a.err_trace = it.err_trace;
+    a.sweeps_run = it.sweeps_run;
+    a.order = it.order;
+    for (int n = 0; n < it.order; ++n) {
+      if (it.dims[n] < 1 || it.K[n] < 1)
+        return fail(h, RTR_ERR_INVALID_ARG, "item " + std::to_string(t) + ": dims and K must be >= 1");
+      a.Kp[n] = (int32_t)keff(it.dims, it.K, n);
+      a.R[n] = it.R[n];
+    }
+    als[t] = a;
+  }
+  BatchPlan plan;
+  {
+    Guard guard(h);
+    st = plan_batch(h, als.data(), count, max_sweeps, tol, &plan);
+    if (st) return st;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  uint64_t key = 1469598103934665603ull;
+  key = fnv(key, items, sizeof(rtr_batch_item) * (size_t)count);
+  const int64_t params[5] = {count, x_dtype, compute, power_iters, max_sweeps};
+  key = fnv(key, params, sizeof(params));
+  key = fnv(key, &tol, sizeof(tol));
+  if (use_graph && h->gexec && key == h->gkey && h->gepoch == h->ws_epoch) {
+    HIP_TRY(hipGraphLaunch(h->gexec, s), "hipGraphLaunch");
+    return RTR_OK;
+  }
+  // eager run (also sizes the workspace for the capture below)
+  rtr::AlsItem* dev = nullptr;
+  {
+    Guard guard(h);
+    st = upload_items(h, plan.items, s, &dev);
+    if (st) return st;
+  }
+  st = batch_sequence(h, items, count, x_dtype, compute, power_iters, max_sweeps, tol, plan, dev, s);
+  if (st || !use_graph) return st;
+  // capture the same sequence into a graph over a dedicated copy of the item array
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  const size_t bytes = plan.items.size() * sizeof(rtr::AlsItem);
+  if (bytes > h->gitems_cap) {
+    if (h->gitems_dev) (void)hipFree(h->gitems_dev);
+    h->gitems_dev = nullptr;
+    h->gitems_cap = 0;
+    HIP_TRY(hipMalloc(&h->gitems_dev, bytes), "hipMalloc");
+    h->gitems_cap = bytes;
+  }
+  HIP_TRY(hipMemcpy(h->gitems_dev, plan.items.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy");
+  if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  const int prof = h->prof_level;
+  h->prof_level = 0;
+  const int epoch = h->ws_epoch;
+  HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+  st = batch_sequence(h, items, count, x_dtype, compute, power_iters, max_sweeps, tol, plan,
+                      (const rtr::AlsItem*)h->gitems_dev, h->cap_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
+  h->prof_level = prof;
+  if (st) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (ec != hipSuccess) return hip_fail(h, ec, "hipStreamEndCapture");
+  if (h->ws_epoch != epoch) {
+    (void)hipGraphDestroy(graph);
+    return fail(h, RTR_ERR_INTERNAL, "workspace moved during graph capture");
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return hip_fail(h, ei, "hipGraphInstantiate");
+  h->gexec = exec;
+  h->gkey = key;
+  h->gepoch = h->ws_epoch;
   return RTR_OK;
 } catch (...) {
   return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
