@@ -56,6 +56,74 @@ def cpu_baseline(I_full, I_sample=80):
                        f"host os.cpu_count()={os.cpu_count()}")}
 
 
+def bench_tr_svd(rt, h, P, eps=0.15, reps=3):
+    """rTR-SVD (Alg. 1 step 9 by TR-SVD) on the projected tensor of the same run."""
+    import torch
+    caps = [512] * P.dim()
+    rt.rtr_decompose_svd(h, P, caps, eps)          # warm-up (workspace, code objects)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Z, ranks, err = rt.rtr_decompose_svd(h, P, caps, eps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"ms": round(ms, 3), "eps": eps, "ranks": [int(r) for r in ranks.cpu()],
+            "p_err": round(float(err.cpu()[0]), 6)}
+
+
+def bench_batched(rt, h, count=512, sweeps=20, reps=3):
+    """The batched workload: ``count`` order-4 FP32 tensors with I_n ~ U{16..96},
+    R ~ U{2..6}, K = 2R+4, 35 dB, 20 sweeps.  Times the batched pipeline replayed as one HIP
+    graph, the same batch run eagerly, and the per-tensor loop over the single-tensor calls."""
+    import torch
+    import workloads as W
+    dev = "cuda:0"
+    ws = W.batched_uneven(count)
+    items = []
+    elems = 0
+    for w in ws:
+        X, _ = W.make_tensor(w, device=dev, dtype=torch.float32)
+        items.append({"X": X, "K": list(w.K), "R": list(w.ranks), "Z_init": rt.pack(W.make_init(w), dev),
+                      "seed": w.seed, "tensor_id": w.tensor_id})
+        elems += X.numel()
+    torch.cuda.synchronize()
+    log(f"[bench] batched: {count} tensors, {elems / 1e9:.2f} G elements")
+
+    def clock(fn, n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n
+
+    rt.rtr_batch_run(h, items, sweeps, use_graph=True)      # eager run + graph capture
+    graph_ms = clock(lambda: rt.rtr_batch_run(h, items, sweeps, use_graph=True), reps)
+    eager_ms = clock(lambda: rt.rtr_batch_run(h, items, sweeps, use_graph=False), 1)
+    rt.rtr_profile_reset(h)
+    rt.rtr_profile_enable(h, 2)
+    rt.rtr_batch_run(h, items, sweeps, use_graph=False)
+    als_ms, _ = rt.rtr_profile_read(h, "als_batch")
+    rt.rtr_profile_enable(h, 0)
+
+    def loop():
+        for it in items:
+            X = it["X"]
+            Q = rt.rtr_sketch(h, X, it["K"], 0, it["seed"], it["tensor_id"], "f32")
+            P = rt.rtr_compress(h, X, it["K"], Q, "f32")
+            Z, tr, ns = rt.rtr_decompose(h, P, it["R"], it["Z_init"], sweeps)
+            rt.rtr_backproject(h, list(X.shape), it["K"], it["R"], Z, Q)
+
+    loop_ms = clock(loop, 1)
+    final = [float(it["err_trace"][-1]) for it in items]
+    return {"tensors": count, "elements": elems, "graph_ms": round(graph_ms, 2),
+            "eager_ms": round(eager_ms, 2), "per_tensor_loop_ms": round(loop_ms, 2),
+            "batched_als_kernel_ms": round(als_ms, 2),
+            "speedup_vs_loop": round(loop_ms / graph_ms, 2),
+            "p_err_median": round(float(np.median(final)), 6), "compute": "f32",
+            "sweeps": sweeps}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +133,8 @@ def main():
     ap.add_argument("--compute", default="bf16", choices=["bf16", "f32"])
     ap.add_argument("--no-fp32-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched 512-tensor workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -146,6 +216,15 @@ def main():
         r32 = rt.rtr_residual(h, X, w.ranks, o32["G"]).cpu().numpy()
         fp32 = {"ms_per_step": round(ms32, 3), "rse": float(np.sqrt(r32[0] / r32[1]))}
 
+    log("[bench] TR-SVD on the projected tensor")
+    svd = bench_tr_svd(rt, h, out["P"])
+    batched = None
+    if not args.no_batched:
+        del out
+        torch.cuda.empty_cache()
+        batched = bench_batched(rt, h)
+        log(f"[bench] batched: graph {batched['graph_ms']} ms, loop {batched['per_tensor_loop_ms']} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] FP64 oracle on the host (bounded sample)")
@@ -163,6 +242,7 @@ def main():
                    "fp64": "QR, power-step orthonormalisation, TR-ALS"},
         "rse": round(rse, 6), "rse_pythagorean": round(rse_py, 6), "p_err": round(e, 6),
         "roofline": roof, "kernels": kern, "fp32_path": fp32, "cpu_baseline": cpu,
+        "tr_svd": svd, "batched": batched,
     }
     h.close()
     print(json.dumps(line), flush=True)

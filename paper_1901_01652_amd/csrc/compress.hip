@@ -15,28 +15,34 @@ namespace rtr {
 
 constexpr int kTtmKMax = 64;
 
-template <int AR, typename Tin>
+// KC: outputs k per thread; thread (p, ks) owns fiber p = (a, b) and k in [ks KC, ks KC + KC),
+// so short products with few fibers still spread over enough threads.
+template <int AR, typename Tin, int KC>
 __global__ __launch_bounds__(256) void ttm_kernel(const Tin* __restrict__ in, int64_t A,
                                                   int64_t In, int64_t B, int K,
                                                   const double* __restrict__ Q,
                                                   double* __restrict__ out) {
   using Acc = typename std::conditional<AR == kF64, double, float>::type;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= A * B) return;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nfib = A * B;
+  const int64_t p = g % nfib;
+  const int k0 = (int)(g / nfib) * KC;
+  if (k0 >= K) return;
+  const int kn = K - k0 < KC ? K - k0 : KC;
   const int64_t a = p / B, b = p % B;
   const Tin* src = in + a * In * B + b;
-  Acc acc[kTtmKMax];
+  Acc acc[KC];
 #pragma unroll
-  for (int k = 0; k < kTtmKMax; ++k) acc[k] = 0;
+  for (int k = 0; k < KC; ++k) acc[k] = 0;
   for (int64_t i = 0; i < In; ++i) {
-    const double* q = Q + i * K;
+    const double* q = Q + i * K + k0;
     if constexpr (AR == kBF16) {
       const float x = (float)src[i * B];
       const float xh = bf16_round(x);
       const float xl = bf16_round(x - xh);
 #pragma unroll
-      for (int k = 0; k < kTtmKMax; ++k) {
-        if (k < K) {
+      for (int k = 0; k < KC; ++k) {
+        if (k < kn) {
           const float qf = (float)q[k];
           const float qh = bf16_round(qf);
           const float ql = bf16_round(qf - qh);
@@ -46,32 +52,45 @@ __global__ __launch_bounds__(256) void ttm_kernel(const Tin* __restrict__ in, in
     } else {
       const Acc x = (Acc)src[i * B];
 #pragma unroll
-      for (int k = 0; k < kTtmKMax; ++k)
-        if (k < K) acc[k] += x * (Acc)q[k];
+      for (int k = 0; k < KC; ++k)
+        if (k < kn) acc[k] += x * (Acc)q[k];
     }
   }
   double* dst = out + a * (int64_t)K * B + b;
 #pragma unroll
-  for (int k = 0; k < kTtmKMax; ++k)
-    if (k < K) dst[(int64_t)k * B] = (double)acc[k];
+  for (int k = 0; k < KC; ++k)
+    if (k < kn) dst[(int64_t)(k0 + k) * B] = (double)acc[k];
+}
+
+template <int KC>
+static void launch_ttm_kc(Arith ar, bool first, const void* in, const ModeView& v, int K,
+                          const double* Q, double* out, hipStream_t s) {
+  const int64_t n = v.A * v.B * ((K + KC - 1) / KC);
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (!first || ar == kF64) {
+    hipLaunchKernelGGL((ttm_kernel<kF64, double, KC>), dim3(blocks), dim3(256), 0, s,
+                       (const double*)in, v.A, v.In, v.B, K, Q, out);
+  } else if (ar == kF32) {
+    hipLaunchKernelGGL((ttm_kernel<kF32, float, KC>), dim3(blocks), dim3(256), 0, s,
+                       (const float*)in, v.A, v.In, v.B, K, Q, out);
+  } else {
+    hipLaunchKernelGGL((ttm_kernel<kBF16, float, KC>), dim3(blocks), dim3(256), 0, s,
+                       (const float*)in, v.A, v.In, v.B, K, Q, out);
+  }
 }
 
 hipError_t launch_ttm(Arith ar, bool first, const void* in, const ModeView& v, int K,
                       const double* Q, double* out, hipStream_t s) {
   if (K > kTtmKMax) return hipErrorInvalidValue;
-  const int64_t n = v.A * v.B;
-  const unsigned blocks = (unsigned)((n + 255) / 256);
+  const int64_t fibers = v.A * v.B;
   prof_begin(first ? "ttm_first" : "ttm", s);
-  if (!first || ar == kF64) {
-    hipLaunchKernelGGL((ttm_kernel<kF64, double>), dim3(blocks), dim3(256), 0, s,
-                       (const double*)in, v.A, v.In, v.B, K, Q, out);
-  } else if (ar == kF32) {
-    hipLaunchKernelGGL((ttm_kernel<kF32, float>), dim3(blocks), dim3(256), 0, s,
-                       (const float*)in, v.A, v.In, v.B, K, Q, out);
-  } else {
-    hipLaunchKernelGGL((ttm_kernel<kBF16, float>), dim3(blocks), dim3(256), 0, s,
-                       (const float*)in, v.A, v.In, v.B, K, Q, out);
-  }
+  // enough threads to cover the GPU: split K when there are few fibers
+  if (fibers >= (1 << 17))
+    launch_ttm_kc<kTtmKMax>(ar, first, in, v, K, Q, out, s);
+  else if (fibers >= (1 << 15))
+    launch_ttm_kc<16>(ar, first, in, v, K, Q, out, s);
+  else
+    launch_ttm_kc<4>(ar, first, in, v, K, Q, out, s);
   prof_end(s);
   return hipGetLastError();
 }

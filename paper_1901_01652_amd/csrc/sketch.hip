@@ -319,29 +319,42 @@ hipError_t launch_power_partial(Arith ar, const void* X, const ModeView& v, int 
 }
 
 // ---------------------------------------------------------------------------------------
+// Y[:, k] = sum over chunks of the per-work-group partials.  A work-group of 1024 threads
+// owns 64 consecutive outputs; its 16 wavefronts take every 16th chunk each (coalesced
+// along the outputs), and the 16 slice sums are added in a fixed order.
 template <typename P>
-__global__ void reduce_partials_kernel(const P* __restrict__ partial, int64_t chunks,
-                                       int64_t In, int K, double* __restrict__ Ycol) {
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(1024) void reduce_partials_kernel(const P* __restrict__ partial,
+                                                               int64_t chunks, int64_t In, int K,
+                                                               double* __restrict__ Ycol) {
+  __shared__ double part[16][65];
+  const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
   const int64_t nout = In * K;
-  if (o >= nout) return;
+  const int64_t o = (int64_t)blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int64_t c = 0; c < chunks; ++c) s += (double)partial[c * nout + o];
-  const int64_t i = o / K;
-  const int k = (int)(o % K);
-  Ycol[(int64_t)k * In + i] = s;
+  if (o < nout)
+    for (int64_t c = slice; c < chunks; c += 16) s += (double)partial[c * nout + o];
+  part[slice][lane] = s;
+  __syncthreads();
+  if (slice == 0 && o < nout) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += part[q][lane];
+    const int64_t i = o / K;
+    const int k = (int)(o % K);
+    Ycol[(int64_t)k * In + i] = t;
+  }
 }
 
 hipError_t launch_reduce_partials(Arith ar, const void* partial, int64_t chunks, int64_t In,
                                   int K, double* Ycol, hipStream_t s) {
   const int64_t nout = In * K;
-  const unsigned blocks = (unsigned)((nout + 255) / 256);
+  const unsigned blocks = (unsigned)((nout + 63) / 64);
   prof_begin("reduce_partials", s);
   if (ar == kF64)
-    hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(blocks), dim3(256), 0, s,
+    hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(blocks), dim3(1024), 0, s,
                        (const double*)partial, chunks, In, K, Ycol);
   else
-    hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(blocks), dim3(256), 0, s,
+    hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(blocks), dim3(1024), 0, s,
                        (const float*)partial, chunks, In, K, Ycol);
   prof_end(s);
   return hipGetLastError();
