@@ -242,6 +242,45 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
                          int32_t max_sweeps, double tol, int32_t use_graph, void* stream);
 
 /*
+ * Learned warm start for TR-ALS (an initialisation of Alg. 1 step 9): a multilayer
+ * perceptron maps the normalised projected tensor P~ = P / ||P|| (row-major, flattened) to
+ * the packed initial cores (R_n, K'_n, R_{n+1}).  Hidden layers h_l = relu(h_{l-1} W_l + b_l),
+ * output y = h_{L-1} W_L + b_L; W_l is sizes[l] x sizes[l+1] row-major FP32 (device),
+ * b_l has sizes[l+1] entries.  compute RTR_BF16 rounds both operands of every product to
+ * bf16 (FP32 accumulation), RTR_F32 multiplies in FP32.  All arrays are device arrays
+ * except sizes, K, R and the pointer arrays W, b, acts, dW, db (host arrays of device
+ * pointers).  Training loss: mean over the batch of ||P~ - Psi(Z)||^2.
+ */
+/* out[r, :] = P[r, :] / ||P[r, :]|| (FP64 in, FP32 out), rows x dim. */
+rtr_status rtr_mlp_normalize(rtr_handle h, const double* P, int64_t dim, int32_t rows,
+                             float* out, void* stream);
+/* y (batch x sizes[layers]) from x (batch x sizes[0]); acts[l] (batch x sizes[l+1]) keeps the
+ * post-ReLU output of hidden layer l for the backward pass. */
+rtr_status rtr_mlp_forward(rtr_handle h, int32_t layers, const int32_t* sizes,
+                           const float* const* W, const float* const* b, const float* x,
+                           int32_t batch, float* const* acts, float* y, rtr_dtype compute,
+                           void* stream);
+/* Order-4 TR loss per sample: loss[s] = ||target[s] - Psi(cores in y[s])||^2 and
+ * dy[s] = grad_scale * d loss[s] / d y[s] (K, R: 4 entries, R_n <= 8). */
+rtr_status rtr_mlp_tr_loss(rtr_handle h, const float* y, const float* target, int32_t batch,
+                           const int32_t* K, const int32_t* R, float grad_scale, float* loss,
+                           float* dy, void* stream);
+/* dW[l], db[l] (overwritten) from dy through the layers of rtr_mlp_forward. */
+rtr_status rtr_mlp_backward(rtr_handle h, int32_t layers, const int32_t* sizes,
+                            const float* const* W, const float* x, int32_t batch,
+                            const float* const* acts, const float* dy, float* const* dW,
+                            float* const* db, rtr_dtype compute, void* stream);
+/* One Adam step (Kingma & Ba 2015) on n FP32 parameters; step = 1, 2, .. */
+rtr_status rtr_mlp_adam(rtr_handle h, float* w, const float* g, float* m, float* v, int64_t n,
+                        double lr, double beta1, double beta2, double eps, int32_t step,
+                        void* stream);
+/* FP64 initial cores for rtr_decompose from the predictions y (rows x per_row):
+ * Z[r, :] = y[r, :] * ||P_r||^(1/order) with ||P_r||^2 = p_norm2[r] (device; NULL: no scaling),
+ * so that Psi(Z) approximates P_r rather than P_r / ||P_r|| (Psi is multilinear). */
+rtr_status rtr_mlp_to_cores(rtr_handle h, const float* y, int64_t per_row, int32_t rows,
+                            const double* p_norm2, int32_t order, double* Z, void* stream);
+
+/*
  * Alg. 1 steps 10-12, read as the product over the physical mode: G_n = Z_n x_2 Q_n,
  * G_n[a, i, b] = sum_k Q_n[i, k] Z_n[a, k, b].
  *   dims, K, R host;  Z, Q device FP64 packed;  G device FP64 packed (R_n, I_n, R_{n+1}).

@@ -75,6 +75,14 @@ def _load():
         "rtr_batch_run": [vp, ctypes.POINTER(_BatchItem), i32, ctypes.c_int, ctypes.c_int, i32, i32,
                           dp, i32, vp],
         "rtr_backproject": [vp, i32, P64, P32, P32, vp, vp, vp, vp],
+        "rtr_mlp_normalize": [vp, vp, i64, i32, vp, vp],
+        "rtr_mlp_forward": [vp, i32, P32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, i32,
+                            ctypes.POINTER(vp), vp, ctypes.c_int, vp],
+        "rtr_mlp_tr_loss": [vp, vp, vp, i32, P32, P32, ctypes.c_float, vp, vp, vp],
+        "rtr_mlp_backward": [vp, i32, P32, ctypes.POINTER(vp), vp, i32, ctypes.POINTER(vp), vp,
+                             ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp],
+        "rtr_mlp_adam": [vp, vp, vp, vp, vp, i64, dp, dp, dp, dp, i32, vp],
+        "rtr_mlp_to_cores": [vp, vp, i64, i32, vp, i32, vp, vp],
         "rtr_residual": [vp, vp, ctypes.c_int, i32, P64, P32, vp, vp, vp],
         "rtr_normals": [vp, u64, u32, u32, i64, i64, ctypes.c_int, vp, vp],
         "rtr_status_sync": [vp, vp, ctypes.POINTER(u32)],
@@ -336,6 +344,71 @@ def rtr_batch_run(h, items, max_sweeps, compute=None, power_iters=0, tol=0.0, us
     h.check(lib.rtr_batch_run(h.ptr, arr, len(items), xdt, _DTYPES[compute], int(power_iters),
                               int(max_sweeps), float(tol), int(bool(use_graph)), _stream(stream, dev)))
     return items
+
+
+def _ptrs(ts):
+    return (ctypes.c_void_p * max(1, len(ts)))(*[t.data_ptr() for t in ts])
+
+
+def rtr_mlp_normalize(h, P, out=None, stream=None):
+    """Rows of P (batch x d, FP64) divided by their norms, FP32."""
+    rows, d = P.shape[0], P[0].numel()
+    if out is None:
+        out = torch.empty((rows, d), dtype=torch.float32, device=P.device)
+    h.check(lib.rtr_mlp_normalize(h.ptr, _ptr(P), d, rows, _ptr(out), _stream(stream, P.device)))
+    return out
+
+
+def rtr_mlp_forward(h, W, b, x, acts=None, y=None, compute="bf16", stream=None):
+    """Forward pass; returns (y, acts)."""
+    sizes = [W[0].shape[0]] + [w.shape[1] for w in W]
+    B = x.shape[0]
+    if acts is None:
+        acts = [torch.empty((B, n), dtype=torch.float32, device=x.device) for n in sizes[1:-1]]
+    if y is None:
+        y = torch.empty((B, sizes[-1]), dtype=torch.float32, device=x.device)
+    h.check(lib.rtr_mlp_forward(h.ptr, len(W), _i32(sizes), _ptrs(W), _ptrs(b), _ptr(x), B,
+                                _ptrs(acts), _ptr(y), _DTYPES[compute], _stream(stream, x.device)))
+    return y, acts
+
+
+def rtr_mlp_tr_loss(h, y, target, K, R, grad_scale, loss=None, dy=None, stream=None):
+    B = y.shape[0]
+    if loss is None:
+        loss = torch.empty(B, dtype=torch.float32, device=y.device)
+    if dy is None:
+        dy = torch.empty_like(y)
+    h.check(lib.rtr_mlp_tr_loss(h.ptr, _ptr(y), _ptr(target), B, _i32(K), _i32(R),
+                                float(grad_scale), _ptr(loss), _ptr(dy), _stream(stream, y.device)))
+    return loss, dy
+
+
+def rtr_mlp_backward(h, W, x, acts, dy, dW=None, db=None, compute="bf16", stream=None):
+    sizes = [W[0].shape[0]] + [w.shape[1] for w in W]
+    if dW is None:
+        dW = [torch.empty_like(w) for w in W]
+    if db is None:
+        db = [torch.empty(w.shape[1], dtype=torch.float32, device=x.device) for w in W]
+    h.check(lib.rtr_mlp_backward(h.ptr, len(W), _i32(sizes), _ptrs(W), _ptr(x), x.shape[0],
+                                 _ptrs(acts), _ptr(dy), _ptrs(dW), _ptrs(db), _DTYPES[compute],
+                                 _stream(stream, x.device)))
+    return dW, db
+
+
+def rtr_mlp_adam(h, w, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    h.check(lib.rtr_mlp_adam(h.ptr, _ptr(w), _ptr(g), _ptr(m), _ptr(v), w.numel(), float(lr),
+                             float(beta1), float(beta2), float(eps), int(step),
+                             _stream(stream, w.device)))
+
+
+def rtr_mlp_to_cores(h, y, p_norm2=None, order=4, Z=None, stream=None):
+    """FP64 cores from predictions y (rows x per_row), each row scaled by ||P||^(1/order)."""
+    y2 = y.reshape(-1, y.shape[-1])
+    if Z is None:
+        Z = torch.empty(y2.shape, dtype=torch.float64, device=y.device)
+    h.check(lib.rtr_mlp_to_cores(h.ptr, _ptr(y2), y2.shape[1], y2.shape[0], _ptr(p_norm2),
+                                 int(order), _ptr(Z), _stream(stream, y.device)))
+    return Z
 
 
 def rtr_backproject(h, dims, K, R, Z, Q, G=None, stream=None):

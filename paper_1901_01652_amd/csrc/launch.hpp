@@ -223,4 +223,33 @@ hipError_t launch_als_batch(const AlsItem* items, int count, int max_sweeps, dou
                             unsigned* status, const BatchLayout& lay, int mq, int gq,
                             hipStream_t s);
 
+// ---- mlp.hip --------------------------------------------------------------------------
+struct GemmArgs {  // C = op(A) op(B): A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn]
+  const float* A;
+  const float* B;
+  float* part;  // [slices][M][N]
+  int64_t M, N, K;
+  int64_t sam, sak, sbk, sbn;
+  int64_t kslice;
+};
+struct TrLoss4 {
+  int K[4];
+  int R[4];
+  int zpad;  // floats reserved for the cores in LDS
+};
+int gemm_slices(int64_t M, int64_t N, int64_t K, int64_t* kslice);
+hipError_t launch_gemm(bool bf, GemmArgs g, int slices, hipStream_t s);
+hipError_t launch_epilogue(const float* part, int slices, int64_t M, int64_t N,
+                           const float* bias, const float* mask, int mode, float* out,
+                           hipStream_t s);
+hipError_t launch_colsum(const float* G, int64_t M, int64_t N, float* out, hipStream_t s);
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, double lr,
+                       double b1, double b2, double eps, int t, hipStream_t s);
+hipError_t launch_to_f64(const float* x, int64_t n, int64_t per_row, const double* pn2, int order,
+                         double* y, hipStream_t s);
+hipError_t launch_normalize(const double* P, int64_t d, int rows, float* out, hipStream_t s);
+size_t tr_loss4_lds(const TrLoss4& sh);
+hipError_t launch_tr_loss4(const float* y, const float* tgt, int dout, const TrLoss4& sh,
+                           float gscale, int batch, float* loss, float* dy, hipStream_t s);
+
 }  // namespace rtr

@@ -1016,6 +1016,195 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
 }
 
 // ---------------------------------------------------------------------------------------
+namespace {
+
+rtr_status check_mlp(rtr_context* h, int32_t layers, const int32_t* sizes, int32_t batch,
+                     rtr_dtype compute) {
+  if (layers < 1 || layers > 16) return fail(h, RTR_ERR_INVALID_ARG, "layers must be in [1, 16]");
+  if (!sizes) return fail(h, RTR_ERR_INVALID_ARG, "sizes is NULL");
+  for (int l = 0; l <= layers; ++l)
+    if (sizes[l] < 1) return fail(h, RTR_ERR_INVALID_ARG, "layer sizes must be >= 1");
+  if (batch < 1) return fail(h, RTR_ERR_INVALID_ARG, "batch must be >= 1");
+  if (compute != RTR_F32 && compute != RTR_BF16)
+    return fail(h, RTR_ERR_UNSUPPORTED, "MLP compute must be RTR_F32 or RTR_BF16");
+  return RTR_OK;
+}
+
+// Partial-sum workspace large enough for every product of one pass.
+size_t gemm_ws_floats(int64_t M, int64_t N, int64_t K) {
+  int64_t ks = 0;
+  const int sl = rtr::gemm_slices(M, N, K, &ks);
+  return (size_t)sl * M * N;
+}
+
+rtr_status run_gemm(rtr_context* h, bool bf, const float* A, int64_t sam, int64_t sak,
+                    const float* B, int64_t sbk, int64_t sbn, int64_t M, int64_t N, int64_t K,
+                    float* part, const float* bias, const float* mask, int mode, float* out,
+                    hipStream_t s) {
+  rtr::GemmArgs g{};
+  g.A = A;
+  g.B = B;
+  g.part = part;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.sam = sam;
+  g.sak = sak;
+  g.sbk = sbk;
+  g.sbn = sbn;
+  const int sl = rtr::gemm_slices(M, N, K, &g.kslice);
+  HIP_TRY(rtr::launch_gemm(bf, g, sl, s), "gemm");
+  HIP_TRY(rtr::launch_epilogue(part, sl, M, N, bias, mask, mode, out, s), "gemm epilogue");
+  return RTR_OK;
+}
+
+}  // namespace
+
+rtr_status rtr_mlp_normalize(rtr_handle h, const double* P, int64_t dim, int32_t rows,
+                             float* out, void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if (!P || !out || dim < 1 || rows < 1) return fail(h, RTR_ERR_INVALID_ARG, "bad arguments");
+  HIP_TRY(rtr::launch_normalize(P, dim, rows, out, (hipStream_t)stream), "normalize");
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+rtr_status rtr_mlp_forward(rtr_handle h, int32_t layers, const int32_t* sizes,
+                           const float* const* W, const float* const* b, const float* x,
+                           int32_t batch, float* const* acts, float* y, rtr_dtype compute,
+                           void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  st = check_mlp(h, layers, sizes, batch, compute);
+  if (st) return st;
+  if (!W || !b || !x || !y || (layers > 1 && !acts))
+    return fail(h, RTR_ERR_INVALID_ARG, "W, b, x, y (and acts for hidden layers) required");
+  size_t need = 0;
+  for (int l = 0; l < layers; ++l) need = std::max(need, gemm_ws_floats(batch, sizes[l + 1], sizes[l]));
+  st = ensure_ws(h, need * sizeof(float) + 256);
+  if (st) return st;
+  float* part = (float*)h->ws;
+  hipStream_t s = (hipStream_t)stream;
+  const bool bf = compute == RTR_BF16;
+  for (int l = 0; l < layers; ++l) {
+    const float* in = l == 0 ? x : acts[l - 1];
+    float* out = l == layers - 1 ? y : acts[l];
+    st = run_gemm(h, bf, in, sizes[l], 1, W[l], sizes[l + 1], 1, batch, sizes[l + 1], sizes[l],
+                  part, b[l], nullptr, l < layers - 1 ? 1 : 0, out, s);
+    if (st) return st;
+  }
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+rtr_status rtr_mlp_tr_loss(rtr_handle h, const float* y, const float* target, int32_t batch,
+                           const int32_t* K, const int32_t* R, float grad_scale, float* loss,
+                           float* dy, void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if (!y || !target || !loss || !dy || !K || !R || batch < 1)
+    return fail(h, RTR_ERR_INVALID_ARG, "bad arguments");
+  rtr::TrLoss4 sh{};
+  int dout = 0;
+  for (int n = 0; n < 4; ++n) {
+    if (K[n] < 1 || R[n] < 1 || R[n] > 8) return fail(h, RTR_ERR_INVALID_ARG, "need K_n >= 1, 1 <= R_n <= 8");
+    sh.K[n] = K[n];
+    sh.R[n] = R[n];
+    dout += R[n] * K[n] * R[(n + 1) % 4];
+  }
+  sh.zpad = (dout + 63) & ~63;
+  const size_t lds = rtr::tr_loss4_lds(sh);
+  if (lds > 150 * 1024)
+    return fail(h, RTR_ERR_UNSUPPORTED, "K_1 K_2 K_3 K_4 too large for the per-sample work-group");
+  HIP_TRY(rtr::launch_tr_loss4(y, target, dout, sh, grad_scale, batch, loss, dy, (hipStream_t)stream),
+          "tr loss");
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+rtr_status rtr_mlp_backward(rtr_handle h, int32_t layers, const int32_t* sizes,
+                            const float* const* W, const float* x, int32_t batch,
+                            const float* const* acts, const float* dy, float* const* dW,
+                            float* const* db, rtr_dtype compute, void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  st = check_mlp(h, layers, sizes, batch, compute);
+  if (st) return st;
+  if (!W || !x || !dy || !dW || !db || (layers > 1 && !acts))
+    return fail(h, RTR_ERR_INVALID_ARG, "W, x, dy, dW, db (and acts for hidden layers) required");
+  size_t need = 0, gmax = 0;
+  for (int l = 0; l < layers; ++l) {
+    need = std::max(need, gemm_ws_floats(sizes[l], sizes[l + 1], batch));
+    if (l > 0) need = std::max(need, gemm_ws_floats(batch, sizes[l], sizes[l + 1]));
+    gmax = std::max(gmax, (size_t)batch * sizes[l]);
+  }
+  Carve plan(nullptr);
+  plan.take<float>(need);
+  plan.take<float>(gmax);
+  plan.take<float>(gmax);
+  st = ensure_ws(h, plan.off);
+  if (st) return st;
+  Carve c(h->ws);
+  float* part = c.take<float>(need);
+  float* gb[2] = {c.take<float>(gmax), c.take<float>(gmax)};
+  hipStream_t s = (hipStream_t)stream;
+  const bool bf = compute == RTR_BF16;
+  const float* g = dy;
+  for (int l = layers - 1; l >= 0; --l) {
+    const float* in = l == 0 ? x : acts[l - 1];
+    const int64_t ni = sizes[l], no = sizes[l + 1];
+    // dW_l = in^T g   (ni x no, contraction over the batch)
+    st = run_gemm(h, bf, in, 1, ni, g, no, 1, ni, no, batch, part, nullptr, nullptr, 0, dW[l], s);
+    if (st) return st;
+    HIP_TRY(rtr::launch_colsum(g, batch, no, db[l], s), "bias gradient");
+    if (l > 0) {
+      // g_{l-1} = (g W_l^T) * (acts[l-1] > 0)
+      float* gn = gb[l & 1];
+      st = run_gemm(h, bf, g, no, 1, W[l], 1, no, batch, ni, no, part, nullptr, acts[l - 1], 2, gn, s);
+      if (st) return st;
+      g = gn;
+    }
+  }
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+rtr_status rtr_mlp_adam(rtr_handle h, float* w, const float* g, float* m, float* v, int64_t n,
+                        double lr, double beta1, double beta2, double eps, int32_t step,
+                        void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if (!w || !g || !m || !v || n < 1 || step < 1) return fail(h, RTR_ERR_INVALID_ARG, "bad arguments");
+  HIP_TRY(rtr::launch_adam(w, g, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream), "adam");
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+rtr_status rtr_mlp_to_cores(rtr_handle h, const float* y, int64_t per_row, int32_t rows,
+                            const double* p_norm2, int32_t order, double* Z, void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if (!y || !Z || per_row < 1 || rows < 1 || order < 1) return fail(h, RTR_ERR_INVALID_ARG, "bad arguments");
+  HIP_TRY(rtr::launch_to_f64(y, per_row * rows, per_row, p_norm2, order, Z, (hipStream_t)stream),
+          "to f64");
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+// ---------------------------------------------------------------------------------------
 rtr_status rtr_backproject(rtr_handle h, int32_t order, const int64_t* dims, const int32_t* K,
                            const int32_t* R, const double* Z, const double* Q, double* G,
                            void* stream) try {
