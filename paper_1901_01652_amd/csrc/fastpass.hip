@@ -64,8 +64,10 @@ struct PassLayout {
   }
 };
 
+// The sketch with the 16-byte loader is held to 128 VGPRs (4 waves per SIMD: two
+// work-groups per CU, twice the loads in flight); the other variants would spill at that cap.
 template <bool BF, int OP, int LD>
-__global__ __launch_bounds__(kFpThreads, 2) void mode_pass_kernel(PassArgs p) {
+__global__ __launch_bounds__(kFpThreads, (LD == 0 && OP == 0 ? 4 : 2)) void mode_pass_kernel(PassArgs p) {
   using T = typename Mma<BF>::T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = (T*)smem_raw;
@@ -217,7 +219,12 @@ __global__ __launch_bounds__(kFpThreads, 2) void mode_pass_kernel(PassArgs p) {
     }
   };
 
-  int64_t t = blockIdx.x;
+  // XCD-aware order: work-groups are dealt round-robin to the 8 XCDs, so block b runs on
+  // XCD b % 8.  Renumber them so that each XCD takes a contiguous run of tiles per round;
+  // neighbouring tiles share the cache lines at their boundaries (rows that are not
+  // 128-byte aligned), and those lines are then fetched into one L2 instead of two.
+  const int64_t G = gridDim.x;
+  int64_t t = (G % 8 == 0) ? (int64_t)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
   if (t < p.ntiles) load(t);
   for (; t < p.ntiles; t += gridDim.x) {
     store();
