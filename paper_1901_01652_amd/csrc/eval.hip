@@ -8,6 +8,7 @@
 // its Rt row in registers.
 #include "common.hpp"
 #include "launch.hpp"
+#include "mfma.hpp"
 
 namespace rtr {
 
@@ -82,6 +83,104 @@ __global__ __launch_bounds__(256) void residual_kernel(const T* __restrict__ X, 
   }
 }
 
+// FP32 input: Psi tiles on the FP32 matrix cores.  L and R^T are first copied to FP32 with
+// the contraction padded to a multiple of 4.  A work-group owns a 128 (il) x 256 (ir) tile;
+// blocks run il-block fastest, so the 8 XCDs each reuse one R^T chunk from L2 and keep their
+// share of L resident.  Each wavefront covers 32 rows; per group of four 16-column tiles it
+// first loads its X values (in flight together) and then forms the Psi tiles,
+// accumulating (x - psi)^2 and x^2 in FP64.
+constexpr int kRtM = 128, kRtN = 256;
+
+__global__ __launch_bounds__(256) void pad_f32_kernel(const double* __restrict__ src, int64_t rows,
+                                                      int RR, int RRp, float* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * RRp) return;
+  const int64_t r = e / RRp;
+  const int k = (int)(e - r * RRp);
+  dst[e] = k < RR ? (float)src[r * RR + k] : 0.f;
+}
+
+__global__ __launch_bounds__(256, 3) void residual_mfma_kernel(const float* __restrict__ X,
+                                                            int64_t IL, int64_t IR, int RRp,
+                                                            const float* __restrict__ Lf,
+                                                            const float* __restrict__ Rf,
+                                                            int64_t nil, double* __restrict__ partial) {
+  extern __shared__ float rsm[];
+  __shared__ double red[16];
+  const int ldk = RRp + 1;
+  float* Ls = rsm;                 // kRtM x ldk
+  float* Rs = rsm + kRtM * ldk;    // kRtN x ldk
+  const int64_t ilb = blockIdx.x % nil, irb = blockIdx.x / nil;
+  const int64_t il0 = ilb * kRtM, ir0 = irb * kRtN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c16 = lane & 15;
+  for (int e = tid; e < kRtM * RRp; e += 256) {
+    const int r = e / RRp, k = e - r * RRp;
+    Ls[r * ldk + k] = (il0 + r < IL) ? Lf[(il0 + r) * RRp + k] : 0.f;
+  }
+  for (int e = tid; e < kRtN * RRp; e += 256) {
+    const int r = e / RRp, k = e - r * RRp;
+    Rs[r * ldk + k] = (ir0 + r < IR) ? Rf[(ir0 + r) * RRp + k] : 0.f;
+  }
+  __syncthreads();
+  double sres = 0.0, sx = 0.0;
+  // this lane's 8 rows of X (clamped to a valid row; out-of-range rows are masked below)
+  const float* xr[8];
+  unsigned rowok = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t row = il0 + 32 * w + 16 * (q >> 2) + 4 * g + (q & 3);
+    rowok |= (row < IL ? 1u : 0u) << q;
+    xr[q] = X + (row < IL ? row : 0) * IR;
+  }
+#pragma unroll 1
+  for (int jg = 0; jg < kRtN / 16; jg += 4) {
+    float xv[2][4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = ir0 + 16 * (jg + j) + c16;
+      const bool cok = col < IR;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        xv[q >> 2][j][q & 3] = (cok && ((rowok >> q) & 1u)) ? xr[q][col] : 0.f;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int i = t >> 2, j = t & 3;
+      const float* a = Ls + (32 * w + 16 * i + c16) * ldk + g;
+      const float* b = Rs + (16 * (jg + j) + c16) * ldk + g;
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 3
+      for (int k0 = 0; k0 < RRp; k0 += 4)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k0], b[k0], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double x = (double)xv[i][j][r];
+        const double d = x - (double)acc[r];
+        sres += d * d;
+        sx += x * x;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // rows or columns beyond the tensor hold x = 0 and psi = 0 (zero L / R^T rows): no effect
+  sres = block_sum(sres, red);
+  sx = block_sum(sx, red);
+  if (tid == 0) {
+    partial[2 * blockIdx.x] = sres;
+    partial[2 * blockIdx.x + 1] = sx;
+  }
+}
+
+int64_t residual_blocks(bool f32, int64_t IL, int64_t IR) {
+  if (f32) return ((IL + kRtM - 1) / kRtM) * ((IR + kRtN - 1) / kRtN);
+  const int64_t ir_tiles = (IR + 255) / 256;
+  int64_t ilb = kResBlocks / ir_tiles;
+  if (ilb < 1) ilb = 1;
+  if (ilb > IL) ilb = IL;
+  const int64_t il_per = (IL + ilb - 1) / ilb;
+  return ir_tiles * ((IL + il_per - 1) / il_per);
+}
+
 __global__ __launch_bounds__(256) void residual_final_kernel(const double* __restrict__ partial,
                                                              int count, double* __restrict__ out) {
   __shared__ double red[16];
@@ -99,26 +198,34 @@ __global__ __launch_bounds__(256) void residual_final_kernel(const double* __res
 }
 
 hipError_t launch_residual(bool f32, const void* X, int64_t IL, int64_t IR, int RR,
-                           const double* L, const double* RtT, double* partial, double* out,
-                           hipStream_t s) {
-  const int64_t ir_tiles = (IR + 255) / 256;
-  int64_t ilb = kResBlocks / ir_tiles;
-  if (ilb < 1) ilb = 1;
-  if (ilb > IL) ilb = IL;
-  const int64_t il_per = (IL + ilb - 1) / ilb;
-  ilb = (IL + il_per - 1) / il_per;
-  const unsigned blocks = (unsigned)(ir_tiles * ilb);
-  const bool reg = RR <= kResRR;
+                           const double* L, const double* RtT, double* partial, float* lr32,
+                           double* out, hipStream_t s) {
   prof_begin("residual", s);
+  unsigned blocks;
   if (f32) {
-    if (reg)
-      hipLaunchKernelGGL((residual_kernel<float, true>), dim3(blocks), dim3(256), 0, s,
-                         (const float*)X, IL, IR, RR, L, RtT, ir_tiles, il_per, partial);
-    else
-      hipLaunchKernelGGL((residual_kernel<float, false>), dim3(blocks), dim3(256), 0, s,
-                         (const float*)X, IL, IR, RR, L, RtT, ir_tiles, il_per, partial);
+    const int RRp = (RR + 3) & ~3;
+    float* Lf = lr32;
+    float* Rf = lr32 + IL * RRp;
+    hipLaunchKernelGGL(pad_f32_kernel, dim3((unsigned)((IL * RRp + 255) / 256)), dim3(256), 0, s, L,
+                       IL, RR, RRp, Lf);
+    hipLaunchKernelGGL(pad_f32_kernel, dim3((unsigned)((IR * RRp + 255) / 256)), dim3(256), 0, s,
+                       RtT, IR, RR, RRp, Rf);
+    const int64_t nil = (IL + kRtM - 1) / kRtM;
+    blocks = (unsigned)residual_blocks(true, IL, IR);
+    const size_t lds = (size_t)(kRtM + kRtN) * (RRp + 1) * sizeof(float);
+    hipError_t e = hipFuncSetAttribute((const void*)residual_mfma_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(residual_mfma_kernel, dim3(blocks), dim3(256), lds, s, (const float*)X, IL,
+                       IR, RRp, Lf, Rf, nil, partial);
   } else {
-    if (reg)
+    const int64_t ir_tiles = (IR + 255) / 256;
+    int64_t ilb = kResBlocks / ir_tiles;
+    if (ilb < 1) ilb = 1;
+    if (ilb > IL) ilb = IL;
+    const int64_t il_per = (IL + ilb - 1) / ilb;
+    blocks = (unsigned)residual_blocks(false, IL, IR);
+    if (RR <= kResRR)
       hipLaunchKernelGGL((residual_kernel<double, true>), dim3(blocks), dim3(256), 0, s,
                          (const double*)X, IL, IR, RR, L, RtT, ir_tiles, il_per, partial);
     else

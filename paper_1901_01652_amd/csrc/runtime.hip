@@ -1253,16 +1253,20 @@ rtr_status rtr_residual(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t 
   for (int n = 0; n < hm; ++n) IL *= dims[n];
   for (int n = hm; n < order; ++n) IR *= dims[n];
   const int RR = R[0] * R[hm];
-  const int64_t ir_tiles = (IR + 255) / 256;
+  const bool f32 = x_dtype == RTR_F32;
+  const int64_t nblocks = rtr::residual_blocks(f32, IL, IR);
+  const int RRp = (RR + 3) & ~3;
   Carve plan(nullptr);
   plan.take<double>((size_t)IL * RR);
   plan.take<double>((size_t)IR * RR);
-  plan.take<double>((size_t)2 * (2048 + ir_tiles));
+  plan.take<double>((size_t)2 * nblocks);
+  plan.take<float>(f32 ? (size_t)(IL + IR) * RRp : 1);
   if ((st = ensure_ws(h, plan.off + 256))) return st;
   Carve cv(h->ws);
   double* L = cv.take<double>((size_t)IL * RR);
   double* RtT = cv.take<double>((size_t)IR * RR);
-  double* partial = cv.take<double>((size_t)2 * (2048 + ir_tiles));
+  double* partial = cv.take<double>((size_t)2 * nblocks);
+  float* lr32 = cv.take<float>(f32 ? (size_t)(IL + IR) * RRp : 1);
   size_t goff[RTR_MAX_ORDER];
   size_t go = 0;
   for (int n = 0; n < order; ++n) {
@@ -1286,8 +1290,7 @@ rtr_status rtr_residual(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t 
   }
   HIP_TRY(rtr::launch_chain(cl, IL, 0, L, nullptr, s), "chain");
   HIP_TRY(rtr::launch_chain(cr, IR, 1, RtT, nullptr, s), "chain");
-  HIP_TRY(rtr::launch_residual(x_dtype == RTR_F32, X, IL, IR, RR, L, RtT, partial, out, s),
-          "residual");
+  HIP_TRY(rtr::launch_residual(f32, X, IL, IR, RR, L, RtT, partial, lr32, out, s), "residual");
   return RTR_OK;
 } catch (...) {
   return fail(h, RTR_ERR_INTERNAL, "unexpected exception");

@@ -166,8 +166,12 @@ def test_als_tolerance_stop(h):
     assert rel(tr.cpu().numpy()[:n], tro) < 1e-10
 
 
-def test_backproject_and_residual(h):
-    dims, K, R = (13, 11, 9, 10), (5, 4, 3, 6), (2, 3, 2, 3)
+@pytest.mark.parametrize("dims,K,R", [((13, 11, 9, 10), (5, 4, 3, 6), (2, 3, 2, 3)),
+                                      ((20, 15, 30, 12), (4, 4, 4, 4), (3, 2, 4, 2))])
+def test_backproject_and_residual(h, dims, K, R):
+    """FP64 residual to 1e-10; FP32 input (Psi on the FP32 matrix cores, sums in FP64) to the
+    FP32 path's 1e-5 on the residual.  The second shape spans several 128 x 256 tiles with
+    ragged edges on both sides."""
     say("backproject/residual", dims, K, R)
     rng = np.random.default_rng(7)
     Qs = [np.linalg.qr(rng.standard_normal((d, k)))[0] for d, k in zip(dims, K)]
@@ -178,13 +182,13 @@ def test_backproject_and_residual(h):
     for a, b in zip(Gg, Go):
         assert rel(a, b) < 1e-13
     X = ot.tr_full(Go) + 0.1 * rng.standard_normal(dims)
-    for dt in (torch.float64, torch.float32):
+    for dt, tol in ((torch.float64, 1e-10), (torch.float32, 1e-5)):
         Xd = torch.as_tensor(X).to(dt).to(DEV)
         out = rt.rtr_residual(h, Xd, R, G).cpu().numpy()
         Xh = Xd.double().cpu().numpy()
         assert abs(out[1] - np.sum(Xh ** 2)) < 1e-12 * np.sum(Xh ** 2)
         r2 = ot.frob(Xh - ot.tr_full(Go)) ** 2
-        assert abs(out[0] - r2) < 1e-10 * r2
+        assert abs(out[0] - r2) < tol * r2, (dt, out[0], r2)
 
 
 def run_end_to_end(h, w, X, compute=None):
