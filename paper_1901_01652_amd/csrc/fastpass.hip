@@ -64,10 +64,12 @@ struct PassLayout {
   }
 };
 
-// The sketch with the 16-byte loader is held to 128 VGPRs (4 waves per SIMD: two
-// work-groups per CU, twice the loads in flight); the other variants would spill at that cap.
-template <bool BF, int OP, int LD>
-__global__ __launch_bounds__(kFpThreads, (LD == 0 && OP == 0 ? 4 : 2)) void mode_pass_kernel(PassArgs p) {
+// AQ: 16x16 output tiles of Y per wavefront (4 covers In <= 128 x K <= 64 or In <= 256 x
+// K <= 32, 8 the rest).  With the 16-byte loader and AQ = 4 the kernel is held to 128 VGPRs
+// (4 waves per SIMD: two work-groups per CU, twice the loads in flight); the other variants
+// would spill at that cap.
+template <bool BF, int OP, int LD, int AQ>
+__global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode_pass_kernel(PassArgs p) {
   using T = typename Mma<BF>::T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = (T*)smem_raw;
@@ -89,9 +91,9 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && OP == 0 ? 4 : 2)) void mode
     }
   }
 
-  f32x4 acc[8];  // output tiles q = wid + 8 s of the (MT x NT) grid
+  f32x4 acc[AQ];  // output tiles q = wid + 8 s of the (MT x NT) grid
 #pragma unroll
-  for (int s = 0; s < 8; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int s = 0; s < AQ; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   float4 buf[8];
   auto load = [&](int64_t t) {
@@ -250,7 +252,7 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && OP == 0 ? 4 : 2)) void mode
     }
     // Y [In x K] += T [In x 64] * (M or W) [64 x K]
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
+    for (int s = 0; s < AQ; ++s) {
       const int q = wid + 8 * s;
       if (q < MT * NT) {
         const int mt = q / NT, nt = q % NT;
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && OP == 0 ? 4 : 2)) void mode
     __syncthreads();
   }
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
+  for (int s = 0; s < AQ; ++s) {
     const int q = wid + 8 * s;
     if (q < MT * NT) {
       const int mt = q / NT, nt = q % NT;
@@ -278,6 +280,12 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && OP == 0 ? 4 : 2)) void mode
 static int ld_t(bool bf) { return bf ? kFpTJ + 8 : kFpTJ + 2; }
 static int k_i(bool bf, int64_t In) { return bf ? (int)((In + 31) / 32 * 32) : (int)((In + 3) / 4 * 4); }
 static int ld_i(bool bf, int64_t In) { return k_i(bf, In) + (bf ? 8 : 2); }
+
+// Output tiles per wavefront needed for an In x K result over 8 wavefronts.
+static int acc_slots(int64_t In, int K) {
+  const int64_t tiles = ((In + 15) / 16) * ((K + 15) / 16);
+  return tiles <= 32 ? 4 : 8;
+}
 
 static size_t pass_lds(bool bf, int op, int64_t In, int K) {
   const int ldT = ld_t(bf), ldI = ld_i(bf, In);
@@ -297,9 +305,11 @@ bool fast_pass_supported(Arith ar, const ModeView& v, int K, int op) {
   return pass_lds(ar == kBF16, op, v.In, K) <= kFpLdsMax;
 }
 
-static const void* pass_fn(bool bf, int op, int loader) {
+static const void* pass_fn(bool bf, int op, int loader, int aq) {
 #define RTR_FP_SEL(B_, O_, L_) \
-  if (bf == B_ && op == O_ && loader == L_) return (const void*)mode_pass_kernel<B_, O_, L_>;
+  if (bf == B_ && op == O_ && loader == L_)                                        \
+    return aq == 4 ? (const void*)mode_pass_kernel<B_, O_, L_, 4>                  \
+                   : (const void*)mode_pass_kernel<B_, O_, L_, 8>;
   RTR_FP_SEL(true, 0, 0) RTR_FP_SEL(true, 0, 1) RTR_FP_SEL(true, 0, 2)
   RTR_FP_SEL(true, 1, 0) RTR_FP_SEL(true, 1, 1) RTR_FP_SEL(true, 1, 2)
   RTR_FP_SEL(false, 0, 0) RTR_FP_SEL(false, 0, 1) RTR_FP_SEL(false, 0, 2)
@@ -321,7 +331,7 @@ int64_t fast_pass_grid(Arith ar, const ModeView& v, int K, int op, const void* X
   const int64_t J = v.A * v.B;
   const int64_t ntiles = (J + kFpTJ - 1) / kFpTJ;
   const size_t lds = pass_lds(bf, op, v.In, K);
-  const void* fn = pass_fn(bf, op, pick_loader(X, v));
+  const void* fn = pass_fn(bf, op, pick_loader(X, v), acc_slots(v.In, K));
   int dev = 0, cus = 256, per_cu = 1;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -356,7 +366,7 @@ hipError_t launch_fast_pass(Arith ar, int op, const void* X, const ModeView& v, 
   p.ldI = ld_i(bf, v.In);
   p.kI = k_i(bf, v.In);
   const size_t lds = pass_lds(bf, op, v.In, K);
-  const void* fn = pass_fn(bf, op, p.loader);
+  const void* fn = pass_fn(bf, op, p.loader, acc_slots(v.In, K));
   if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
