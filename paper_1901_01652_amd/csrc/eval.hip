@@ -113,13 +113,24 @@ __global__ __launch_bounds__(256, 3) void residual_mfma_kernel(const float* __re
   const int64_t ilb = blockIdx.x % nil, irb = blockIdx.x / nil;
   const int64_t il0 = ilb * kRtM, ir0 = irb * kRtN;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c16 = lane & 15;
-  for (int e = tid; e < kRtM * RRp; e += 256) {
-    const int r = e / RRp, k = e - r * RRp;
-    Ls[r * ldk + k] = (il0 + r < IL) ? Lf[(il0 + r) * RRp + k] : 0.f;
-  }
-  for (int e = tid; e < kRtN * RRp; e += 256) {
-    const int r = e / RRp, k = e - r * RRp;
-    Rs[r * ldk + k] = (ir0 + r < IR) ? Rf[(ir0 + r) * RRp + k] : 0.f;
+  {
+    // 16-byte copies: thread t owns column group t % q4 of every (256 / q4)-th row
+    const int q4 = RRp >> 2, k4 = tid % q4, rstep = 256 / q4;
+    int r = tid / q4;
+    if (r < rstep) {
+      for (int rr = r; rr < kRtM + kRtN; rr += rstep) {
+        const bool isL = rr < kRtM;
+        const int64_t src_row = isL ? il0 + rr : ir0 + (rr - kRtM);
+        const bool ok = src_row < (isL ? IL : IR);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ok) v = *(const float4*)((isL ? Lf : Rf) + src_row * RRp + 4 * k4);
+        float* d = rsm + rr * ldk + 4 * k4;  // Ls rows, then Rs rows
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
+      }
+    }
   }
   __syncthreads();
   double sres = 0.0, sx = 0.0;
@@ -137,12 +148,20 @@ __global__ __launch_bounds__(256, 3) void residual_mfma_kernel(const float* __re
     float xv[2][4][4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
+      // unconditional loads from clamped (valid) addresses, masked by a multiply afterwards
+      // (a select lets the compiler sink each load into a branch with its own wait), so that
+      // the 32 loads issue back to back
       const int64_t col = ir0 + 16 * (jg + j) + c16;
       const bool cok = col < IR;
+      const int64_t colc = cok ? col : IR - 1;
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        xv[q >> 2][j][q & 3] = (cok && ((rowok >> q) & 1u)) ? xr[q][col] : 0.f;
+      for (int q = 0; q < 8; ++q) {
+        const float mk = (cok && ((rowok >> q) & 1u)) ? 1.f : 0.f;
+        xv[q >> 2][j][q & 3] = xr[q][colc] * mk;  // clamped entries are finite tensor values
+      }
     }
+    // keep all 32 loads of the group ahead of the products (in flight together)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int i = t >> 2, j = t & 3;
@@ -171,8 +190,11 @@ __global__ __launch_bounds__(256, 3) void residual_mfma_kernel(const float* __re
   }
 }
 
-int64_t residual_blocks(bool f32, int64_t IL, int64_t IR) {
-  if (f32) return ((IL + kRtM - 1) / kRtM) * ((IR + kRtN - 1) / kRtN);
+// The matrix-core residual keeps a (128 + 256) x (RR + 1) FP32 tile in LDS: RR <= 96.
+static bool residual_mfma_ok(bool f32, int RR) { return f32 && ((RR + 3) & ~3) <= 96; }
+
+int64_t residual_blocks(bool f32, int64_t IL, int64_t IR, int RR) {
+  if (residual_mfma_ok(f32, RR)) return ((IL + kRtM - 1) / kRtM) * ((IR + kRtN - 1) / kRtN);
   const int64_t ir_tiles = (IR + 255) / 256;
   int64_t ilb = kResBlocks / ir_tiles;
   if (ilb < 1) ilb = 1;
@@ -202,7 +224,7 @@ hipError_t launch_residual(bool f32, const void* X, int64_t IL, int64_t IR, int 
                            double* out, hipStream_t s) {
   prof_begin("residual", s);
   unsigned blocks;
-  if (f32) {
+  if (residual_mfma_ok(f32, RR)) {
     const int RRp = (RR + 3) & ~3;
     float* Lf = lr32;
     float* Rf = lr32 + IL * RRp;
@@ -211,7 +233,7 @@ hipError_t launch_residual(bool f32, const void* X, int64_t IL, int64_t IR, int 
     hipLaunchKernelGGL(pad_f32_kernel, dim3((unsigned)((IR * RRp + 255) / 256)), dim3(256), 0, s,
                        RtT, IR, RR, RRp, Rf);
     const int64_t nil = (IL + kRtM - 1) / kRtM;
-    blocks = (unsigned)residual_blocks(true, IL, IR);
+    blocks = (unsigned)residual_blocks(true, IL, IR, RR);
     const size_t lds = (size_t)(kRtM + kRtN) * (RRp + 1) * sizeof(float);
     hipError_t e = hipFuncSetAttribute((const void*)residual_mfma_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -224,8 +246,11 @@ hipError_t launch_residual(bool f32, const void* X, int64_t IL, int64_t IR, int 
     if (ilb < 1) ilb = 1;
     if (ilb > IL) ilb = IL;
     const int64_t il_per = (IL + ilb - 1) / ilb;
-    blocks = (unsigned)residual_blocks(false, IL, IR);
-    if (RR <= kResRR)
+    blocks = (unsigned)residual_blocks(f32, IL, IR, RR);
+    if (f32)
+      hipLaunchKernelGGL((residual_kernel<float, false>), dim3(blocks), dim3(256), 0, s,
+                         (const float*)X, IL, IR, RR, L, RtT, ir_tiles, il_per, partial);
+    else if (RR <= kResRR)
       hipLaunchKernelGGL((residual_kernel<double, true>), dim3(blocks), dim3(256), 0, s,
                          (const double*)X, IL, IR, RR, L, RtT, ir_tiles, il_per, partial);
     else

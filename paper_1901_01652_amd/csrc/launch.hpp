@@ -179,7 +179,7 @@ hipError_t launch_backproject(const double* Z, const double* Q, int Ra, int K, i
 // out[0] = sum (x - tr(L[il] Rt[ir]))^2, out[1] = sum x^2 (two-stage, fixed order).
 // ``partial`` holds 2 residual_blocks(...) doubles; for FP32 X, ``lr32`` holds
 // (IL + IR) * ceil4(RR) floats (FP32 copies of L and R^T).
-int64_t residual_blocks(bool f32, int64_t IL, int64_t IR);
+int64_t residual_blocks(bool f32, int64_t IL, int64_t IR, int RR);
 hipError_t launch_residual(bool f32, const void* X, int64_t IL, int64_t IR, int RR,
                            const double* L, const double* RtT, double* partial, float* lr32,
                            double* out, hipStream_t s);

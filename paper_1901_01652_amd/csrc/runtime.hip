@@ -1254,7 +1254,7 @@ rtr_status rtr_residual(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t 
   for (int n = hm; n < order; ++n) IR *= dims[n];
   const int RR = R[0] * R[hm];
   const bool f32 = x_dtype == RTR_F32;
-  const int64_t nblocks = rtr::residual_blocks(f32, IL, IR);
+  const int64_t nblocks = rtr::residual_blocks(f32, IL, IR, RR);
   const int RRp = (RR + 3) & ~3;
   Carve plan(nullptr);
   plan.take<double>((size_t)IL * RR);
