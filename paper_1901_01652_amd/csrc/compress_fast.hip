@@ -19,7 +19,7 @@
 
 namespace rtr {
 
-constexpr int kCsTR = 32;        // rows of the slab per block
+constexpr int kCsTR = 32;        // smallest rows-per-item block (see cs_tr)
 constexpr int kCsThreads = 512;  // 8 wavefronts
 constexpr int kCsMaxI2 = 512;
 constexpr int kCsMaxK = 64;
@@ -34,7 +34,7 @@ struct CsArgs {
   int ldX, kI2, ldS, vec4;
 };
 
-template <bool BF>
+template <bool BF, int TR>
 struct CsLayout {
   using T = typename Mma<BF>::T;
   int oXh, oXl, oQ2h, oQ2l, oQ1h, oQ1l, oSh, oSl, total;
@@ -44,8 +44,8 @@ struct CsLayout {
     const int K1p = (K1 + 15) / 16 * 16, K2p = (K2 + 15) / 16 * 16;
     const int np = BF ? 2 : 1;  // hi and lo parts
     int o = 0;
-    oXh = o; o = up(o + kCsTR * ldX);
-    oXl = o; o = up(o + (np - 1) * kCsTR * ldX);
+    oXh = o; o = up(o + TR * ldX);
+    oXl = o; o = up(o + (np - 1) * TR * ldX);
     oQ2h = o; o = up(o + K2p * ldX);
     oQ2l = o; o = up(o + (np - 1) * K2p * ldX);
     oQ1h = o; o = up(o + K1p * ldS);
@@ -79,12 +79,13 @@ __device__ __forceinline__ f32x4 mma3(const typename Mma<BF>::T* Ah, const typen
   return acc;
 }
 
-template <bool BF>
+// TR: rows of the slab per item (64 when TR * I2 fits the register staging, else 32).
+template <bool BF, int TR>
 __global__ __launch_bounds__(kCsThreads, 2) void compress_slab_kernel(CsArgs p) {
   using T = typename Mma<BF>::T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = (T*)smem_raw;
-  const CsLayout<BF> L(p.K1, p.K2, p.ldX, p.ldS);
+  const CsLayout<BF, TR> L(p.K1, p.K2, p.ldX, p.ldS);
   T* Xh = sm + L.oXh;
   T* Xl = sm + L.oXl;
   T* Q2h = sm + L.oQ2h;
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(kCsThreads, 2) void compress_slab_kernel(CsArgs p) 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int I1 = p.I1, I2 = p.I2, K1 = p.K1, K2 = p.K2, ldX = p.ldX, ldS = p.ldS;
   const int K1T = (K1 + 15) / 16, K2T = (K2 + 15) / 16;
-  const int nblk = (I1 + kCsTR - 1) / kCsTR;
+  const int nblk = (I1 + TR - 1) / TR;
 
   for (int x = tid; x < L.total; x += kCsThreads) sm[x] = Mma<BF>::cvt(0.f);
   __syncthreads();
@@ -112,8 +113,8 @@ __global__ __launch_bounds__(kCsThreads, 2) void compress_slab_kernel(CsArgs p) 
   float4 buf[8];
   auto load = [&](int64_t item) {
     const int64_t a = item / nblk;
-    const int r0 = (int)(item % nblk) * kCsTR;
-    const int rows = min(kCsTR, I1 - r0);
+    const int r0 = (int)(item % nblk) * TR;
+    const int rows = min(TR, I1 - r0);
     const float* src = p.X + (a * I1 + r0) * (int64_t)I2;
     const int n = rows * I2;
     if (p.vec4) {
@@ -135,27 +136,37 @@ __global__ __launch_bounds__(kCsThreads, 2) void compress_slab_kernel(CsArgs p) 
       }
     }
   };
+  // (row, column) of the first of this thread's 4 elements in each of its 8 float4 slots,
+  // fixed for every item: the stores below advance it with a carry instead of dividing
+  int il_s[8], c_s[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int x0 = 4 * (tid + kCsThreads * s);
+    il_s[s] = x0 / I2;
+    c_s[s] = x0 - il_s[s] * I2;
+  }
   auto store = [&](int64_t item) {
-    const int r0 = (int)(item % nblk) * kCsTR;
-    const int rows = min(kCsTR, I1 - r0);
-    const int n = kCsTR * I2;
+    const int r0 = (int)(item % nblk) * TR;
+    const int rows = min(TR, I1 - r0);
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-      const int f = tid + kCsThreads * s;
       const float vv[4] = {buf[s].x, buf[s].y, buf[s].z, buf[s].w};
+      int il = il_s[s], c = c_s[s];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int x = 4 * f + e;
-        if (x < n) {
-          const int il = x / I2, c = x % I2;
+        if (il < TR) {
           T hi, lo;
           split<BF>(il < rows ? vv[e] : 0.f, hi, lo);
           Xh[il * ldX + c] = hi;
           if (BF) Xl[il * ldX + c] = lo;
         }
+        if (++c == I2) {
+          c = 0;
+          ++il;
+        }
       }
     }
-    for (int x = tid; x < kCsTR * K1; x += kCsThreads) {
+    for (int x = tid; x < TR * K1; x += kCsThreads) {
       const int il = x / K1, k = x % K1;
       T hi, lo;
       split<BF>(il < rows ? (float)p.Q1[(int64_t)(r0 + il) * K1 + k] : 0.f, hi, lo);
@@ -177,9 +188,9 @@ __global__ __launch_bounds__(kCsThreads, 2) void compress_slab_kernel(CsArgs p) 
     store(item);
     __syncthreads();
     if (item + 1 < item_end) load(item + 1);
-    // S [32 x K2] = X_blk [32 x I2] * Q2 [I2 x K2]; tile (mt, nt) on wave mt*K2T + nt
-    if (wid < 2 * K2T) {
-      const int mt = wid / K2T, nt = wid % K2T;
+    // S [TR x K2] = X_blk [TR x I2] * Q2 [I2 x K2]; tiles q = wid + 8 s, (mt, nt) = q / K2T
+    for (int q = wid; q < (TR / 16) * K2T; q += 8) {
+      const int mt = q / K2T, nt = q % K2T;
       f32x4 sacc = mma3<BF>(Xh + mt * 16 * ldX, Xl + mt * 16 * ldX, ldX, Q2h + nt * 16 * ldX,
                             Q2l + nt * 16 * ldX, ldX, p.kI2, f32x4{0.f, 0.f, 0.f, 0.f});
       const int col = nt * 16 + (lane & 15);  // k2
@@ -200,7 +211,7 @@ __global__ __launch_bounds__(kCsThreads, 2) void compress_slab_kernel(CsArgs p) 
       if (q < K1T * K2T) {
         const int mt = q / K2T, nt = q % K2T;
         tacc[s] = mma3<BF>(Q1h + mt * 16 * ldS, Q1l + mt * 16 * ldS, ldS, Sh + nt * 16 * ldS,
-                           Sl + nt * 16 * ldS, ldS, kCsTR, tacc[s]);
+                           Sl + nt * 16 * ldS, ldS, TR, tacc[s]);
       }
     }
     if ((item + 1) % nblk == 0) {  // slab done: write T[a], reset
@@ -225,16 +236,23 @@ __global__ __launch_bounds__(kCsThreads, 2) void compress_slab_kernel(CsArgs p) 
 }
 
 // ---------------------------------------------------------------------------------------
+// Rows per item: 64 when 64 x I2 fits the register staging (32 float4 per thread), else 32.
+static int cs_tr(int64_t I2) { return 64 * I2 <= 4LL * 8 * kCsThreads ? 64 : 32; }
+
 static void cs_dims(bool bf, int I2, int& ldX, int& kI2, int& ldS) {
   kI2 = bf ? (I2 + 31) / 32 * 32 : (I2 + 3) / 4 * 4;
   ldX = kI2 + (bf ? 8 : 2);
-  ldS = kCsTR + (bf ? 8 : 2);
+  ldS = cs_tr(I2) + (bf ? 8 : 2);
 }
 
 static size_t cs_lds(bool bf, int I2, int K1, int K2) {
   int ldX, kI2, ldS;
   cs_dims(bf, I2, ldX, kI2, ldS);
-  const int total = bf ? CsLayout<true>(K1, K2, ldX, ldS).total : CsLayout<false>(K1, K2, ldX, ldS).total;
+  const bool tr64 = cs_tr(I2) == 64;
+  const int total = bf ? (tr64 ? CsLayout<true, 64>(K1, K2, ldX, ldS).total
+                               : CsLayout<true, 32>(K1, K2, ldX, ldS).total)
+                       : (tr64 ? CsLayout<false, 64>(K1, K2, ldX, ldS).total
+                               : CsLayout<false, 32>(K1, K2, ldX, ldS).total);
   return (size_t)total * (bf ? 2 : 4);
 }
 
@@ -263,7 +281,11 @@ hipError_t launch_compress_slab(Arith ar, const void* X, int64_t A, int64_t I1, 
   cs_dims(bf, (int)I2, p.ldX, p.kI2, p.ldS);
   p.vec4 = (((uintptr_t)X & 15) == 0) && (I2 % 4 == 0);
   const size_t lds = cs_lds(bf, (int)I2, K1, K2);
-  const void* fn = bf ? (const void*)compress_slab_kernel<true> : (const void*)compress_slab_kernel<false>;
+  const bool tr64 = cs_tr(I2) == 64;
+  const void* fn = bf ? (tr64 ? (const void*)compress_slab_kernel<true, 64>
+                              : (const void*)compress_slab_kernel<true, 32>)
+                      : (tr64 ? (const void*)compress_slab_kernel<false, 64>
+                              : (const void*)compress_slab_kernel<false, 32>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int dev = 0, cus = 256, per_cu = 1;
