@@ -287,20 +287,25 @@ __global__ __launch_bounds__(512) void als_solve2_kernel(AlsSolveArgs g) {
     __syncthreads();
     if (*g.done || g.report_only) return;
   }
-  // fixed-order sum of the partials, sixteen loads in flight
+  // fixed-order sum of the partials in batches of 32 loads issued together; the last batch
+  // reads clamped (valid) records and masks them by a multiply, so no record is fetched by
+  // a lone dependent load
   for (int o = tid; o < nstore; o += nth) {
     const double* src = g.part + o;
     const int64_t st = nstore + 1;
+    const int last = g.nparts - 1;
     double s = 0.0;
-    int c = 0;
-    for (; c + 16 <= g.nparts; c += 16) {
-      double v[16];
+    for (int c = 0; c < g.nparts; c += 32) {
+      double v[32];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) v[e] = src[(c + e) * st];
+      for (int e = 0; e < 32; ++e) {
+        const int cc = c + e <= last ? c + e : last;
+        v[e] = src[(int64_t)cc * st] * (c + e <= last ? 1.0 : 0.0);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // all 32 loads ahead of the sums
 #pragma unroll
-      for (int e = 0; e < 16; ++e) s += v[e];
+      for (int e = 0; e < 32; ++e) s += v[e];
     }
-    for (; c < g.nparts; ++c) s += src[c * st];
     sm[o] = s;
   }
   if (tid == 0) failed = 0;
