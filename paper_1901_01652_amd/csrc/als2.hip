@@ -40,9 +40,19 @@ static __host__ __device__ inline int pad16(int v) { return (v + 15) / 16 * 16; 
 static __host__ __device__ inline int64_t zwords(int64_t z) { return (z + 1) / 2 * 2; }
 
 // ---------------------------------------------------------------------------------------
+__device__ void transfer_gram(const double* __restrict__ Z, int64_t ztotal, int N, int n,
+                              const int64_t* zoff, const int* Kc, const int* Rc, int tdim, int Ra,
+                              int Rb, double* xt, double* G);
+
 template <int RM, int TJ, int kAcTiles>
 __global__ __launch_bounds__(kAcThreads) void als_accum_kernel(AlsArgs2 g) {
   extern __shared__ __align__(16) double sm[];
+  if (g.gram_extra && blockIdx.x == gridDim.x - 1) {  // the Gram, beside the accumulation
+    if (*g.done) return;
+    transfer_gram(g.Z, g.ztotal, g.N, g.n, g.zoffs, g.Kc, g.Rc, g.tdim, g.Ra, g.Rb, sm,
+                  g.gram_out);
+    return;
+  }
   const int RR = g.RR, Kn = g.Kn, Ra = g.Ra, Rb = g.Rb;
   const int NT = pad16(RR) / 16, MT = pad16(Kn) / 16;
   const int ldB = pad16(RR) + 1, ldL = TJ + 1;
@@ -259,6 +269,86 @@ __device__ void gemm_f64(const double* A, int lda, int ska, const double* B, int
   }
 }
 
+// Gram of core n's least squares from transfer matrices (every core except n is read):
+// sum_j S_j (x) S_j = E_{n+1} .. E_{n-1}.  xt: LDS workspace of 3 tdim^2 + 64 tdim + ztotal
+// doubles; G: RR x RR output (LDS or global).  Called by a whole work-group.
+__device__ void transfer_gram(const double* __restrict__ Z, int64_t ztotal, int N, int n,
+                              const int64_t* zoff, const int* Kc, const int* Rc, int tdim, int Ra,
+                              int Rb, double* xt, double* G) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int RR = Ra * Rb;
+  // Gram from transfer matrices: sum_j S_j (x) S_j = E_{n+1} E_{n+2} ... E_{n-1},
+  // E_m[(p,p'),(q,q')] = sum_i Z_m[p,i,q] Z_m[p',i,q']; entry [(b,b'),(a,a')] of the
+  // product is Gram[(a,b),(a',b')].  Buffers are D x D (D = pad16(max R^2)), zero padded.
+  const int D = tdim;
+  double* Tm = xt;
+  double* Em = Tm + D * D;
+  double* Tn = Em + D * D;
+  double* Fz = Tn + D * D;   // Kp x W slice matrix, Kp <= 64
+  double* Zs = Fz + 64 * D;  // cores
+  {
+    double zt[12];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+      const int64_t x = tid + (int64_t)e * nth;
+      zt[e] = x < ztotal ? Z[x] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+      const int64_t x = tid + (int64_t)e * nth;
+      if (x < ztotal) Zs[x] = zt[e];
+    }
+  }
+  for (int x = tid; x < 3 * D * D; x += nth) Tm[x] = 0.0;
+  __syncthreads();
+  const int Rn1 = Rc[(n + 1) % N];
+  for (int t = 1; t < N; ++t) {
+    const int m = (n + t) % N;
+    const int Rp = Rc[m], Rq = Rc[(m + 1) % N], Km = Kc[m];
+    const int Kp = (Km + 3) / 4 * 4, W = pad16(Rp * Rq);
+    const double* Zm = Zs + zoff[m];
+    // Fz[i][(p,q)] = Z_m[p,i,q], zero padded
+    for (int x = tid; x < Kp * W; x += nth) {
+      const int i = x / W, c = x % W;
+      const int p = c / Rq, q = c % Rq;
+      Fz[x] = (i < Km && c < Rp * Rq) ? Zm[(p * Km + i) * Rq + q] : 0.0;
+    }
+    __syncthreads();
+    // F = Fz^T Fz (W x W) into Tn, then scattered into the E layout
+    gemm_f64(Fz, 1, W, Fz, W, Tn, D, W, W, Kp);
+    __syncthreads();
+    double* dst = (t == 1) ? Tm : Em;
+    for (int x = tid; x < D * D; x += nth) {  // whole buffer: zero outside the block
+      const int row = x / D, col = x % D;
+      double v = 0.0;
+      if (row < Rp * Rp && col < Rq * Rq) {
+        const int p = row / Rp, pp = row % Rp, q = col / Rq, qq = col % Rq;
+        v = Tn[(p * Rq + q) * D + pp * Rq + qq];
+      }
+      dst[x] = v;
+    }
+    __syncthreads();
+    if (t > 1) {
+      const int mp = pad16(Rn1 * Rn1), np = pad16(Rq * Rq);
+      gemm_f64(Tm, D, 1, Em, D, Tn, D, mp, np, pad16(Rp * Rp));
+      __syncthreads();
+      for (int x = tid; x < D * D; x += nth) {
+        const int row = x / D, col = x % D;
+        Tm[x] = (row < mp && col < np) ? Tn[x] : 0.0;
+      }
+      __syncthreads();
+    }
+  }
+  // Tm is R_{n+1}^2 x R_n^2
+  const int Rb2 = Rb, Ra2 = Ra;
+  for (int x = tid; x < RR * RR; x += nth) {
+    const int r1 = x / RR, r2 = x % RR;
+    const int a = r1 / Rb2, b = r1 % Rb2, a2 = r2 / Rb2, b2 = r2 % Rb2;
+    G[x] = Tm[(b * Rb2 + b2) * D + (a * Ra2 + a2)];
+  }
+  __syncthreads();
+}
+
 template <int RMAX>
 __global__ __launch_bounds__(512) void als_solve2_kernel(AlsSolveArgs g) {
   if (*g.done) return;
@@ -309,76 +399,10 @@ __global__ __launch_bounds__(512) void als_solve2_kernel(AlsSolveArgs g) {
     sm[o] = s;
   }
   if (tid == 0) failed = 0;
-  if (!g.gram_direct) {
-    // Gram from transfer matrices: sum_j S_j (x) S_j = E_{n+1} E_{n+2} ... E_{n-1},
-    // E_m[(p,p'),(q,q')] = sum_i Z_m[p,i,q] Z_m[p',i,q']; entry [(b,b'),(a,a')] of the
-    // product is Gram[(a,b),(a',b')].  Buffers are D x D (D = pad16(max R^2)), zero padded.
-    const int D = g.tdim;
-    double* Tm = xt;
-    double* Em = Tm + D * D;
-    double* Tn = Em + D * D;
-    double* Fz = Tn + D * D;   // Kp x W slice matrix, Kp <= 64
-    double* Zs = Fz + 64 * D;  // cores
-    {
-      double zt[12];
-#pragma unroll
-      for (int e = 0; e < 12; ++e) {
-        const int64_t x = tid + (int64_t)e * nth;
-        zt[e] = x < g.ztotal ? g.Z[x] : 0.0;
-      }
-#pragma unroll
-      for (int e = 0; e < 12; ++e) {
-        const int64_t x = tid + (int64_t)e * nth;
-        if (x < g.ztotal) Zs[x] = zt[e];
-      }
-    }
-    for (int x = tid; x < 3 * D * D; x += nth) Tm[x] = 0.0;
-    __syncthreads();
-    const int Rn1 = g.Rc[(g.n + 1) % g.N];
-    for (int t = 1; t < g.N; ++t) {
-      const int m = (g.n + t) % g.N;
-      const int Rp = g.Rc[m], Rq = g.Rc[(m + 1) % g.N], Km = g.Kc[m];
-      const int Kp = (Km + 3) / 4 * 4, W = pad16(Rp * Rq);
-      const double* Zm = Zs + g.zoff[m];
-      // Fz[i][(p,q)] = Z_m[p,i,q], zero padded
-      for (int x = tid; x < Kp * W; x += nth) {
-        const int i = x / W, c = x % W;
-        const int p = c / Rq, q = c % Rq;
-        Fz[x] = (i < Km && c < Rp * Rq) ? Zm[(p * Km + i) * Rq + q] : 0.0;
-      }
-      __syncthreads();
-      // F = Fz^T Fz (W x W) into Tn, then scattered into the E layout
-      gemm_f64(Fz, 1, W, Fz, W, Tn, D, W, W, Kp);
-      __syncthreads();
-      double* dst = (t == 1) ? Tm : Em;
-      for (int x = tid; x < D * D; x += nth) {  // whole buffer: zero outside the block
-        const int row = x / D, col = x % D;
-        double v = 0.0;
-        if (row < Rp * Rp && col < Rq * Rq) {
-          const int p = row / Rp, pp = row % Rp, q = col / Rq, qq = col % Rq;
-          v = Tn[(p * Rq + q) * D + pp * Rq + qq];
-        }
-        dst[x] = v;
-      }
-      __syncthreads();
-      if (t > 1) {
-        const int mp = pad16(Rn1 * Rn1), np = pad16(Rq * Rq);
-        gemm_f64(Tm, D, 1, Em, D, Tn, D, mp, np, pad16(Rp * Rp));
-        __syncthreads();
-        for (int x = tid; x < D * D; x += nth) {
-          const int row = x / D, col = x % D;
-          Tm[x] = (row < mp && col < np) ? Tn[x] : 0.0;
-        }
-        __syncthreads();
-      }
-    }
-    // Tm is R_{n+1}^2 x R_n^2
-    const int Rb2 = g.Rb, Ra2 = g.Ra;
-    for (int x = tid; x < RR * RR; x += nth) {
-      const int r1 = x / RR, r2 = x % RR;
-      const int a = r1 / Rb2, b = r1 % Rb2, a2 = r2 / Rb2, b2 = r2 % Rb2;
-      G[x] = Tm[(b * Rb2 + b2) * D + (a * Ra2 + a2)];
-    }
+  if (g.gram_in) {
+    for (int x = tid; x < RR * RR; x += nth) G[x] = g.gram_in[x];
+  } else if (!g.gram_direct) {
+    transfer_gram(g.Z, g.ztotal, g.N, g.n, g.zoff, g.Kc, g.Rc, g.tdim, g.Ra, g.Rb, xt, G);
   }
   __syncthreads();
   if constexpr (RMAX > 0) {
@@ -508,7 +532,9 @@ hipError_t launch_als_accum(AlsArgs2 g, int rmax, hipStream_t s) {
   const int64_t grid = als2_parts(g.Kn, g.RR, g.J, g.ztotal);
   g.tiles_per_wg = (ntiles + grid - 1) / grid;
   g.zlds = g.ztotal <= kZldsMax;
-  const size_t lds = (size_t)accum_words(g.Kn, g.RR, g.ztotal, tj) * 8;
+  size_t lds = (size_t)accum_words(g.Kn, g.RR, g.ztotal, tj) * 8;
+  if (g.gram_extra)
+    lds = std::max(lds, (size_t)(3 * (int64_t)g.tdim * g.tdim + 64 * (int64_t)g.tdim + g.ztotal) * 8);
   const int NT = pad16(g.RR) / 16, MT = pad16(g.Kn) / 16;
   const int ntot = MT * NT + (g.gram_direct ? NT * NT : 0);
   const int ntw = (ntot + 15) / 16;  // output tiles per wavefront
@@ -519,7 +545,8 @@ hipError_t launch_als_accum(AlsArgs2 g, int rmax, hipStream_t s) {
   if (e != hipSuccess) return e;
   prof_begin("als_accum", s);
   void* args[] = {&g};
-  e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kAcThreads), args, lds, s);
+  e = hipLaunchKernel(fn, dim3((unsigned)(grid + (g.gram_extra ? 1 : 0))), dim3(kAcThreads), args,
+                      lds, s);
   prof_end(s);
   if (e != hipSuccess) return e;
   return hipGetLastError();

@@ -134,8 +134,16 @@ struct AlsArgs2 {
   int64_t tiles_per_wg;
   double* part;          // [grid][nout + 1], nout = Kn*RR (+ RR*RR if gram_direct)
   const int* done;
+  // gram_extra: one more work-group forms the transfer-matrix Gram of core n into gram_out
+  // (RR x RR) while the others accumulate M
+  int gram_extra;
+  double* gram_out;
+  int tdim;
+  int64_t zoffs[8];
+  int Kc[8], Rc[8];
 };
 struct AlsSolveArgs {
+  const double* gram_in;  // Gram formed by the accumulation launch (NULL: form it here)
   const double* part;
   int nparts, Kn, RR, Rb, Ra;
   int gram_direct;

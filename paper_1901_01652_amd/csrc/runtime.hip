@@ -556,6 +556,7 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
   plan.take<double>(1024);
   plan.take<double>(1);
   plan.take<int>(1);
+  plan.take<double>((size_t)RRmax * RRmax);
   if ((st = ensure_ws(h, plan.off + 256))) return st;
   Carve cv(h->ws);
   double* Bm = cv.take<double>((size_t)Jmax * RRmax);
@@ -565,6 +566,7 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
   double* red = cv.take<double>(1024);
   double* pn2 = cv.take<double>(1);
   int* done = cv.take<int>(1);
+  double* gram = cv.take<double>((size_t)RRmax * RRmax);  // transfer-matrix Gram of the update
 
   if (Z != Z_init)
     HIP_TRY(hipMemcpyAsync(Z, Z_init, zoff[order] * sizeof(double), hipMemcpyDeviceToDevice, s),
@@ -599,6 +601,15 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
       a.ztotal = (int64_t)zoff[order];
       a.part = part;
       a.done = done;
+      // the transfer-matrix Gram of core n is formed by one extra work-group of this launch
+      a.gram_extra = (!gram_direct && (mode & 1)) ? 1 : 0;
+      a.gram_out = gram;
+      a.tdim = tdim;
+      for (int m = 0; m < order; ++m) {
+        a.zoffs[m] = (int64_t)zoff[m];
+        a.Kc[m] = Kp[m];
+        a.Rc[m] = R[m];
+      }
       return a;
     };
     auto solve_for = [&](int n, int64_t grid, int report, int report_only) {
@@ -630,6 +641,7 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
       a.trace = err_trace;
       a.sweeps_run = sweeps_run;
       a.tol = opts->tol;
+      a.gram_in = (!gram_direct && !report_only) ? gram : nullptr;
       return a;
     };
     for (int sw = 0; sw < opts->max_sweeps; ++sw) {
