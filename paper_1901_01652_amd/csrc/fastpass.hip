@@ -23,6 +23,15 @@
 namespace rtr {
 
 constexpr int kFpTJ = 64;
+
+// Column of element (row, col) of the [i][j] tile for the contiguous-fiber loader: the 8-wide
+// column groups of a row are XOR-permuted by (row / 16) mod 8.  That loader's threads write
+// four consecutive rows of one column, which without the permutation land in 4 of the 64 LDS
+// banks (16-way conflicts); the permutation spreads them, and 8-element groups stay whole so
+// the matrix-core reads below remain single 16-byte loads.
+__device__ __forceinline__ int swz_col(int row, int col) {
+  return ((((col >> 3) ^ (row >> 4)) & 7) << 3) | (col & 7);
+}
 constexpr int kFpThreads = 512;   // 8 wavefronts
 constexpr int kFpMaxIn = 256;
 constexpr int kFpMaxK = 64;
@@ -165,10 +174,10 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
         if (al < kFpTJ) {
           const float4 v = buf[s];
           const int i = 4 * i4;
-          Tij[(i + 0) * ldT + al] = Mma<BF>::cvt(v.x);
-          Tij[(i + 1) * ldT + al] = Mma<BF>::cvt(v.y);
-          Tij[(i + 2) * ldT + al] = Mma<BF>::cvt(v.z);
-          Tij[(i + 3) * ldT + al] = Mma<BF>::cvt(v.w);
+          Tij[(i + 0) * ldT + swz_col(i + 0, al)] = Mma<BF>::cvt(v.x);
+          Tij[(i + 1) * ldT + swz_col(i + 1, al)] = Mma<BF>::cvt(v.y);
+          Tij[(i + 2) * ldT + swz_col(i + 2, al)] = Mma<BF>::cvt(v.z);
+          Tij[(i + 3) * ldT + swz_col(i + 3, al)] = Mma<BF>::cvt(v.w);
           if (OP == 1) {
             T* d = Tji + al * ldI + i;
             d[0] = Mma<BF>::cvt(v.x);
@@ -256,7 +265,31 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
       const int q = wid + 8 * s;
       if (q < MT * NT) {
         const int mt = q / NT, nt = q % NT;
-        acc[s] = tile_abt(Tij + mt * 16 * ldT, ldT, Ot + nt * 16 * ldT, ldT, kFpTJ, acc[s]);
+        if constexpr (LD == 1) {
+          // tile_abt with the swizzled A operand: lane reads row mt*16 + (lane & 15),
+          // column group (k0 / 8 + lane / 16) permuted as in swz_col
+          const int r = mt * 16 + (lane & 15), gq = lane >> 4;
+          const T* arow = Tij + r * ldT;
+          const T* brow = Ot + (nt * 16 + (lane & 15)) * ldT;
+          f32x4 c = acc[s];
+          if constexpr (BF) {
+#pragma unroll
+            for (int k0 = 0; k0 < kFpTJ; k0 += 32) {
+              const int ca = swz_col(r, k0 + 8 * gq);
+              const bf16x8 av = *(const bf16x8*)(arow + ca);
+              const bf16x8 bv = *(const bf16x8*)(brow + k0 + 8 * gq);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+            }
+          } else {
+#pragma unroll
+            for (int k0 = 0; k0 < kFpTJ; k0 += 4)
+              c = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[swz_col(r, k0 + gq)],
+                                                      brow[k0 + gq], c, 0, 0, 0);
+          }
+          acc[s] = c;
+        } else {
+          acc[s] = tile_abt(Tij + mt * 16 * ldT, ldT, Ot + nt * 16 * ldT, ldT, kFpTJ, acc[s]);
+        }
       }
     }
     __syncthreads();
