@@ -23,9 +23,9 @@ HBM_PEAK_GBPS = 8000.0
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # (calibrated on a 1 GiB copy), valid only for the kernel source they were taken on.
-TRAFFIC = {"power_fused": {"bytes_per_launch": 6483473353, "workload": "dense-200^4 bf16",
+TRAFFIC = {"power_fused": {"bytes_per_launch": 6476062020, "workload": "dense-200^4 bf16",
                            "source": "paper_1901_01652_amd/csrc/fastpass.hip",
-                           "sha256": "be6bbb656f5a540f272329618deae3b7f3f9a6a9e5f0b6dce184e18bcb28aed5",
+                           "sha256": "7bb27689a1237f20e5cd35672afbb4373e37a3eaaf27768787dc5966e42e20fc",
                            "profile": "profiles/dense200_hbm_traffic_counters.md"}}
 
 
