@@ -73,7 +73,7 @@ extern "C" {
 typedef enum {
   RTR_OK = 0,
   RTR_ERR_INVALID_ARG = 1,  /* a size, pointer or option is out of range */
-  RTR_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement */
+  RTR_ERR_UNSUPPORTED = 2,  /* valid request outside what the library implements */
   RTR_ERR_OOM = 3,          /* workspace allocation failed */
   RTR_ERR_DEVICE = 4,       /* a HIP runtime call failed */
   RTR_ERR_NUMERICAL = 5,    /* device status word reported a numerical failure */
