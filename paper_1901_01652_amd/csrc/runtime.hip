@@ -42,9 +42,17 @@ struct rtr_context {
   int gepoch = -1;
   void* gitems_dev = nullptr;
   size_t gitems_cap = 0;
+  // branch streams of the captured batch (default priority) and their fork/join events
+  hipStream_t br[8] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[8] = {};
+  bool ws_locked = false;  // set while a capture hands out fixed slices of the workspace
+  size_t ws_hi = 0;        // largest workspace request since it was last reset
 };
 
 namespace {
+
+constexpr int kBatchBranches = 8;  // concurrent branches of a captured batch
 
 thread_local rtr_context* g_ctx = nullptr;
 
@@ -94,7 +102,10 @@ struct Carve {
 };
 
 rtr_status ensure_ws(rtr_context* h, size_t bytes) {
+  h->ws_hi = std::max(h->ws_hi, bytes);
   if (bytes <= h->ws_cap) return RTR_OK;
+  if (h->ws_locked)
+    return fail(h, RTR_ERR_INTERNAL, "workspace slice too small inside a graph capture");
   size_t cap = bytes + bytes / 8 + (1 << 20);
   if (h->ws) {
     HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
@@ -227,6 +238,11 @@ rtr_status rtr_destroy(rtr_handle h) {
   for (auto e : h->pool) (void)hipEventDestroy(e);
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  for (int b = 0; b < 8; ++b) {
+    if (h->br[b]) (void)hipStreamDestroy(h->br[b]);
+    if (h->join_ev[b]) (void)hipEventDestroy(h->join_ev[b]);
+  }
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
   if (h->items_copied) (void)hipEventDestroy(h->items_copied);
   if (h->items_dev) (void)hipFree(h->items_dev);
   if (h->gitems_dev) (void)hipFree(h->gitems_dev);
@@ -905,15 +921,41 @@ namespace {
 rtr_status batch_sequence(rtr_context* h, const rtr_batch_item* items, int32_t count,
                           rtr_dtype x_dtype, rtr_dtype compute, int32_t power_iters,
                           int32_t max_sweeps, double tol, const BatchPlan& plan,
-                          const rtr::AlsItem* dev, hipStream_t s) {
-  for (int t = 0; t < count; ++t) {
-    const rtr_batch_item& it = items[t];
-    rtr_status st = rtr_sketch(h, it.X, x_dtype, it.order, it.dims, it.K, power_iters, it.seed,
-                               it.tensor_id, compute, it.Q, s);
-    if (st) return st;
-    st = rtr_compress(h, it.X, x_dtype, it.order, it.dims, it.K, it.Q, compute, it.P, nullptr, s);
-    if (st) return st;
+                          const rtr::AlsItem* dev, hipStream_t s, int nb = 1) {
+  // Sketch and compression of every tensor.  With nb > 1 (graph capture only) tensor t goes
+  // to branch stream t % nb with its own slice of the workspace, so that the launches of small
+  // tensors, which leave most of the chip idle, overlap; the branches join before TR-ALS.
+  char* const base = (char*)h->ws;
+  const size_t cap = h->ws_cap;
+  const size_t slice = nb > 1 ? (cap / nb) & ~size_t(255) : cap;
+  if (nb > 1) {
+    HIP_TRY(hipEventRecord(h->fork_ev, s), "hipEventRecord");
+    for (int b = 0; b < nb; ++b) HIP_TRY(hipStreamWaitEvent(h->br[b], h->fork_ev, 0), "hipStreamWaitEvent");
+    h->ws_locked = true;
   }
+  rtr_status st = RTR_OK;
+  for (int t = 0; t < count && !st; ++t) {
+    const rtr_batch_item& it = items[t];
+    hipStream_t ts = nb > 1 ? h->br[t % nb] : s;
+    if (nb > 1) {
+      h->ws = base + (size_t)(t % nb) * slice;
+      h->ws_cap = slice;
+    }
+    st = rtr_sketch(h, it.X, x_dtype, it.order, it.dims, it.K, power_iters, it.seed,
+                    it.tensor_id, compute, it.Q, ts);
+    if (!st)
+      st = rtr_compress(h, it.X, x_dtype, it.order, it.dims, it.K, it.Q, compute, it.P, nullptr, ts);
+  }
+  if (nb > 1) {
+    h->ws = base;
+    h->ws_cap = cap;
+    h->ws_locked = false;
+    for (int b = 0; b < nb; ++b) {  // join every branch, also after an error
+      HIP_TRY(hipEventRecord(h->join_ev[b], h->br[b]), "hipEventRecord");
+      HIP_TRY(hipStreamWaitEvent(s, h->join_ev[b], 0), "hipStreamWaitEvent");
+    }
+  }
+  if (st) return st;
   Guard guard(h);
   HIP_TRY(rtr::launch_als_batch(dev, count, max_sweeps, tol, h->status, plan.lay, plan.mq, plan.gq, s),
           "batched TR-ALS");
@@ -973,6 +1015,7 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
     return RTR_OK;
   }
   // eager run (also sizes the workspace for the capture below)
+  h->ws_hi = 0;
   rtr::AlsItem* dev = nullptr;
   {
     Guard guard(h);
@@ -993,6 +1036,20 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
   }
   HIP_TRY(hipMemcpy(h->gitems_dev, plan.items.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy");
   if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+  const int nb = std::min(kBatchBranches, count);
+  if (nb > 1) {
+    for (int b = 0; b < nb; ++b) {
+      if (!h->br[b]) HIP_TRY(hipStreamCreateWithFlags(&h->br[b], hipStreamNonBlocking), "hipStreamCreate");
+      if (!h->join_ev[b]) HIP_TRY(hipEventCreateWithFlags(&h->join_ev[b], hipEventDisableTiming), "hipEventCreate");
+    }
+    if (!h->fork_ev) HIP_TRY(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming), "hipEventCreate");
+    // every branch gets a slice as large as the largest request of the eager run
+    const size_t one = (h->ws_hi + 255) & ~size_t(255);
+    {
+      Guard guard(h);
+      if ((st = ensure_ws(h, one * nb))) return st;
+    }
+  }
   if (h->gexec) {
     (void)hipGraphExecDestroy(h->gexec);
     h->gexec = nullptr;
@@ -1002,7 +1059,7 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
   const int epoch = h->ws_epoch;
   HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
   st = batch_sequence(h, items, count, x_dtype, compute, power_iters, max_sweeps, tol, plan,
-                      (const rtr::AlsItem*)h->gitems_dev, h->cap_stream);
+                      (const rtr::AlsItem*)h->gitems_dev, h->cap_stream, nb);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
   h->prof_level = prof;
