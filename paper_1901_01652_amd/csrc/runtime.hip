@@ -17,6 +17,8 @@ struct ProfRec {
   hipEvent_t e0, e1;
 };
 
+constexpr int kBatchBranches = 8;  // concurrent branches of a captured batch (16 measured no faster)
+
 struct rtr_context {
   int device = 0;
   void* ws = nullptr;
@@ -43,16 +45,14 @@ struct rtr_context {
   void* gitems_dev = nullptr;
   size_t gitems_cap = 0;
   // branch streams of the captured batch (default priority) and their fork/join events
-  hipStream_t br[8] = {};
+  hipStream_t br[kBatchBranches] = {};
   hipEvent_t fork_ev = nullptr;
-  hipEvent_t join_ev[8] = {};
+  hipEvent_t join_ev[kBatchBranches] = {};
   bool ws_locked = false;  // set while a capture hands out fixed slices of the workspace
   size_t ws_hi = 0;        // largest workspace request since it was last reset
 };
 
 namespace {
-
-constexpr int kBatchBranches = 8;  // concurrent branches of a captured batch
 
 thread_local rtr_context* g_ctx = nullptr;
 
@@ -238,7 +238,7 @@ rtr_status rtr_destroy(rtr_handle h) {
   for (auto e : h->pool) (void)hipEventDestroy(e);
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-  for (int b = 0; b < 8; ++b) {
+  for (int b = 0; b < kBatchBranches; ++b) {
     if (h->br[b]) (void)hipStreamDestroy(h->br[b]);
     if (h->join_ev[b]) (void)hipEventDestroy(h->join_ev[b]);
   }
