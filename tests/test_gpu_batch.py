@@ -167,11 +167,14 @@ def test_batch_pipeline_matches_oracle(h, dtype, tol_trace, tol_psi):
     assert worst_t < tol_trace
 
 
-def test_batch_graph_replay(h):
+@pytest.mark.parametrize("count", [16, 3, 1])
+def test_batch_graph_replay(h, count):
     """The captured graph replays the whole batch: every replay (with other work and
-    synchronisations in between) reproduces the eager outputs bit for bit."""
-    say("batch graph replay")
-    items, _ = pipeline_items(16, torch.float32)
+    synchronisations in between) reproduces the eager outputs bit for bit.  16 tensors fill
+    all branch streams of the capture (two per branch, each branch on its own workspace
+    slice), 3 leave branches unused, 1 captures a single chain."""
+    say("batch graph replay", count)
+    items, _ = pipeline_items(count, torch.float32)
     rt.rtr_batch_run(h, items, 10, use_graph=True)       # eager run + capture
     torch.cuda.synchronize()
     want = {k: [it[k].clone() for it in items] for k in ("Q", "P", "Z", "G", "err_trace")}
