@@ -27,6 +27,7 @@
 namespace rtr {
 
 constexpr int kAcThreads = 1024;  // 16 wavefronts
+constexpr int kSolveThreads = 1024;
 constexpr int kAcTilesMax = 8;    // 16x16 output tiles per wavefront, at most
 constexpr int64_t kZldsMax = 6144;
 
@@ -350,7 +351,7 @@ __device__ void transfer_gram(const double* __restrict__ Z, int64_t ztotal, int 
 }
 
 template <int RMAX>
-__global__ __launch_bounds__(512) void als_solve2_kernel(AlsSolveArgs g) {
+__global__ __launch_bounds__(kSolveThreads) void als_solve2_kernel(AlsSolveArgs g) {
   if (*g.done) return;
   extern __shared__ __align__(16) double sm[];
   const int RR = g.RR, Kn = g.Kn, nM = Kn * RR;
@@ -555,20 +556,20 @@ hipError_t launch_als_accum(AlsArgs2 g, int rmax, hipStream_t s) {
 hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s) {
   const size_t lds = solve_lds(g.Kn, g.RR, g.gram_direct, g.tdim, g.ztotal);
   // Gauss-Jordan path: augmented rows of at most 256 entries (the LDS row/column buffers),
-  // elements spread over 512 threads
+  // elements spread over kSolveThreads threads
   const int ne = (g.RR + g.Kn <= 256) ? g.RR * (g.RR + g.Kn) : (1 << 30);
-  const void* fn = ne <= 512 ? (const void*)als_solve2_kernel<1>
-                 : ne <= 1024 ? (const void*)als_solve2_kernel<2>
-                 : ne <= 2048 ? (const void*)als_solve2_kernel<4>
-                 : ne <= 4096 ? (const void*)als_solve2_kernel<8>
-                 : ne <= 8192 ? (const void*)als_solve2_kernel<16>
-                 : ne <= 16384 ? (const void*)als_solve2_kernel<32>
-                              : (const void*)als_solve2_kernel<0>;
+  const int T = kSolveThreads;
+  const void* fn = ne <= T ? (const void*)als_solve2_kernel<1>
+                 : ne <= 2 * T ? (const void*)als_solve2_kernel<2>
+                 : ne <= 4 * T ? (const void*)als_solve2_kernel<4>
+                 : ne <= 8 * T ? (const void*)als_solve2_kernel<8>
+                 : ne <= 16 * T ? (const void*)als_solve2_kernel<16>
+                                : (const void*)als_solve2_kernel<0>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   prof_begin("als_solve", s);
   void* args[] = {&g};
-  e = hipLaunchKernel(fn, dim3(1), dim3(512), args, lds, s);
+  e = hipLaunchKernel(fn, dim3(1), dim3(kSolveThreads), args, lds, s);
   prof_end(s);
   if (e != hipSuccess) return e;
   return hipGetLastError();
