@@ -35,22 +35,6 @@ def gaussian_test_matrix(seed, n, rows, K, tensor_id=0):
     return z.reshape(rows, K)
 
 
-def sketch(X, K, seed, tensor_id=0):
-    """Alg. 1 steps 4-5 for every mode: Y_n = X_(n) M_n (None where K_n >= I_n).
-
-    Parity: pinned by the range-finder property (exact recovery) and the N=2 textbook case."""
-    Ys = []
-    for n in range(X.ndim):
-        In = X.shape[n]
-        if K[n] >= In:
-            Ys.append(None)
-            continue
-        A = unfold(X, n)
-        M = gaussian_test_matrix(seed, n, A.shape[1], K[n], tensor_id)
-        Ys.append(A @ M)
-    return Ys
-
-
 def qr_pos(Y):
     """Alg. 1 step 6: economy QR (Householder, LAPACK) with R_ii >= 0.
 
@@ -161,16 +145,19 @@ def _svd_fixed_sign(C):
     return U * sign, s, Vt * sign[:, None]
 
 
-def tr_svd(P, eps):
+def tr_svd(P, eps, steps=None):
     """Alg. 1 step 9 with TR-SVD (sequential truncated SVDs, Zhao et al. 2016):
     per-step budget delta = eps ||P|| / sqrt(N), the first step sqrt(2) delta; the first
     rank r_1 is split as R_1 R_2 = r_1 with R_1 <= R_2 as close as possible; the last core
-    closes the ring through R_1.  Returns (cores, ranks [R_1..R_N]).
+    closes the ring through R_1.  Returns (cores, ranks [R_1..R_N]).  If ``steps`` is a
+    list, one (matrix, budget, kept rank) record per truncation is appended to it.
 
-    Parity: pinned by the error bound ||P - Psi(Z)|| <= eps ||P|| and per-step minimality;
-    the exact cores are partly unpinned (the rank split is a reading).  Singular vectors
-    follow the sign rule of ``_svd_fixed_sign`` (a reading: the split first rank makes the
-    later truncations depend on those signs)."""
+    Parity: pinned by the error bound ||P - Psi(Z)|| <= eps ||P||, by the minimality of every
+    truncation (each kept rank is the smallest within its budget, checked on singular values
+    obtained by another route), and by the error being exactly the root sum of the discarded
+    tails; the exact cores are partly unpinned (the rank split is a reading).  Singular
+    vectors follow the sign rule of ``_svd_fixed_sign`` (a reading: the split first rank
+    makes the later truncations depend on those signs)."""
     shape = P.shape
     N = len(shape)
     nP = frob(P)
@@ -178,6 +165,8 @@ def tr_svd(P, eps):
     C = P.reshape(shape[0], -1)
     U, s, Vt = _svd_fixed_sign(C)
     r = _trunc_rank(s, np.sqrt(2.0) * delta)
+    if steps is not None:
+        steps.append((C, np.sqrt(2.0) * delta, r))
     R1, R2 = _split_rank(r)
     Z = [np.transpose(U[:, :r].reshape(shape[0], R1, R2), (1, 0, 2))]
     C = (s[:r, None] * Vt[:r]).reshape(R1, R2, -1)
@@ -188,6 +177,8 @@ def tr_svd(P, eps):
         C = C.reshape(Rk * shape[k], -1)
         U, s, Vt = _svd_fixed_sign(C)
         r = _trunc_rank(s, delta)
+        if steps is not None:
+            steps.append((C, delta, r))
         Z.append(U[:, :r].reshape(Rk, shape[k], r))
         C = s[:r, None] * Vt[:r]
         ranks.append(r)

@@ -1,5 +1,6 @@
 """Pins of the oracle's Algorithm 1 steps: exact recovery, closed forms, textbook limits."""
 import numpy as np
+import scipy.linalg
 import pytest
 
 from oracle import rtr, tensor as T
@@ -230,6 +231,62 @@ def test_tr_svd_error_bound_and_minimal_ranks(eps):
         assert np.sqrt(np.sum(s[r1 - 1:] ** 2)) > d1
 
 
+def _sv_by_eigh(C):
+    """Singular values of C from the symmetric eigen-solver on the smaller Gram matrix (a
+    route independent of the SVD that tr_svd calls), descending."""
+    G = C @ C.T if C.shape[0] <= C.shape[1] else C.T @ C
+    ev = scipy.linalg.eigvalsh(G)[::-1]
+    return np.sqrt(np.maximum(ev, 0.0))
+
+
+@pytest.mark.parametrize("shape,ranks,noise,eps", [
+    ((6, 7, 5, 6), (2, 3, 2, 3), 0.05, 0.3),
+    ((6, 7, 5, 6), (2, 3, 2, 3), 0.05, 0.1),
+    ((6, 7, 5, 6), (2, 3, 2, 3), 0.05, 0.02),
+    ((5, 6, 4, 5, 4), (2, 2, 3, 2, 2), 0.1, 0.2),
+    ((9, 8, 10), (3, 2, 4), 0.02, 0.05),
+])
+def test_tr_svd_every_truncation_minimal(shape, ranks, noise, eps):
+    """Every truncation of TR-SVD keeps the smallest rank whose discarded singular values
+    fit its budget (tail(r) <= budget < tail(r - 1)), the budgets are eps ||P|| / sqrt(N)
+    (twice the energy for the first), and the final error is exactly the root sum of the
+    discarded tails (the truncations are orthogonal projections onto nested subspaces)."""
+    rng = np.random.default_rng(40)
+    S = T.tr_full(cores(list(shape), list(ranks), seed=41))
+    P = S + noise * np.std(S) * rng.standard_normal(shape)
+    steps = []
+    Z, R = rtr.tr_svd(P, eps, steps=steps)
+    N = len(shape)
+    assert len(steps) == N - 1
+    nP = T.frob(P)
+    lost2 = 0.0
+    for k, (C, budget, r) in enumerate(steps):
+        want = eps * nP / np.sqrt(N) * (np.sqrt(2.0) if k == 0 else 1.0)
+        assert abs(budget - want) <= 1e-14 * want
+        s = _sv_by_eigh(C)
+        tail = lambda t: float(np.sqrt(np.sum(s[t:] ** 2)))
+        assert tail(r) <= budget * (1 + 1e-9), (k, r, tail(r), budget)
+        if r > 1:
+            assert tail(r - 1) > budget * (1 - 1e-9), (k, r, tail(r - 1), budget)
+        lost2 += tail(r) ** 2
+    err = T.frob(P - T.tr_full(Z))
+    assert abs(err - np.sqrt(lost2)) <= 1e-8 * nP
+    assert err <= eps * nP * (1 + 1e-12)
+    # the kept ranks are the cores' ranks (first split into R_1 R_2)
+    assert steps[0][2] == R[0] * R[1]
+    assert [st[2] for st in steps[1:]] == R[2:]
+
+
+def test_tr_svd_tensor_train_ranks_exact():
+    """With R_1 = 1 the ring is a tensor train, whose sequential unfoldings have the TT-ranks
+    as exact ranks: TR-SVD at a tiny eps must return exactly those ranks."""
+    G = cores([6, 7, 8, 5], [1, 3, 4, 2], seed=42)
+    P = T.tr_full(G)
+    Z, R = rtr.tr_svd(P, 1e-9)
+    assert R == [1, 3, 4, 2]
+    assert T.frob(P - T.tr_full(Z)) <= 1e-9 * T.frob(P)
+
+
 def test_tr_svd_independent_of_lapack_signs(monkeypatch):
     """The split first rank makes TR-SVD depend on singular-vector signs; with the fixed
     sign rule the result is a function of P alone: random sign flips of every SVD that
@@ -285,3 +342,39 @@ def test_generator_snr():
     S = T.tr_full(G)
     snr = 20 * np.log10(T.frob(S) / T.frob(X.numpy() - S))
     assert abs(snr - 20.0) < 0.05
+
+
+def test_generator_noise_is_the_published_philox_stream():
+    """The generator's noise stream is element e of the Philox4x32-10 / Box-Muller stream
+    (tag 3), the same definition the oracle's generator is pinned to by the known-answer
+    vectors: both the per-element and the four-per-call routes."""
+    import torch
+    from oracle import philox
+    seed, tid = 20190107, 5
+    sw = philox.stream_word(3, 0)
+    assert sw == W.NOISE_STREAM
+    start = (1 << 33) + 3
+    ref = philox.normals(seed, sw, tid, start, 1001)
+    e = torch.arange(start, start + 1001, dtype=torch.int64)
+    np.testing.assert_allclose(W.stream_normals(seed, sw, tid, e).numpy(), ref, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(W._stream_run(seed, sw, tid, start, 1001, "cpu").numpy(), ref,
+                               rtol=0, atol=1e-15)
+
+
+def test_generator_block_is_exact_slice_of_full_tensor():
+    """A block workload is the leading block of the full tensor: same cores, same sigma,
+    noise keyed by the full index (the 64^4 sample of the 200^4 workload, at 12^4 of 40^4)."""
+    full = W.dense_200(I=40)
+    blk = W.dense_200_block(block=12, I=40)
+    Xf, Gf = W.make_tensor(full)
+    Xb, Gb = W.make_tensor(blk)
+    assert list(Xb.shape) == [12] * 4
+    np.testing.assert_allclose(Xb.numpy(), Xf.numpy()[:12, :12, :12, :12], rtol=0,
+                               atol=1e-12 * float(np.abs(Xf.numpy()).max()))
+    for a, b in zip(Gb, Gf):
+        np.testing.assert_array_equal(a, b[:, :12, :])
+
+
+def test_generator_signal_norm_closed_form():
+    G = cores([5, 4, 6, 3], [2, 3, 2, 2], seed=43)
+    assert abs(W.tr_norm2(G) - T.frob(T.tr_full(G)) ** 2) < 1e-10 * T.frob(T.tr_full(G)) ** 2

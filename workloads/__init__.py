@@ -15,8 +15,15 @@ decomposition's arithmetic (no sketch, QR, compression, ALS or back-projection).
 * the five workload definitions (small exact-arithmetic case, large dense sketch,
   hyperspectral-shaped, batched uneven, learned warm start).
 
-Noise and signal are produced with torch on the requested device; numbers are reproducible
-for a given (seed, device type).  Small cases are generated on the CPU and copied.
+Noise is keyed by the element's index in the FULL tensor: element e (row-major over the full
+dims) is element e of a Philox4x32-10 Gaussian stream (Salmon et al., SC'11; Box-Muller on
+word pairs, uniforms (w + 1/2) 2^-32), key (seed mod 2^32, seed >> 32), counter
+(c mod 2^32, c >> 32, 0x03000000, tensor_id) with c = e >> 2 and lane e & 3.  A workload that
+is the leading block of a larger one (``full_dims``) therefore gets exactly the noise of that
+block of the larger tensor, and its noise level sigma is the larger tensor's (the signal norm
+comes from the cores in closed form, ||Psi(G)||^2 = Tr prod_n sum_i G_n(i) (x) G_n(i)).
+Signal and noise are formed in FP64 with torch on the requested device and rounded once to
+the requested dtype.
 """
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
@@ -93,18 +100,112 @@ def tr_signal(cores, device="cpu", dtype=torch.float64):
     return S.to(dtype)
 
 
-def add_noise(S, snr_db, seed, tensor_id=0):
-    """X = S + sigma * N(0,1) with sigma^2 numel = ||S||^2 10^(-snr/10); returns (X, sigma)."""
-    if snr_db is None:
-        return S.clone(), 0.0
-    nS2 = float(torch.sum(S.double() ** 2))
-    sigma = (nS2 * 10.0 ** (-snr_db / 10.0) / S.numel()) ** 0.5
-    g = torch.Generator(device=S.device)
-    g.manual_seed((int(seed) * 1000003 + int(tensor_id) * 7919 + 5) % (2 ** 63))
-    E = torch.randn(S.shape, generator=g, device=S.device, dtype=S.dtype)
-    E.mul_(sigma)
-    E.add_(S)
-    return E, sigma
+_PH_M0, _PH_M1 = 0xD2511F53, 0xCD9E8D57
+_PH_W0, _PH_W1 = 0x9E3779B9, 0xBB67AE85
+_U32 = 0xFFFFFFFF
+NOISE_STREAM = 3 << 24
+
+
+def _philox_words(c, stream, tensor_id, seed):
+    """Philox4x32-10 of the counters (c lo, c hi, stream, tensor_id) under key ``seed``.
+    ``c`` is an int64 torch tensor of call indices; returns four int64 tensors of 32-bit
+    words.  Products of two 32-bit words are formed in int64, which wraps modulo 2^64, so
+    the low and high halves are exact."""
+    c0 = c & _U32
+    c1 = (c >> 32) & _U32
+    c2 = torch.full_like(c, stream & _U32)
+    c3 = torch.full_like(c, tensor_id & _U32)
+    k0, k1 = seed & _U32, (seed >> 32) & _U32
+    for rnd in range(10):
+        if rnd:
+            k0 = (k0 + _PH_W0) & _U32
+            k1 = (k1 + _PH_W1) & _U32
+        p0 = c0 * _PH_M0
+        p1 = c2 * _PH_M1
+        c0, c1, c2, c3 = (((p1 >> 32) & _U32) ^ c1 ^ k0, p1 & _U32,
+                          ((p0 >> 32) & _U32) ^ c3 ^ k1, p0 & _U32)
+    return c0, c1, c2, c3
+
+
+def _box_muller(wa, wb):
+    ua = (wa.double() + 0.5) * 2.0 ** -32
+    ub = (wb.double() + 0.5) * 2.0 ** -32
+    r = torch.sqrt(-2.0 * torch.log(ua))
+    t = (2.0 * np.pi) * ub
+    return r * torch.cos(t), r * torch.sin(t)
+
+
+def stream_normals(seed, stream, tensor_id, e):
+    """FP64 N(0,1) samples for the stream elements ``e`` (int64 torch tensor, any shape)."""
+    w = _philox_words(e >> 2, stream, tensor_id, seed)
+    z01 = _box_muller(w[0], w[1])
+    z23 = _box_muller(w[2], w[3])
+    lane = e & 3
+    return torch.where(lane == 0, z01[0], torch.where(lane == 1, z01[1],
+                       torch.where(lane == 2, z23[0], z23[1])))
+
+
+def _stream_run(seed, stream, tensor_id, e0, count, device):
+    """FP64 stream elements [e0, e0 + count): one generator call per four elements."""
+    c = torch.arange(e0 >> 2, ((e0 + count - 1) >> 2) + 1, dtype=torch.int64, device=device)
+    w = _philox_words(c, stream, tensor_id, seed)
+    z01 = _box_muller(w[0], w[1])
+    z23 = _box_muller(w[2], w[3])
+    z = torch.stack([z01[0], z01[1], z23[0], z23[1]], dim=1).reshape(-1)
+    off = e0 - 4 * (e0 >> 2)
+    return z[off:off + count]
+
+
+def noise_block(seed, tensor_id, full_dims, dims, device="cpu", out=None, scale=1.0):
+    """Noise of the leading ``dims`` block of a tensor of shape ``full_dims``: element
+    (i_1..i_N) is stream element e = row-major index of (i_1..i_N) in ``full_dims``.
+    Returns FP64 ``scale`` * noise, or adds it into ``out`` (FP64, shape ``dims``).  Built in
+    slabs of the first index to bound temporary memory."""
+    dims = [int(d) for d in dims]
+    full = [int(d) for d in full_dims]
+    N = len(dims)
+    strides = [1] * N
+    for n in range(N - 2, -1, -1):
+        strides[n] = strides[n + 1] * full[n + 1]
+    if out is None:
+        out = torch.zeros(dims, dtype=torch.float64, device=device)
+    rest = int(np.prod(dims[1:])) if N > 1 else 1
+    i0_chunk = max(1, (1 << 24) // max(rest, 1))
+    contiguous = dims[1:] == full[1:]  # each slab of the first index is one run of the stream
+    off = None
+    if not contiguous:
+        # offsets of the block's elements inside one slab of the first index
+        off = torch.zeros([1] * N, dtype=torch.int64, device=device)
+        for n in range(1, N):
+            shp = [1] * N
+            shp[n] = dims[n]
+            off = off + (torch.arange(dims[n], dtype=torch.int64, device=device) * strides[n]).reshape(shp)
+    for a in range(0, dims[0], i0_chunk):
+        b = min(dims[0], a + i0_chunk)
+        if contiguous:
+            z = _stream_run(seed, NOISE_STREAM, tensor_id, a * strides[0], (b - a) * rest, device)
+            z = z.reshape([b - a] + dims[1:])
+        else:
+            i0 = torch.arange(a, b, dtype=torch.int64, device=device).reshape([b - a] + [1] * (N - 1))
+            z = stream_normals(seed, NOISE_STREAM, tensor_id, i0 * strides[0] + off)
+        out[a:b].add_(z, alpha=scale)
+    return out
+
+
+def tr_norm2(cores):
+    """||Psi(cores)||_F^2 in closed form: trace of the product of the transfer matrices
+    E_n = sum_i G_n(i) (x) G_n(i) (FP64)."""
+    E = None
+    for G in cores:
+        G = np.asarray(G, dtype=np.float64)
+        En = np.einsum("aib,cid->acbd", G, G).reshape(G.shape[0] ** 2, G.shape[2] ** 2)
+        E = En if E is None else E @ En
+    return float(np.trace(E))
+
+
+def noise_sigma(signal_norm2, numel, snr_db):
+    """sigma with sigma^2 numel = ||S||^2 10^(-snr/10)."""
+    return (signal_norm2 * 10.0 ** (-snr_db / 10.0) / numel) ** 0.5
 
 
 @dataclass
@@ -122,6 +223,7 @@ class Workload:
     rescale01: bool = False
     tol: float = 0.0
     tensor_id: int = 0
+    full_dims: Optional[List[int]] = None  # this is the leading block of a tensor of these dims
 
     def numel(self):
         return int(np.prod(self.dims))
@@ -135,6 +237,16 @@ def small_fp64(seed_offset=1):
 def dense_200(I=200, seed_offset=2):
     """Order-4 I^4 FP32 (200^4 = 6.4 GB), rank 6, 30 dB, K=20, q=1, TR-ALS rank 6, 30 sweeps."""
     return Workload(f"dense-{I}^4", [I] * 4, [6] * 4, [20] * 4, 1, 30, 30.0, BASE_SEED + seed_offset)
+
+
+def dense_200_block(block=64, I=200, seed_offset=2):
+    """The leading block^4 block of the dense I^4 workload (same cores, noise and sigma), with
+    the same method parameters: the sample on which the oracle runs beside the GPU."""
+    w = dense_200(I, seed_offset)
+    w.name = f"dense-{I}^4-block-{block}^4"
+    w.full_dims = list(w.dims)
+    w.dims = [block] * 4
+    return w
 
 
 def hsi_shaped(scale=1, seed_offset=3):
@@ -165,17 +277,31 @@ def batched_uneven(count=512, seed_offset=4, lo=16, hi=96):
 
 
 def make_tensor(w: Workload, device="cpu", dtype=torch.float64):
-    """Synthetic X for workload ``w``; returns (X, generating cores)."""
-    cores = tr_cores(w.seed, w.dims, w.ranks, w.tensor_id)
+    """Synthetic X for workload ``w``; returns (X, generating cores of X's own shape).
+
+    The signal and the noise are formed in FP64 and rounded once to ``dtype``.  A block
+    workload (``w.full_dims``) draws the cores of the full tensor, keeps their leading
+    slices, and takes sigma and the noise of the full tensor, so X is exactly the leading
+    block of the full tensor's X."""
+    full = list(w.full_dims) if w.full_dims else list(w.dims)
+    cores = tr_cores(w.seed, full, w.ranks, w.tensor_id)
     if w.smooth_sigma:
         cores = [smooth_along(c, 1, w.smooth_sigma) if n < 2 else c for n, c in enumerate(cores)]
-    S = tr_signal(cores, device, torch.float64 if device == "cpu" else torch.float32)
+    block = [c[:, :d, :] for c, d in zip(cores, w.dims)]
+    S = tr_signal(block, device, torch.float64)
     if w.rescale01:
+        if w.full_dims:
+            raise ValueError("a rescaled workload has no block form")
         lo, hi = torch.min(S), torch.max(S)
         S = (S - lo) / (hi - lo)
-    S = S.to(dtype)
-    X, _ = add_noise(S, w.snr_db, w.seed, w.tensor_id)
-    return X, cores
+        s_norm2 = float(torch.sum(S * S))
+    else:
+        s_norm2 = tr_norm2(cores)
+    if w.snr_db is not None:
+        sigma = noise_sigma(s_norm2, int(np.prod(full)), w.snr_db)
+        noise_block(w.seed, w.tensor_id, full, w.dims, device, out=S, scale=sigma)
+    X = S if dtype == torch.float64 else S.to(dtype)
+    return X, block
 
 
 def make_init(w: Workload):
