@@ -46,34 +46,140 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(I_full, I_sample=80):
-    """The FP64 oracle on the same recipe at I_sample^4; the stages that stream X scale by
-    (I_full / I_sample)^4, the TR-ALS stage (same K^4 projected tensor) does not."""
+# Kernels timed at profiling level 1 (those that stream X), the stage of Alg. 1 each belongs
+# to, and how many modes one launch covers (for the per-launch share of the stage's bytes).
+KERNEL_STAGE = {"sketch_partial": "sketch", "sketch_fused": "sketch", "sketch_slab": "sketch",
+                "power_partial": "power", "power_fused": "power", "power_slab": "power",
+                "ttm_first": "compress", "compress_fused": "compress"}
+MODES_PER_LAUNCH = {"sketch_partial": 1, "sketch_fused": 1, "sketch_slab": 2,
+                    "power_partial": 1, "power_fused": 1, "power_slab": 2}
+
+
+def measure_read_peak(rt, h, X, reps=5):
+    """Achievable HBM read rate: the library's 16-byte read-stream probe over X, median of
+    ``reps`` launches timed with HIP events on the launch stream."""
+    import torch
+    rt.rtr_read_probe(h, X)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        rt.rtr_profile_reset(h)
+        rt.rtr_profile_enable(h, 1)
+        rt.rtr_read_probe(h, X)
+        rt.rtr_profile_enable(h, 0)
+        ms, n = rt.rtr_profile_read(h, "read_probe")
+        times.append(ms / max(n, 1))
+    rt.rtr_profile_reset(h)
+    ms = float(np.median(times))
+    nbytes = X.numel() * X.element_size()
+    return {"gbps": round(nbytes / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4), "bytes": nbytes}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(I_full, block=64, reps=3):
+    """The FP64 oracle, stage by stage, on the leading block^4 block of the dense workload
+    (exactly X[:block, ..] of the I_full^4 tensor: same cores, noise and sigma), median of
+    ``reps`` runs per stage.  ``value`` scales the stages that stream X (Gaussian draws, sketch
+    and power products, compression) by (I_full / block)^4 and the QR by I_full / block; TR-ALS
+    and back-projection work on the same K^4 projected tensor and are not scaled."""
     import torch
     from threadpoolctl import threadpool_info
     import workloads as W
     from oracle import rtr as orc
+    from oracle.tensor import unfold
 
-    w = W.dense_200(I=I_sample)
-    X, _ = W.make_tensor(w)
-    X = X.float().double().numpy()
+    w = W.dense_200_block(block, I=I_full)
+    X, _ = W.make_tensor(w, dtype=torch.float32)
+    X = X.numpy().astype(np.float64)
     Z0 = W.make_init(w)
-    t0 = time.perf_counter()
-    Qs = [orc.range_basis(X, n, w.K[n], w.q, w.seed) for n in range(4)]
-    P = orc.compress(X, Qs)
-    t1 = time.perf_counter()
-    Z, _ = orc.tr_als(P, Z0, w.sweeps)
-    orc.backproject(Z, Qs)
-    t2 = time.perf_counter()
-    scale = (I_full / I_sample) ** 4
-    est_ms = ((t1 - t0) * scale + (t2 - t1)) * 1e3
+    names = ("rng", "sketch_gemm", "qr", "power_gemm", "compress", "tr_als", "backproject")
+    runs = {k: [] for k in names}
+    pc = time.perf_counter
+    for _ in range(reps):
+        t = dict.fromkeys(names, 0.0)
+        Qs = []
+        for n in range(X.ndim):
+            t0 = pc()
+            A = unfold(X, n)
+            t1 = pc()
+            M = orc.gaussian_test_matrix(w.seed, n, A.shape[1], w.K[n])
+            t2 = pc()
+            Y = A @ M
+            t3 = pc()
+            Q, _ = orc.qr_pos(Y)
+            t4 = pc()
+            t["sketch_gemm"] += (t1 - t0) + (t3 - t2)
+            t["rng"] += t2 - t1
+            t["qr"] += t4 - t3
+            for _ in range(w.q):
+                t0 = pc()
+                B = A.T @ Q
+                t1 = pc()
+                Wq, _ = orc.qr_pos(B)
+                t2 = pc()
+                Y = A @ Wq
+                t3 = pc()
+                Q, _ = orc.qr_pos(Y)
+                t4 = pc()
+                t["power_gemm"] += (t1 - t0) + (t3 - t2)
+                t["qr"] += (t2 - t1) + (t4 - t3)
+            Qs.append(Q)
+        t0 = pc()
+        P = orc.compress(X, Qs)
+        t1 = pc()
+        Z, _ = orc.tr_als(P, Z0, w.sweeps)
+        t2 = pc()
+        orc.backproject(Z, Qs)
+        t3 = pc()
+        t["compress"] = t1 - t0
+        t["tr_als"] = t2 - t1
+        t["backproject"] = t3 - t2
+        for k in names:
+            runs[k].append(t[k])
+    med = {k: float(np.median(v)) for k, v in runs.items()}
+    f4 = (I_full / block) ** 4
+    f1 = I_full / block
+    scaled = {"rng": f4, "sketch_gemm": f4, "power_gemm": f4, "compress": f4, "qr": f1,
+              "tr_als": 1.0, "backproject": f1}
+    est_s = sum(med[k] * scaled[k] for k in names)
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    del torch
-    return {"value": round(est_ms, 1), "unit": "ms", "cores": int(threads), "kind": "oracle",
-            "sample": (f"FP64 oracle on the same recipe at {I_sample}^4 (K=20, q=1, rank 6, 30 sweeps): "
-                       f"sketch+QR+power+compression {t1 - t0:.2f} s scaled by ({I_full}/{I_sample})^4="
-                       f"{scale:.1f}, TR-ALS+back-projection {t2 - t1:.2f} s unscaled; "
-                       f"host os.cpu_count()={os.cpu_count()}")}
+    return {"value": round(est_s * 1e3, 1), "unit": "ms", "cores": int(threads), "kind": "oracle",
+            "sample": (f"FP64 oracle per stage on the {block}^4 block X[:{block}]^4 of the "
+                       f"{I_full}^4 tensor (K=20, q=1, rank 6, 30 sweeps), median of {reps}; "
+                       f"X-streaming stages scaled by ({I_full}/{block})^4 = {f4:.1f}, QR by "
+                       f"{f1:.3g}, TR-ALS unscaled"),
+            "block_ms_per_stage": {k: round(v * 1e3, 1) for k, v in med.items()},
+            "block_ms": round(sum(med.values()) * 1e3, 1),
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
+
+
+def gpu_block(rt, h, I_full, compute, block=64, reps=5):
+    """The GPU path on the same block^4 block, for a like-for-like line beside the oracle."""
+    import torch
+    import workloads as W
+    from paper_1901_01652_amd import pipeline
+    w = W.dense_200_block(block, I=I_full)
+    X, _ = W.make_tensor(w, device="cuda:0", dtype=torch.float32)
+    Z0 = rt.pack(W.make_init(w), "cuda:0")
+    pipeline.rtr_als(h, X, w.K, w.ranks, Z0, w.sweeps, w.q, w.seed, compute=compute)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = pipeline.rtr_als(h, X, w.K, w.ranks, Z0, w.sweeps, w.q, w.seed, compute=compute)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"ms": round(ms, 3), "rse": round(pipeline.rse(h, X, w.ranks, out["G"]), 6),
+            "compute": compute}
 
 
 def bench_tr_svd(rt, h, P, eps=0.15, reps=3):
@@ -239,29 +345,47 @@ def main():
         log("[bench] copy probe: 1 GiB read + 1 GiB written")
         del src, dst
 
+    read_peak = measure_read_peak(rt, h, X)
+    log(f"[bench] read-stream probe over X: {read_peak['gbps']} GB/s")
     log(f"[bench] {args.compute}: warmup {args.warmup}, {args.steps} timed steps")
     out, ms, wall = timed(args.compute, args.steps, args.warmup, True)
     log(f"[bench] {args.compute}: {ms:.2f} ms/step (host wall {wall:.2f})")
 
     numel = w.numel()
     xbytes = numel * 4
+    N = len(w.dims)
     kern = {}
-    for name in ("sketch_partial", "power_partial", "ttm_first", "sketch_fused", "power_fused",
-                 "compress_fused"):
+    for name in KERNEL_STAGE:
         tot, n = rt.rtr_profile_read(h, name)
         if n:
-            kern[name] = {"total_ms": tot, "launches": n, "avg_ms": tot / n}
-    # algorithmic bytes per launch: one read of X, plus the FP64 intermediate written by the
-    # unfused first compression pass
-    mid_bytes = numel // w.dims[0] * w.K[0] * 8
-    alg = {"sketch_partial": xbytes, "power_partial": xbytes, "sketch_fused": xbytes,
-           "power_fused": xbytes, "compress_fused": xbytes, "ttm_first": xbytes + mid_bytes}
+            kern[name] = {"total_ms": tot, "launches": n, "avg_ms": tot / n,
+                          "stage": KERNEL_STAGE[name],
+                          # per-launch HBM efficiency: bytes this launch streams (one read of X)
+                          "launch_gbps": round(xbytes / (tot / n * 1e-3) / 1e9, 1)}
+    # algorithmic bytes of each stage per step (one read of X for the sketch of every mode,
+    # ceil(N/2) reads per power round, one read for the compression) over the stage's
+    # measured kernel time per step
+    stage_alg = {"sketch": xbytes, "power": w.q * ((N + 1) // 2) * xbytes, "compress": xbytes}
+    stages = {}
+    for st, alg in stage_alg.items():
+        ms_st = sum(k["total_ms"] for k in kern.values() if k["stage"] == st) / args.steps
+        if ms_st > 0:
+            gbps = alg / (ms_st * 1e-3) / 1e9
+            stages[st] = {"alg_bytes": alg, "ms_per_step": round(ms_st, 4), "gbps": round(gbps, 1),
+                          "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                          "frac_measured_peak": round(gbps / read_peak["gbps"], 4)}
+    # dominant kernel; its algorithmic bytes per launch are its stage's bytes per mode times
+    # the modes one launch covers
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
-    achieved = alg[dom] / (kern[dom]["avg_ms"] * 1e-3) / 1e9
+    st = KERNEL_STAGE[dom]
+    alg_launch = stage_alg[st] * MODES_PER_LAUNCH.get(dom, N) / N
+    achieved = alg_launch / (kern[dom]["avg_ms"] * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": measured_traffic(dom, f"dense-{args.size}^4 {args.compute}"),
-            "alg_bytes_per_launch": alg[dom], "avg_launch_ms": round(kern[dom]["avg_ms"], 4)}
+            "alg_bytes_per_launch": int(alg_launch), "avg_launch_ms": round(kern[dom]["avg_ms"], 4),
+            "measured_read_peak_gbps": read_peak["gbps"],
+            "frac_measured_peak": round(achieved / read_peak["gbps"], 4)}
 
     rt.rtr_residual(h, X, w.ranks, out["G"])            # warm-up (workspace)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -304,6 +428,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] FP64 oracle on the host (bounded sample)")
         cpu = cpu_baseline(args.size)
+        cpu["gpu_same_block"] = gpu_block(rt, h, args.size, args.compute)
 
     line = {
         "metric": "end-to-end rTR-ALS time + sketch HBM GB/s (% roofline) at stated rel. error",
@@ -318,7 +443,8 @@ def main():
         "rse": round(rse, 6), "rse_pythagorean": round(rse_py, 6), "p_err": round(e, 6),
         "rse_explicit": {"ms": round(res_ms, 3), "gbps": round(xbytes / (res_ms * 1e-3) / 1e9, 1),
                          "note": "one extra pass over X (timed apart from the step)"},
-        "roofline": roof, "kernels": kern, "fp32_path": fp32, "cpu_baseline": cpu,
+        "roofline": roof, "stages": stages, "read_peak": read_peak, "kernels": kern,
+        "fp32_path": fp32, "cpu_baseline": cpu,
         "tr_svd": svd, "batched": batched, "warm_start": warm,
     }
     h.close()

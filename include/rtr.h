@@ -42,7 +42,11 @@
  * Memory and execution
  * --------------------
  * - Every array argument named "device" is caller-owned device memory; the library reads
- *   or writes it only inside the work it enqueues and never frees it.  Host arrays
+ *   or writes it only inside the work it enqueues and never frees it.  Each such pointer is
+ *   checked before anything is enqueued: it must be memory of the handle's device
+ *   (hipMalloc'd or managed) whose allocation holds at least the bytes the call accesses
+ *   from that address; host memory (plain, pinned or registered) and memory of another
+ *   device are refused with RTR_ERR_INVALID_ARG.  Host arrays
  *   (dims, K, R, options) are read before the call returns.
  * - Calls enqueue work on ``stream`` (a hipStream_t; NULL = the legacy default stream) and
  *   return without waiting, except where a call says it synchronises.
@@ -151,8 +155,12 @@ typedef struct {
  *              (entries after the last sweep run are left untouched)
  *   sweeps_run device, 1 int32: sweeps performed
  * TR-ALS updates core n by the exact least-squares solution of Eq. (2) restricted to P
- * (normal equations, FP64 Cholesky).  A Gram matrix that is not positive definite sets
- * RTR_STATUS_CHOLESKY_FAILED and leaves that core unchanged.
+ * (normal equations in FP64, solved by Gauss-Jordan elimination without pivoting on
+ * [Gram | M^T]: every pivot of a positive-definite Gram is a positive Schur-complement
+ * diagonal, so the solution is the Cholesky one; systems whose augmented rows exceed 256
+ * entries use an FP64 Cholesky factorisation instead).  A Gram matrix that is not positive
+ * definite (a non-positive pivot) sets RTR_STATUS_CHOLESKY_FAILED and leaves that core
+ * unchanged.
  * RTR_METHOD_SVD is rejected with RTR_ERR_INVALID_ARG: TR-SVD chooses the ranks, so it has
  * its own entry point, rtr_decompose_svd.
  */
@@ -189,8 +197,9 @@ rtr_status rtr_decompose_svd(rtr_handle h, const double* P, int32_t order, const
  * Batched Alg. 1 step 9: TR-ALS on many small projected tensors in ONE persistent launch
  * (one work-group per tensor runs all of that tensor's sweeps with its cores in LDS).
  * The per-tensor arithmetic is that of rtr_decompose (RTR_METHOD_ALS): exact least-squares
- * core updates by the normal equations in FP64; err_trace[s] = ||P - Psi(Z)|| / ||P|| after
- * sweep s (computed from the Gram: ||P||^2 - 2 <M, W> + <W, G W>), stopping rule as there.
+ * core updates by the normal equations in FP64 (Gauss-Jordan); err_trace[s] =
+ * ||P - Psi(Z)|| / ||P|| after sweep s, computed explicitly (the residual of every entry of P
+ * is accumulated in the tile pass that follows the sweep), stopping rule as there.
  * A Gram that is not positive definite skips that update and sets RTR_STATUS_CHOLESKY_FAILED.
  *   items      host array of count entries; every pointer in it is a device pointer
  *   Limits: 2 <= order <= 8, K'_n <= 64, R_n <= 6, R_n R_{n+1} <= prod_{m != n} K'_m, and the
@@ -323,6 +332,15 @@ rtr_status rtr_status_sync(rtr_handle h, void* stream, uint32_t* bits);
  * records.
  */
 rtr_status rtr_profile_enable(rtr_handle h, int32_t on);
+/*
+ * Measurement helper: stream ``bytes`` of device memory at ``x`` once with 16-byte loads
+ * over a persistent grid and write their sum (as FP32 values, FP64 total) to out[0].  Its
+ * launch time, recorded as kernel "read_probe", is the device's achievable HBM read rate:
+ * the measured peak the passes over X are compared against beside the published 8 TB/s.
+ *   x    device, 16-byte aligned;  bytes a positive multiple of 16;  out device, 1 FP64.
+ */
+rtr_status rtr_read_probe(rtr_handle h, const void* x, int64_t bytes, double* out,
+                          void* stream);
 rtr_status rtr_profile_reset(rtr_handle h);
 rtr_status rtr_profile_read(rtr_handle h, const char* name, double* total_ms,
                             int64_t* launches);

@@ -87,6 +87,7 @@ def _load():
         "rtr_normals": [vp, u64, u32, u32, i64, i64, ctypes.c_int, vp, vp],
         "rtr_status_sync": [vp, vp, ctypes.POINTER(u32)],
         "rtr_profile_enable": [vp, i32],
+        "rtr_read_probe": [vp, vp, i64, vp, vp],
         "rtr_profile_reset": [vp],
         "rtr_profile_read": [vp, ctypes.c_char_p, ctypes.POINTER(dp), P64],
     }
@@ -448,6 +449,15 @@ def rtr_status_sync(h, stream=None, device=0):
     if st not in (0, 5):
         h.check(st)
     return int(bits.value)
+
+
+def rtr_read_probe(h, x, out=None, stream=None):
+    """HBM read-stream probe over the bytes of device tensor ``x`` (timed as "read_probe")."""
+    if out is None:
+        out = torch.zeros(1, dtype=torch.float64, device=x.device)
+    h.check(lib.rtr_read_probe(h.ptr, _ptr(x), int(x.numel() * x.element_size()), _ptr(out),
+                               _stream(stream, x.device)))
+    return out
 
 
 def rtr_profile_enable(h, level=1):

@@ -13,9 +13,12 @@
 //            sweep reports the error of the sweep before it without another pass.
 // als_solve  one work-group: fixed-order sum of the partials; Gram from transfer matrices
 //            E_m = sum_i Z_m(i) (x) Z_m(i) multiplied around the ring (FP64 matrix cores)
-//            when every rank is small; FP64 Cholesky (rows in lane registers, each column
-//            passed through LDS once); forward and back substitution for every row of M;
-//            the new core.  It also closes the previous sweep (error, stopping test, and
+//            when every rank is small; the normal equations solved in FP64 by Gauss-Jordan
+//            elimination without pivoting on [Gram | M^T] (solve.hpp: every pivot of a
+//            positive-definite Gram is a positive Schur-complement diagonal, so this gives
+//            the Cholesky solution; a non-positive pivot is the failure flag); the new core.
+//            Cholesky with forward and back substitution remains only as the fallback for
+//            systems too large for the Gauss-Jordan register tiers.  It also closes the previous sweep (error, stopping test, and
 //            the device flag that turns every later kernel of the decomposition into a no-op).
 #include <algorithm>
 

@@ -263,4 +263,9 @@ size_t tr_loss4_lds(const TrLoss4& sh);
 hipError_t launch_tr_loss4(const float* y, const float* tgt, int dout, const TrLoss4& sh,
                            float gscale, int batch, float* loss, float* dy, hipStream_t s);
 
+// ---- probe.hip: HBM read-stream probe -------------------------------------------------
+int probe_blocks();
+hipError_t launch_read_probe(const void* x, int64_t bytes, double* part, double* out,
+                             hipStream_t s);
+
 }  // namespace rtr

@@ -132,6 +132,60 @@ rtr_status check_handle(rtr_context* h) {
   return RTR_OK;
 }
 
+// A device array argument: memory of the handle's device (hipMalloc'd or managed) whose
+// allocation covers [p, p + bytes).  Host memory (pinned, registered or plain) and memory of
+// another device are rejected here, before anything is enqueued, instead of faulting a kernel.
+// Where the runtime cannot report the allocation's extent the size check is skipped.
+rtr_status check_dev(rtr_context* h, const void* p, size_t bytes, const char* what) {
+  if (!p) return fail(h, RTR_ERR_INVALID_ARG, std::string(what) + " is NULL");
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof(a));
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, RTR_ERR_INVALID_ARG, std::string(what) + " is not device memory");
+  }
+  if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+    return fail(h, RTR_ERR_INVALID_ARG, std::string(what) + " is not device memory (memory type " +
+                                            std::to_string((int)a.type) + ")");
+  if (a.device != h->device)
+    return fail(h, RTR_ERR_INVALID_ARG, std::string(what) + " is memory of device " +
+                                            std::to_string(a.device) + ", not of the handle's device " +
+                                            std::to_string(h->device));
+  if (bytes > 0) {
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return RTR_OK;
+    }
+    const uintptr_t end = (uintptr_t)base + size, q = (uintptr_t)p;
+    if (q < (uintptr_t)base || bytes > end - q)
+      return fail(h, RTR_ERR_INVALID_ARG, std::string(what) + " holds " + std::to_string(end - q) +
+                                              " bytes from the given address, the call accesses " +
+                                              std::to_string(bytes));
+  }
+  return RTR_OK;
+}
+
+// Optional device argument: NULL is accepted.
+rtr_status check_dev_opt(rtr_context* h, const void* p, size_t bytes, const char* what) {
+  return p ? check_dev(h, p, bytes, what) : RTR_OK;
+}
+
+#define CHECK_DEV(p, bytes, what)                             \
+  do {                                                        \
+    rtr_status s_ = check_dev(h, (p), (bytes), (what));       \
+    if (s_) return s_;                                        \
+  } while (0)
+
+size_t x_bytes(const int64_t* dims, int order, rtr_dtype dt) {
+  size_t z = dt == RTR_F64 ? 8 : 4;
+  for (int n = 0; n < order; ++n) z *= (size_t)dims[n];
+  return z;
+}
+
 rtr_status check_shape(rtr_context* h, int32_t order, const int64_t* dims, const int32_t* K) {
   if (order < 1 || order > RTR_MAX_ORDER)
     return fail(h, RTR_ERR_INVALID_ARG, "order must be in [1, " + std::to_string(RTR_MAX_ORDER) + "]");
@@ -166,6 +220,12 @@ int64_t keff(const int64_t* dims, const int32_t* K, int n) {
   return K[n] < dims[n] ? (int64_t)K[n] : dims[n];
 }
 
+size_t q_bytes(const int64_t* dims, const int32_t* K, int order) {
+  size_t z = 0;
+  for (int n = 0; n < order; ++n) z += (size_t)dims[n] * keff(dims, K, n);
+  return z * sizeof(double);
+}
+
 rtr::ModeView mode_view(const int64_t* dims, int order, int n) {
   rtr::ModeView v{1, dims[n], 1};
   for (int m = 0; m < n; ++m) v.A *= dims[m];
@@ -179,7 +239,7 @@ namespace rtr {
 static bool streams_x(const char* name) {
   static const char* const kNames[] = {"sketch_partial", "power_partial", "ttm_first",
                                        "residual", "sketch_fused", "power_fused",
-                                       "compress_fused"};
+                                       "compress_fused", "read_probe"};
   for (const char* k : kNames)
     if (std::strcmp(k, name) == 0) return true;
   return false;
@@ -278,11 +338,12 @@ rtr_status rtr_sketch(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t or
   Guard guard(h);
   if ((st = check_shape(h, order, dims, K))) return st;
   if (!K) return fail(h, RTR_ERR_INVALID_ARG, "K is NULL");
-  if (!X || !Q) return fail(h, RTR_ERR_INVALID_ARG, "X and Q must be device pointers");
   if (power_iters < 0 || power_iters > 64)
     return fail(h, RTR_ERR_INVALID_ARG, "power_iters must be in [0, 64]");
   rtr::Arith ar;
   if ((st = check_arith(h, x_dtype, compute, &ar))) return st;
+  CHECK_DEV(X, x_bytes(dims, order, x_dtype), "X");
+  CHECK_DEV(Q, q_bytes(dims, K, order), "Q");
   hipStream_t s = (hipStream_t)stream;
 
   // workspace: partial sums (largest mode), then per mode Ycol and Qwork
@@ -398,9 +459,16 @@ rtr_status rtr_compress(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t 
   Guard guard(h);
   if ((st = check_shape(h, order, dims, K))) return st;
   if (!K) return fail(h, RTR_ERR_INVALID_ARG, "K is NULL");
-  if (!X || !Q || !P) return fail(h, RTR_ERR_INVALID_ARG, "X, Q and P must be device pointers");
   rtr::Arith ar;
   if ((st = check_arith(h, x_dtype, compute, &ar))) return st;
+  CHECK_DEV(X, x_bytes(dims, order, x_dtype), "X");
+  CHECK_DEV(Q, q_bytes(dims, K, order), "Q");
+  {
+    size_t pb = sizeof(double);
+    for (int n = 0; n < order; ++n) pb *= (size_t)keff(dims, K, n);
+    CHECK_DEV(P, pb, "P");
+  }
+  if ((st = check_dev_opt(h, p_norm2, sizeof(double), "p_norm2"))) return st;
   hipStream_t s = (hipStream_t)stream;
   for (int n = 0; n < order; ++n)
     if (keff(dims, K, n) > 64)
@@ -548,6 +616,11 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
     noutmax = std::max(noutmax, g.Kn * g.RR + g.RR * g.RR);
     chunkmax = std::max(chunkmax, rtr::als_chunks(g));
   }
+  CHECK_DEV(P, (size_t)total * sizeof(double), "P");
+  CHECK_DEV(Z_init, zoff[order] * sizeof(double), "Z_init");
+  CHECK_DEV(Z, zoff[order] * sizeof(double), "Z");
+  CHECK_DEV(err_trace, (size_t)opts->max_sweeps * sizeof(double), "err_trace");
+  CHECK_DEV(sweeps_run, sizeof(int32_t), "sweeps_run");
   int rmax = 0;
   for (int n = 0; n < order; ++n) rmax = std::max(rmax, (int)R[n]);
   // Gram from transfer matrices when every rank is at most 7 and the cores fit the solve's
@@ -724,6 +797,14 @@ rtr_status rtr_decompose_svd(rtr_handle h, const double* P, int32_t order, const
     total *= Kp[n];
     if (total > ((int64_t)1 << 31)) return fail(h, RTR_ERR_UNSUPPORTED, "P above 2^31 entries");
   }
+  {
+    size_t zb = 0;
+    for (int n = 0; n < order; ++n) zb += (size_t)Rcap[n] * Kp[n] * Rcap[(n + 1) % order];
+    CHECK_DEV(P, (size_t)total * sizeof(double), "P");
+    CHECK_DEV(Z, zb * sizeof(double), "Z");
+    CHECK_DEV(ranks, (size_t)order * sizeof(int32_t), "ranks");
+    CHECK_DEV(err, sizeof(double), "err");
+  }
   // Bounds of the Gram sizes: step 0 has d_0 = min(K_1, prod K / K_1); R_1 <= R_2 and
   // R_1 R_2 <= d_0; step k >= 1 works on (R_{k+1} K_k) x (K_{k+1} .. K_N R_1) with
   // R_{k+1} <= min(cap, d_{k-1}).
@@ -852,6 +933,13 @@ rtr_status plan_batch(rtr_context* h, const rtr_als_item* items, int32_t count,
       maxRR = std::max(maxRR, (int)(it.R[n] * rb));
     }
     maxZ = std::max(maxZ, ztot);
+    rtr_status sc;
+    if ((sc = check_dev(h, it.P, (size_t)total * sizeof(double), (where + "P").c_str())) ||
+        (sc = check_dev(h, it.Z_init, (size_t)ztot * sizeof(double), (where + "Z_init").c_str())) ||
+        (sc = check_dev(h, it.Z, (size_t)ztot * sizeof(double), (where + "Z").c_str())) ||
+        (sc = check_dev(h, it.err_trace, (size_t)max_sweeps * sizeof(double), (where + "err_trace").c_str())) ||
+        (sc = check_dev(h, it.sweeps_run, sizeof(int32_t), (where + "sweeps_run").c_str())))
+      return sc;
     plan->items[t] = a;
   }
   if (!rtr::batch_layout(maxK, maxRR, maxR, maxZ, minK, &plan->lay, &plan->mq, &plan->gq))
@@ -976,6 +1064,18 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
   rtr_status st = check_handle(h);
   if (st) return st;
   if (!items || count < 1) return fail(h, RTR_ERR_INVALID_ARG, "items must hold count >= 1 entries");
+  hipStream_t s = (hipStream_t)stream;
+  // A call identical to the captured one (same item array and parameters) replays the graph;
+  // its arguments were validated when it was captured.
+  uint64_t key = 1469598103934665603ull;
+  key = fnv(key, items, sizeof(rtr_batch_item) * (size_t)count);
+  const int64_t params[5] = {count, x_dtype, compute, power_iters, max_sweeps};
+  key = fnv(key, params, sizeof(params));
+  key = fnv(key, &tol, sizeof(tol));
+  if (use_graph && h->gexec && key == h->gkey && h->gepoch == h->ws_epoch) {
+    HIP_TRY(hipGraphLaunch(h->gexec, s), "hipGraphLaunch");
+    return RTR_OK;
+  }
   std::vector<rtr_als_item> als(count);
   for (int t = 0; t < count; ++t) {
     const rtr_batch_item& it = items[t];
@@ -996,6 +1096,17 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
       a.Kp[n] = (int32_t)keff(it.dims, it.K, n);
       a.R[n] = it.R[n];
     }
+    if (x_dtype != RTR_F64 && x_dtype != RTR_F32)
+      return fail(h, RTR_ERR_UNSUPPORTED, "X must be FP64 or FP32");
+    const std::string where = "item " + std::to_string(t) + ": ";
+    size_t gb = 0;
+    for (int n = 0; n < it.order; ++n)
+      gb += (size_t)std::max(it.R[n], 1) * it.dims[n] * std::max(it.R[(n + 1) % it.order], 1);
+    rtr_status sc;
+    if ((sc = check_dev(h, it.X, x_bytes(it.dims, it.order, x_dtype), (where + "X").c_str())) ||
+        (sc = check_dev(h, it.Q, q_bytes(it.dims, it.K, it.order), (where + "Q").c_str())) ||
+        (sc = check_dev_opt(h, it.G, gb * sizeof(double), (where + "G").c_str())))
+      return sc;
     als[t] = a;
   }
   BatchPlan plan;
@@ -1003,16 +1114,6 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
     Guard guard(h);
     st = plan_batch(h, als.data(), count, max_sweeps, tol, &plan);
     if (st) return st;
-  }
-  hipStream_t s = (hipStream_t)stream;
-  uint64_t key = 1469598103934665603ull;
-  key = fnv(key, items, sizeof(rtr_batch_item) * (size_t)count);
-  const int64_t params[5] = {count, x_dtype, compute, power_iters, max_sweeps};
-  key = fnv(key, params, sizeof(params));
-  key = fnv(key, &tol, sizeof(tol));
-  if (use_graph && h->gexec && key == h->gkey && h->gepoch == h->ws_epoch) {
-    HIP_TRY(hipGraphLaunch(h->gexec, s), "hipGraphLaunch");
-    return RTR_OK;
   }
   // eager run (also sizes the workspace for the capture below)
   h->ws_hi = 0;
@@ -1135,6 +1236,8 @@ rtr_status rtr_mlp_normalize(rtr_handle h, const double* P, int64_t dim, int32_t
   if (st) return st;
   Guard guard(h);
   if (!P || !out || dim < 1 || rows < 1) return fail(h, RTR_ERR_INVALID_ARG, "bad arguments");
+  CHECK_DEV(P, (size_t)dim * rows * sizeof(double), "P");
+  CHECK_DEV(out, (size_t)dim * rows * sizeof(float), "out");
   HIP_TRY(rtr::launch_normalize(P, dim, rows, out, (hipStream_t)stream), "normalize");
   return RTR_OK;
 } catch (...) {
@@ -1152,6 +1255,13 @@ rtr_status rtr_mlp_forward(rtr_handle h, int32_t layers, const int32_t* sizes,
   if (st) return st;
   if (!W || !b || !x || !y || (layers > 1 && !acts))
     return fail(h, RTR_ERR_INVALID_ARG, "W, b, x, y (and acts for hidden layers) required");
+  CHECK_DEV(x, (size_t)batch * sizes[0] * sizeof(float), "x");
+  CHECK_DEV(y, (size_t)batch * sizes[layers] * sizeof(float), "y");
+  for (int l = 0; l < layers; ++l) {
+    CHECK_DEV(W[l], (size_t)sizes[l] * sizes[l + 1] * sizeof(float), "W[l]");
+    CHECK_DEV(b[l], (size_t)sizes[l + 1] * sizeof(float), "b[l]");
+    if (l < layers - 1) CHECK_DEV(acts[l], (size_t)batch * sizes[l + 1] * sizeof(float), "acts[l]");
+  }
   size_t need = 0;
   for (int l = 0; l < layers; ++l) need = std::max(need, gemm_ws_floats(batch, sizes[l + 1], sizes[l]));
   st = ensure_ws(h, need * sizeof(float) + 256);
@@ -1188,6 +1298,13 @@ rtr_status rtr_mlp_tr_loss(rtr_handle h, const float* y, const float* target, in
     dout += R[n] * K[n] * R[(n + 1) % 4];
   }
   sh.zpad = (dout + 63) & ~63;
+  {
+    const size_t pk = (size_t)K[0] * K[1] * K[2] * K[3];
+    CHECK_DEV(y, (size_t)batch * dout * sizeof(float), "y");
+    CHECK_DEV(dy, (size_t)batch * dout * sizeof(float), "dy");
+    CHECK_DEV(target, (size_t)batch * pk * sizeof(float), "target");
+    CHECK_DEV(loss, (size_t)batch * sizeof(float), "loss");
+  }
   const size_t lds = rtr::tr_loss4_lds(sh);
   if (lds > 150 * 1024)
     return fail(h, RTR_ERR_UNSUPPORTED, "K_1 K_2 K_3 K_4 too large for the per-sample work-group");
@@ -1209,6 +1326,14 @@ rtr_status rtr_mlp_backward(rtr_handle h, int32_t layers, const int32_t* sizes,
   if (st) return st;
   if (!W || !x || !dy || !dW || !db || (layers > 1 && !acts))
     return fail(h, RTR_ERR_INVALID_ARG, "W, x, dy, dW, db (and acts for hidden layers) required");
+  CHECK_DEV(x, (size_t)batch * sizes[0] * sizeof(float), "x");
+  CHECK_DEV(dy, (size_t)batch * sizes[layers] * sizeof(float), "dy");
+  for (int l = 0; l < layers; ++l) {
+    CHECK_DEV(W[l], (size_t)sizes[l] * sizes[l + 1] * sizeof(float), "W[l]");
+    CHECK_DEV(dW[l], (size_t)sizes[l] * sizes[l + 1] * sizeof(float), "dW[l]");
+    CHECK_DEV(db[l], (size_t)sizes[l + 1] * sizeof(float), "db[l]");
+    if (l < layers - 1) CHECK_DEV(acts[l], (size_t)batch * sizes[l + 1] * sizeof(float), "acts[l]");
+  }
   size_t need = 0, gmax = 0;
   for (int l = 0; l < layers; ++l) {
     need = std::max(need, gemm_ws_floats(sizes[l], sizes[l + 1], batch));
@@ -1254,6 +1379,10 @@ rtr_status rtr_mlp_adam(rtr_handle h, float* w, const float* g, float* m, float*
   if (st) return st;
   Guard guard(h);
   if (!w || !g || !m || !v || n < 1 || step < 1) return fail(h, RTR_ERR_INVALID_ARG, "bad arguments");
+  CHECK_DEV(w, (size_t)n * sizeof(float), "w");
+  CHECK_DEV(g, (size_t)n * sizeof(float), "g");
+  CHECK_DEV(m, (size_t)n * sizeof(float), "m");
+  CHECK_DEV(v, (size_t)n * sizeof(float), "v");
   HIP_TRY(rtr::launch_adam(w, g, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream), "adam");
   return RTR_OK;
 } catch (...) {
@@ -1266,6 +1395,9 @@ rtr_status rtr_mlp_to_cores(rtr_handle h, const float* y, int64_t per_row, int32
   if (st) return st;
   Guard guard(h);
   if (!y || !Z || per_row < 1 || rows < 1 || order < 1) return fail(h, RTR_ERR_INVALID_ARG, "bad arguments");
+  CHECK_DEV(y, (size_t)per_row * rows * sizeof(float), "y");
+  CHECK_DEV(Z, (size_t)per_row * rows * sizeof(double), "Z");
+  if ((st = check_dev_opt(h, p_norm2, (size_t)rows * sizeof(double), "p_norm2"))) return st;
   HIP_TRY(rtr::launch_to_f64(y, per_row * rows, per_row, p_norm2, order, Z, (hipStream_t)stream),
           "to f64");
   return RTR_OK;
@@ -1285,6 +1417,17 @@ rtr_status rtr_backproject(rtr_handle h, int32_t order, const int64_t* dims, con
   if (!Z || !Q || !G) return fail(h, RTR_ERR_INVALID_ARG, "Z, Q and G must be device pointers");
   for (int n = 0; n < order; ++n)
     if (R[n] < 1 || R[n] > RTR_MAX_RANK) return fail(h, RTR_ERR_INVALID_ARG, "rank out of range");
+  {
+    size_t zb = 0, gb = 0;
+    for (int n = 0; n < order; ++n) {
+      const size_t rr = (size_t)R[n] * R[(n + 1) % order];
+      zb += rr * keff(dims, K, n);
+      gb += rr * dims[n];
+    }
+    CHECK_DEV(Z, zb * sizeof(double), "Z");
+    CHECK_DEV(Q, q_bytes(dims, K, order), "Q");
+    CHECK_DEV(G, gb * sizeof(double), "G");
+  }
   hipStream_t s = (hipStream_t)stream;
   size_t zo = 0, qo = 0, go = 0;
   for (int n = 0; n < order; ++n) {
@@ -1316,6 +1459,13 @@ rtr_status rtr_residual(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t 
     return fail(h, RTR_ERR_UNSUPPORTED, "X must be FP64 or FP32");
   for (int n = 0; n < order; ++n)
     if (R[n] < 1 || R[n] > RTR_MAX_RANK) return fail(h, RTR_ERR_INVALID_ARG, "rank out of range");
+  {
+    size_t gb = 0;
+    for (int n = 0; n < order; ++n) gb += (size_t)R[n] * dims[n] * R[(n + 1) % order];
+    CHECK_DEV(X, x_bytes(dims, order, x_dtype), "X");
+    CHECK_DEV(G, gb * sizeof(double), "G");
+    CHECK_DEV(out, 2 * sizeof(double), "out");
+  }
   hipStream_t s = (hipStream_t)stream;
   const int hm = order / 2;
   int64_t IL = 1, IR = 1;
@@ -1376,9 +1526,28 @@ rtr_status rtr_normals(rtr_handle h, uint64_t seed, uint32_t stream_word, uint32
   if (count > 0 && !out) return fail(h, RTR_ERR_INVALID_ARG, "out must be a device pointer");
   if (dtype != RTR_F64 && dtype != RTR_F32)
     return fail(h, RTR_ERR_UNSUPPORTED, "normals are FP64 or FP32");
+  if (count > 0) CHECK_DEV(out, (size_t)count * (dtype == RTR_F64 ? 8 : 4), "out");
   HIP_TRY(rtr::launch_normals(dtype == RTR_F32, seed, stream_word, tensor_id, start, count, out,
                               (hipStream_t)stream),
           "normals");
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+// ---------------------------------------------------------------------------------------
+rtr_status rtr_read_probe(rtr_handle h, const void* x, int64_t bytes, double* out,
+                          void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if (bytes < 16 || bytes % 16 != 0 || ((uintptr_t)x & 15) != 0)
+    return fail(h, RTR_ERR_INVALID_ARG, "x must be 16-byte aligned and bytes a positive multiple of 16");
+  CHECK_DEV(x, (size_t)bytes, "x");
+  CHECK_DEV(out, sizeof(double), "out");
+  const int blocks = rtr::probe_blocks();
+  if ((st = ensure_ws(h, (size_t)blocks * sizeof(double) + 256))) return st;
+  HIP_TRY(rtr::launch_read_probe(x, bytes, (double*)h->ws, out, (hipStream_t)stream), "read probe");
   return RTR_OK;
 } catch (...) {
   return fail(h, RTR_ERR_INTERNAL, "unexpected exception");

@@ -1,0 +1,133 @@
+"""Parity on the kernel paths the benchmark times.
+
+* The large dense workload's recipe (order 4, rank-6 TR cores, 30 dB, K = 20, one power
+  iteration, TR-ALS rank 6 for 30 sweeps) on its 64^4 block: exactly X[:64, :64, :64, :64] of
+  the 200^4 tensor.  Each pass over X then streams 64^3 = 262144 columns in 4096 tiles of 64,
+  so every work-group of the matrix-core passes runs many tiles with the next one prefetched.
+  FP64, FP32 and BF16-sketch paths against the FP64 oracle: projectors, P, the per-sweep error
+  on P, Psi(G) at tol * max(1, cond) with cond from the oracle's conditioning probe
+  (tests/conditioning.py), the final RSE at the plain tolerance.
+* Single-tensor TR-ALS shapes that reach every Gauss-Jordan register tier of the solve and
+  the rank-6 accumulation the benchmark runs (K' = 20, R = 6), at 1e-10.
+"""
+import numpy as np
+import pytest
+import torch
+
+import conditioning as C
+import paper_1901_01652_amd as rt
+from paper_1901_01652_amd import pipeline
+from oracle import rtr as orc, tensor as ot
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16": 3e-3}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def h():
+    hd = rt.Handle(0)
+    yield hd
+    hd.close()
+
+
+@pytest.fixture(scope="module")
+def dense_block():
+    w = W.dense_200_block(64)
+    say("oracle + conditioning probe on", w.name)
+    X, _ = W.make_tensor(w, dtype=torch.float32)
+    X = X.numpy()
+    Z0 = W.make_init(w)
+    base, qref, cond = C.condition(X.astype(np.float64), w.K, Z0, w.sweeps, w.q, w.seed)
+    say("cond", {k: f"{v:.3g}" for k, v in cond.items()}, "oracle RSE", base["rse"])
+    return w, X, Z0, base, qref, cond
+
+
+@pytest.mark.parametrize("compute", ["f64", "f32", "bf16"])
+def test_dense_block_parity(h, dense_block, compute):
+    w, X, Z0, base, qref, cond = dense_block
+    tol = TOL[compute]
+    say("dense 64^4 block", compute)
+    Xin = X.astype(np.float64) if compute == "f64" else X
+    Xd = torch.as_tensor(Xin).to(DEV)
+    out = pipeline.rtr_als(h, Xd, w.K, w.ranks, Z0, w.sweeps, w.q, w.seed,
+                           compute=None if compute == "f64" else compute)
+    torch.cuda.synchronize()
+    Q = [t.cpu().numpy() for t in rt.unpack(out["Q"], rt.q_shapes(w.dims, w.K))]
+    G = [g.cpu().numpy() for g in rt.unpack(out["G"], rt.core_shapes(w.dims, w.ranks))]
+    got = {"proj": [q @ q.T for q in Q], "P": out["P"].cpu().numpy(),
+           "trace": out["err_trace"].cpu().numpy(), "psi": ot.tr_full(G),
+           "rse": pipeline.rse(h, Xd, w.ranks, out["G"])}
+    assert int(out["sweeps_run"].item()) == w.sweeps
+    errs = {k: C.distance(got[k], qref[k], k) for k in C.KEYS}
+    say(compute, {k: f"{errs[k]:.3g} (limit {tol * max(1.0, cond[k]):.3g})" for k in C.KEYS})
+    for k in ("proj", "P", "trace", "psi"):
+        assert errs[k] <= tol * max(1.0, cond[k]), (k, errs[k], cond[k])
+    assert errs["rse"] <= tol, errs["rse"]
+
+
+def als_case(dims, R, seed, noise=0.05):
+    G = W.tr_cores(seed, dims, [max(2, r) for r in R])
+    S = ot.tr_full(G)
+    P = S + noise * np.random.default_rng(seed).standard_normal(dims) * np.std(S)
+    return P, W.init_cores(seed + 1, dims, R)
+
+
+# tiers of the solve by augmented-matrix size ne = RR (RR + K'_n) over 1024 threads:
+# <1> ne <= 1024, <2> <= 2048, <4> <= 4096, <8> <= 8192, <16> <= 16384, and the Cholesky
+# fallback when a row exceeds 256 entries (RR + K'_n > 256)
+@pytest.mark.parametrize("dims,R,sweeps", [
+    ((20, 20, 20, 20), (6, 6, 6, 6), 10),     # the benchmark's updates: ne = 36 * 56, tier <2>
+    ((20, 20, 20, 20), (5, 5, 5, 5), 10),     # ne = 25 * 45 -> <2>
+    ((20, 20, 20, 20), (7, 7, 7, 7), 8),      # ne = 49 * 69 -> <4>
+    ((64, 10, 10, 10), (7, 7, 7, 7), 6),      # mode 1: ne = 49 * 113 -> <8>; others <4>
+    ((250, 6, 6), (4, 4, 4), 6),              # mode 1: 16 + 250 > 256 -> Cholesky fallback
+])
+def test_als_solve_tiers(h, dims, R, sweeps):
+    say("als tiers", dims, R)
+    P, Z0 = als_case(dims, R, 21)
+    Zo, tro = orc.tr_als(P, Z0, sweeps)
+    Z, tr, ns = rt.rtr_decompose(h, torch.as_tensor(P).to(DEV), R, rt.pack(Z0, DEV), sweeps)
+    assert rt.rtr_status_sync(h) == 0
+    assert int(ns.item()) == sweeps
+    Zg = [z.cpu().numpy() for z in rt.unpack(Z, rt.core_shapes(dims, R))]
+    e_tr = C.rel(tr.cpu().numpy(), tro)
+    e_psi = C.rel(ot.tr_full(Zg), ot.tr_full(Zo))
+    say("  trace", e_tr, "psi", e_psi)
+    assert e_tr < 1e-10 and e_psi < 1e-10
+
+
+def test_host_memory_rejected(h):
+    """Host arrays passed where the ABI takes device arrays are refused before anything is
+    enqueued (RTR_ERR_INVALID_ARG), for plain and for pinned host memory."""
+    say("host pointers")
+    s = torch.cuda.current_stream(DEV)
+    dims, K = (8, 9, 10), (3, 3, 3)
+    Xd = torch.randn(dims, dtype=torch.float64, device=DEV)
+    Qd = torch.empty(rt.q_size(dims, K), dtype=torch.float64, device=DEV)
+    for host in (torch.randn(dims, dtype=torch.float64),
+                 torch.randn(dims, dtype=torch.float64).pin_memory()):
+        with pytest.raises(rt.RtrError) as e:
+            rt.rtr_sketch(h, host, K, Q=Qd, stream=s)
+        assert e.value.code == 1 and "X" in str(e.value)
+    with pytest.raises(rt.RtrError) as e:
+        rt.rtr_sketch(h, Xd, K, Q=torch.empty(rt.q_size(dims, K), dtype=torch.float64), stream=s)
+    assert e.value.code == 1 and "Q" in str(e.value)
+    P = torch.zeros((3, 3, 3), dtype=torch.float64, device=DEV)
+    Z0 = torch.zeros(3 * 3 * 2 * 2, dtype=torch.float64)
+    with pytest.raises(rt.RtrError) as e:
+        rt.rtr_decompose(h, P, [2, 2, 2], Z0, 2, Z=torch.empty(36, dtype=torch.float64, device=DEV),
+                         stream=s)
+    assert e.value.code == 1 and "Z_init" in str(e.value)
+    torch.cuda.synchronize()
+    # the handle still works after the refusals
+    Q = rt.rtr_sketch(h, Xd, K)
+    torch.cuda.synchronize()
+    Qh = [q.cpu().numpy() for q in rt.unpack(Q, rt.q_shapes(dims, K))]
+    for q in Qh:
+        assert np.max(np.abs(q.T @ q - np.eye(q.shape[1]))) < 1e-13
