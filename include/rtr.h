@@ -73,6 +73,8 @@ extern "C" {
 
 #define RTR_MAX_ORDER 8
 #define RTR_MAX_RANK 32
+/* Fixed scratch of rtr_sketch_noalloc, per GPU (32 MiB). */
+#define RTR_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
 
 typedef enum {
   RTR_OK = 0,
@@ -124,6 +126,24 @@ rtr_status rtr_sketch(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t or
                       const int64_t* dims, const int32_t* K, int32_t power_iters,
                       uint64_t seed, uint32_t tensor_id, rtr_dtype compute, double* Q,
                       void* stream);
+
+/*
+ * rtr_sketch for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments, kernels and results
+ * as rtr_sketch (bitwise identical for the same inputs); it calls no hipMalloc, hipFree or
+ * other allocating routine, and kernel timing (rtr_profile_enable) does not apply to it.
+ * Its scratch (the partial sketches and the QR work arrays) is one fixed device array of
+ * RTR_NOALLOC_SCRATCH_BYTES per GPU, set up by the first rtr_create on that device and held
+ * until the process ends.  A request that needs more scratch than that returns
+ * RTR_ERR_UNSUPPORTED before anything is enqueued; RTR_ERR_DEVICE if the array could not be
+ * located on this device.  Every call of this entry point on one GPU shares that array, and
+ * the array keeps the contents of the last call: calls that overlap in time on one GPU (other
+ * streams, handles or threads) race, so the caller serialises them.
+ */
+rtr_status rtr_sketch_noalloc(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
+                              const int64_t* dims, const int32_t* K, int32_t power_iters,
+                              uint64_t seed, uint32_t tensor_id, rtr_dtype compute, double* Q,
+                              void* stream);
 
 /*
  * Alg. 1 step 7 read cumulatively (Eq. 3): P = X x_1 Q_1^T x_2 .. x_N Q_N^T.

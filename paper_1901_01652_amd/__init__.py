@@ -68,6 +68,8 @@ def _load():
         "rtr_create": [ctypes.c_int, ctypes.POINTER(vp)],
         "rtr_destroy": [vp],
         "rtr_sketch": [vp, vp, ctypes.c_int, i32, P64, P32, i32, u64, u32, ctypes.c_int, vp, vp],
+        "rtr_sketch_noalloc": [vp, vp, ctypes.c_int, i32, P64, P32, i32, u64, u32, ctypes.c_int, vp,
+                               vp],
         "rtr_compress": [vp, vp, ctypes.c_int, i32, P64, P32, vp, ctypes.c_int, vp, vp, vp],
         "rtr_decompose": [vp, vp, i32, P32, P32, ctypes.POINTER(_Opts), vp, vp, vp, vp, vp],
         "rtr_decompose_svd": [vp, vp, i32, P32, P32, dp, vp, vp, vp, vp],
@@ -215,6 +217,18 @@ def rtr_sketch(h, X, K, power_iters=0, seed=0, tensor_id=0, compute=None, Q=None
         Q = torch.empty(q_size(dims, K), dtype=torch.float64, device=X.device)
     h.check(lib.rtr_sketch(h.ptr, _ptr(X), xd, len(dims), _i64(dims), _i32(K), int(power_iters),
                            int(seed), int(tensor_id), cd, _ptr(Q), _stream(stream, X.device)))
+    return Q
+
+
+def rtr_sketch_noalloc(h, X, K, Q, power_iters=0, seed=0, tensor_id=0, compute=None, stream=None):
+    """rtr_sketch without device allocation (fixed per-GPU scratch); ``Q`` is caller-owned."""
+    dims = list(X.shape)
+    assert X.is_contiguous()
+    xd = _xdtype(X)
+    cd = xd if compute is None else _DTYPES[compute]
+    h.check(lib.rtr_sketch_noalloc(h.ptr, _ptr(X), xd, len(dims), _i64(dims), _i32(K),
+                                   int(power_iters), int(seed), int(tensor_id), cd, _ptr(Q),
+                                   _stream(stream, X.device)))
     return Q
 
 

@@ -5,12 +5,26 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "launch.hpp"
 #include "rtr.h"
+
+// Scratch of the no-allocation sketch entry point (rtr_sketch_noalloc): one array per GPU the
+// library runs on, held until the process ends.  In host code ``scratch`` names a host-side
+// stand-in; its device address on each GPU comes from hipGetSymbolAddress (rtr_create) and is
+// the only form host code passes on.
+constexpr size_t kScratchBytes = RTR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};  // device address of ``scratch`` per device ordinal
+}  // namespace
 
 struct ProfRec {
   const char* name;
@@ -31,6 +45,7 @@ struct rtr_context {
   const char* pending = nullptr;
   hipEvent_t pending_e0 = nullptr;
   int ws_epoch = 0;  // bumped whenever the workspace moves (cached graphs point into it)
+  void* scratch = nullptr;  // device address of this device's no-allocation scratch
   // batched TR-ALS: device item array, pinned staging for its upload
   void* items_dev = nullptr;
   size_t items_cap = 0;
@@ -283,6 +298,17 @@ rtr_status rtr_create(int device, rtr_handle* out) {
     delete h;
     return RTR_ERR_DEVICE;
   }
+  if (device < kMaxDevices) {  // once per device, with that device current
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess && ptr)
+        g_scratch_dev[device] = ptr;
+      else
+        (void)hipGetLastError();  // the no-allocation entry point then reports the failure
+    }
+    h->scratch = g_scratch_dev[device];
+  }
   *out = h;
   return RTR_OK;
 }
@@ -329,13 +355,16 @@ const char* rtr_status_string(rtr_status s) {
 }
 
 // ---------------------------------------------------------------------------------------
-rtr_status rtr_sketch(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
-                      const int64_t* dims, const int32_t* K, int32_t power_iters,
-                      uint64_t seed, uint32_t tensor_id, rtr_dtype compute, double* Q,
-                      void* stream) try {
-  rtr_status st = check_handle(h);
-  if (st) return st;
-  Guard guard(h);
+namespace {
+
+// Alg. 1 steps 3-6 (+ power iterations).  With ``fixed`` the partial sketches and QR work
+// arrays live in that buffer of ``fixed_cap`` bytes and nothing is allocated (a request that
+// needs more is refused before anything is enqueued); otherwise in the handle's workspace.
+rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t order,
+                       const int64_t* dims, const int32_t* K, int32_t power_iters, uint64_t seed,
+                       uint32_t tensor_id, rtr_dtype compute, double* Q, void* stream,
+                       void* fixed, size_t fixed_cap) {
+  rtr_status st;
   if ((st = check_shape(h, order, dims, K))) return st;
   if (!K) return fail(h, RTR_ERR_INVALID_ARG, "K is NULL");
   if (power_iters < 0 || power_iters > 64)
@@ -378,8 +407,18 @@ rtr_status rtr_sketch(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t or
     plan.take<double>((size_t)dims[n] * keff(dims, K, n));
     plan.take<double>((size_t)dims[n] * keff(dims, K, n));
   }
-  if ((st = ensure_ws(h, plan.off + 256))) return st;
-  Carve cv(h->ws);
+  void* ws;
+  if (fixed) {
+    if (plan.off + 256 > fixed_cap)
+      return fail(h, RTR_ERR_UNSUPPORTED,
+                  "this sketch needs " + std::to_string(plan.off + 256) + " bytes of scratch; the " +
+                      "no-allocation entry point has " + std::to_string(fixed_cap));
+    ws = fixed;
+  } else {
+    if ((st = ensure_ws(h, plan.off + 256))) return st;
+    ws = h->ws;
+  }
+  Carve cv(ws);
   void* partial = cv.take<char>(pmax);
   double* Ycol[RTR_MAX_ORDER];
   double* Qw[RTR_MAX_ORDER];
@@ -446,6 +485,34 @@ rtr_status rtr_sketch(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t or
     HIP_TRY(rtr::launch_householder_qr(jobs, s), "householder_qr");
   }
   return RTR_OK;
+}
+
+}  // namespace
+
+rtr_status rtr_sketch(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
+                      const int64_t* dims, const int32_t* K, int32_t power_iters,
+                      uint64_t seed, uint32_t tensor_id, rtr_dtype compute, double* Q,
+                      void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  return sketch_impl(h, X, x_dtype, order, dims, K, power_iters, seed, tensor_id, compute, Q,
+                     stream, nullptr, 0);
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+rtr_status rtr_sketch_noalloc(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
+                              const int64_t* dims, const int32_t* K, int32_t power_iters,
+                              uint64_t seed, uint32_t tensor_id, rtr_dtype compute, double* Q,
+                              void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  // no Guard: the timing hooks stay off, so no event is created here
+  if (!h->scratch)
+    return fail(h, RTR_ERR_DEVICE, "the no-allocation scratch of this device is unavailable");
+  return sketch_impl(h, X, x_dtype, order, dims, K, power_iters, seed, tensor_id, compute, Q,
+                     stream, h->scratch, kScratchBytes);
 } catch (...) {
   return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
 }
