@@ -95,6 +95,9 @@ typedef enum { RTR_METHOD_ALS = 0, RTR_METHOD_SVD = 1 } rtr_method;
                                            that core update was skipped */
 #define RTR_STATUS_RANK_CAPPED 0x2u     /* TR-SVD: a rank was lowered to its cap, so the
                                            error bound eps may not hold */
+#define RTR_STATUS_SYNC_TIMEOUT 0x4u    /* a device-wide barrier of the single-launch TR-ALS
+                                           did not complete within its bound; the launch
+                                           ended early and its outputs are not valid */
 
 typedef struct rtr_context* rtr_handle;
 
@@ -188,6 +191,16 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
                          const int32_t* R, const rtr_decompose_opts* opts,
                          const double* Z_init, double* Z, double* err_trace,
                          int32_t* sweeps_run, void* stream);
+
+/*
+ * How rtr_decompose runs TR-ALS on this handle.  mode 0 (default): the whole decomposition in
+ * one cooperative launch (every work-group keeps the cores in LDS, grid barriers between the
+ * phases of a core update) when every rank is at most 6, K'_n <= 64 and the cores fit; other
+ * shapes, and devices that cannot hold the launch's work-groups at once, use mode 1.
+ * mode 1: two launches per core update (accumulation of P_<n> B over column tiles, then the
+ * solve).  Both compute the same least-squares updates; their sums run in different orders.
+ */
+rtr_status rtr_set_als_launch(rtr_handle h, int32_t mode);
 
 /*
  * Alg. 1 step 9 with TR-SVD (the rTR-SVD variant of Sec. 4): sequential truncated SVDs of

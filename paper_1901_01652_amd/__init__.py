@@ -26,6 +26,7 @@ RTR_F64, RTR_F32, RTR_BF16 = 0, 1, 2
 RTR_METHOD_ALS, RTR_METHOD_SVD = 0, 1
 RTR_STATUS_CHOLESKY_FAILED = 0x1
 RTR_STATUS_RANK_CAPPED = 0x2
+RTR_STATUS_SYNC_TIMEOUT = 0x4
 MAX_ORDER = 8
 
 _DTYPES = {"f64": RTR_F64, "f32": RTR_F32, "bf16": RTR_BF16}
@@ -90,6 +91,7 @@ def _load():
         "rtr_status_sync": [vp, vp, ctypes.POINTER(u32)],
         "rtr_profile_enable": [vp, i32],
         "rtr_read_probe": [vp, vp, i64, vp, vp],
+        "rtr_set_als_launch": [vp, i32],
         "rtr_profile_reset": [vp],
         "rtr_profile_read": [vp, ctypes.c_char_p, ctypes.POINTER(dp), P64],
     }
@@ -463,6 +465,11 @@ def rtr_status_sync(h, stream=None, device=0):
     if st not in (0, 5):
         h.check(st)
     return int(bits.value)
+
+
+def rtr_set_als_launch(h, mode):
+    """0: TR-ALS in one cooperative launch where supported (default); 1: two launches per update."""
+    h.check(lib.rtr_set_als_launch(h.ptr, int(mode)))
 
 
 def rtr_read_probe(h, x, out=None, stream=None):

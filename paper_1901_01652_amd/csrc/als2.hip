@@ -46,7 +46,7 @@ static __host__ __device__ inline int64_t zwords(int64_t z) { return (z + 1) / 2
 // ---------------------------------------------------------------------------------------
 __device__ void transfer_gram(const double* __restrict__ Z, int64_t ztotal, int N, int n,
                               const int64_t* zoff, const int* Kc, const int* Rc, int tdim, int Ra,
-                              int Rb, double* xt, double* G);
+                              int Rb, double* xt, double* G, const double* Zstaged = nullptr);
 
 template <int RM, int TJ, int kAcTiles>
 __global__ __launch_bounds__(kAcThreads) void als_accum_kernel(AlsArgs2 g) {
@@ -275,10 +275,11 @@ __device__ void gemm_f64(const double* A, int lda, int ska, const double* B, int
 
 // Gram of core n's least squares from transfer matrices (every core except n is read):
 // sum_j S_j (x) S_j = E_{n+1} .. E_{n-1}.  xt: LDS workspace of 3 tdim^2 + 64 tdim + ztotal
-// doubles; G: RR x RR output (LDS or global).  Called by a whole work-group.
+// doubles (3 tdim^2 + 64 tdim when the cores are already in LDS at ``Zstaged``); G: RR x RR
+// output (LDS or global).  Called by a whole work-group.
 __device__ void transfer_gram(const double* __restrict__ Z, int64_t ztotal, int N, int n,
                               const int64_t* zoff, const int* Kc, const int* Rc, int tdim, int Ra,
-                              int Rb, double* xt, double* G) {
+                              int Rb, double* xt, double* G, const double* Zstaged) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int RR = Ra * Rb;
   // Gram from transfer matrices: sum_j S_j (x) S_j = E_{n+1} E_{n+2} ... E_{n-1},
@@ -289,8 +290,9 @@ __device__ void transfer_gram(const double* __restrict__ Z, int64_t ztotal, int 
   double* Em = Tm + D * D;
   double* Tn = Em + D * D;
   double* Fz = Tn + D * D;   // Kp x W slice matrix, Kp <= 64
-  double* Zs = Fz + 64 * D;  // cores
-  {
+  const double* Zs = Zstaged ? Zstaged : Fz + 64 * D;  // cores
+  if (!Zstaged) {
+    double* Zw = Fz + 64 * D;
     double zt[12];
 #pragma unroll
     for (int e = 0; e < 12; ++e) {
@@ -300,7 +302,7 @@ __device__ void transfer_gram(const double* __restrict__ Z, int64_t ztotal, int 
 #pragma unroll
     for (int e = 0; e < 12; ++e) {
       const int64_t x = tid + (int64_t)e * nth;
-      if (x < ztotal) Zs[x] = zt[e];
+      if (x < ztotal) Zw[x] = zt[e];
     }
   }
   for (int x = tid; x < 3 * D * D; x += nth) Tm[x] = 0.0;
@@ -573,6 +575,396 @@ hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s) {
   prof_begin("als_solve", s);
   void* args[] = {&g};
   e = hipLaunchKernel(fn, dim3(1), dim3(kSolveThreads), args, lds, s);
+  prof_end(s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// TR-ALS in one cooperative launch: every sweep and core update of one decomposition.
+//
+// Each work-group keeps all cores in LDS.  Work-groups 0..G-1 accumulate M = P_<n> B over
+// tiles of TJ columns (tile t goes to work-group t mod G); work-group G forms the
+// transfer-matrix Gram of core n beside them.  Per core update:
+//   A  each accumulating work-group writes its partial M (and, on the first update of a
+//      sweep, the residual ||P - Psi(Z)||^2 of its columns with the cores of the sweep
+//      before) to its record in ``part``
+//   -- grid barrier --
+//   B  the records are summed in a fixed order; the elements are split over all work-groups
+//   -- grid barrier --
+//   C  every work-group reads the summed M and the Gram and solves the normal equations by
+//      Gauss-Jordan itself; the arithmetic is identical in each, so every LDS copy of core n
+//      receives the same new values and no third barrier is needed.
+// The grid barrier is an agent-scope release/acquire on a monotonic arrival counter (zero at
+// launch).  Its wait is bounded: a barrier that does not complete sets
+// RTR_STATUS_SYNC_TIMEOUT and every work-group leaves the launch.
+constexpr int kPsThreads = 512;  // 8 wavefronts
+
+__device__ __forceinline__ bool ps_grid_sync(unsigned* bar, unsigned nblk, unsigned& epoch,
+                                             unsigned limit, unsigned* status, int* s_fail) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0 && !*s_fail) {
+    ++epoch;
+    const unsigned target = epoch * nblk;
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > limit) {
+        *s_fail = 1;
+        atomicOr(status, (unsigned)RTR_STATUS_SYNC_TIMEOUT);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return *s_fail == 0;
+}
+
+template <int RM, int QMAX, int TJ>
+__global__ __launch_bounds__(kPsThreads) void als_persist_kernel(AlsPersistArgs g) {
+  extern __shared__ __align__(16) double sm[];
+  __shared__ double wred[16];
+  __shared__ int s_fail, s_gj;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int N = g.N, G = g.G;
+  const unsigned nblk = (unsigned)G + 1;
+  const bool gram_wg = (int)blockIdx.x == G;
+  double* Zs = sm;
+  double* U = sm + zwords(g.ztotal);
+  for (int64_t x = tid; x < g.ztotal; x += kPsThreads) Zs[x] = g.Z[x];
+  if (tid == 0) {
+    s_fail = 0;
+    s_gj = 0;
+  }
+  __syncthreads();
+  const double pn2 = g.pn2[0];
+  unsigned epoch = 0;
+  double eprev = 0.0;
+  bool stop = false;
+  const int S = g.max_sweeps;
+  for (int s = 0; s <= S && !stop; ++s) {
+    for (int n = 0; n < N; ++n) {
+      const bool last = s == S;  // the closing pass: the residual of the final sweep only
+      if (last && n > 0) break;
+      const bool report = n == 0 && s > 0;
+      const int Kn = g.K[n], Ra = g.R[n], Rb = g.R[(n + 1) % N], RR = Ra * Rb;
+      const int nM = Kn * RR;
+      const int J = (int)(g.total / Kn);
+      const int ntiles = (J + TJ - 1) / TJ;
+      const int nrec = ntiles < G ? ntiles : G;
+      const int64_t zoffN = g.zoff[n];
+      // ---- A: partial M (and residual) over this work-group's tiles; Gram beside --------
+      if (gram_wg) {
+        if (!last)
+          transfer_gram(nullptr, g.ztotal, N, n, g.zoff, g.K, g.R, g.tdim, Ra, Rb, U, g.gram, Zs);
+      } else if ((int)blockIdx.x < nrec) {
+        int cycK[7], chI[7], chRb[7];
+        int64_t cycStride[7], chOff[7];
+#pragma unroll
+        for (int t = 0; t < 7; ++t) {
+          const int m = (n + 1 + t) % N;
+          cycK[t] = g.K[m];
+          cycStride[t] = g.strideP[m];
+          chI[t] = g.K[m];
+          chRb[t] = g.R[(m + 1) % N];
+          chOff[t] = g.zoff[m];
+        }
+        const int strideN = (int)g.strideP[n];
+        const int NT = pad16(RR) / 16, MT = pad16(Kn) / 16, ntM = MT * NT;
+        const int ldB = pad16(RR) + 1, ldL = TJ + 1;
+        double* Bs = U;                   // [TJ][ldB]
+        double* Ls = Bs + TJ * ldB;       // [pad16(Kn)][ldL]
+        for (int x = tid; x < TJ * ldB; x += kPsThreads) Bs[x] = 0.0;
+        f64x4 acc[2] = {f64x4{0.0, 0.0, 0.0, 0.0}, f64x4{0.0, 0.0, 0.0, 0.0}};
+        double rsum = 0.0;
+        for (int t = blockIdx.x; t < ntiles; t += G) {
+          const int j0 = t * TJ;
+          const int jn = min(TJ, J - j0);
+          __syncthreads();
+          {  // P_<n>[:, tile] into Ls, rows zero-padded to a multiple of 16
+            constexpr int kPer = (64 * TJ + kPsThreads - 1) / kPsThreads;
+            double pv[kPer];
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) {
+              const int x = tid + e * kPsThreads;
+              const int i = x / TJ, jj = x % TJ;
+              pv[e] = 0.0;
+              if (i < Kn && jj < jn) {
+                int rem = j0 + jj, base = 0;
+#pragma unroll
+                for (int u = 6; u >= 0; --u) {
+                  if (u <= N - 2) {
+                    const int d = cycK[u];
+                    const int q = rem / d;
+                    base += (rem - q * d) * (int)cycStride[u];
+                    rem = q;
+                  }
+                }
+                pv[e] = g.P[base + i * strideN];
+              }
+            }
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) {
+              const int x = tid + e * kPsThreads;
+              const int i = x / TJ, jj = x % TJ;
+              if (i < MT * 16) Ls[i * ldL + jj] = pv[e];
+            }
+          }
+          // subchain rows: item (jl, b) forms row b of S_j from the LDS cores
+          for (int x = tid; x < TJ * Rb; x += kPsThreads) {
+            const int jl = x / Rb, b = x % Rb;
+            double v[RM], w[RM];
+#pragma unroll
+            for (int a = 0; a < RM; ++a) v[a] = 0.0;
+            if (jl < jn) {
+              int rem = j0 + jl;
+              int idx[7];
+#pragma unroll
+              for (int u = 6; u >= 0; --u) {
+                if (u <= N - 2) {
+                  idx[u] = rem % chI[u];
+                  rem /= chI[u];
+                }
+              }
+              {
+                const int cRb = chRb[0];
+                const double* G0 = Zs + chOff[0] + ((int64_t)b * chI[0] + idx[0]) * cRb;
+#pragma unroll
+                for (int c = 0; c < RM; ++c) v[c] = c < cRb ? G0[c] : 0.0;
+              }
+              int cur = chRb[0];
+#pragma unroll
+              for (int u = 1; u < 7; ++u) {
+                if (u < N - 1) {
+                  const int cRb = chRb[u];
+                  const double* Gm = Zs + chOff[u] + (int64_t)idx[u] * cRb;
+                  const int rs = chI[u] * cRb;
+#pragma unroll
+                  for (int c = 0; c < RM; ++c) w[c] = 0.0;
+#pragma unroll
+                  for (int a = 0; a < RM; ++a) {
+                    if (a < cur) {
+                      const double va = v[a];
+                      const double* gr = Gm + a * rs;
+#pragma unroll
+                      for (int c = 0; c < RM; ++c)
+                        if (c < cRb) w[c] += va * gr[c];
+                    }
+                  }
+#pragma unroll
+                  for (int c = 0; c < RM; ++c) v[c] = w[c];
+                  cur = cRb;
+                }
+              }
+            }
+#pragma unroll
+            for (int a = 0; a < RM; ++a)
+              if (a < Ra) Bs[jl * ldB + a * Rb + b] = v[a];
+          }
+          __syncthreads();
+          if (!last) {  // M += P tile * B tile on the FP64 matrix cores
+            const int r16 = lane & 15, g4 = lane >> 4;
+#pragma unroll
+            for (int q2 = 0; q2 < 2; ++q2) {
+              const int q = wid + 8 * q2;
+              if (q < ntM) {
+                const int mt = q / NT, nt = q % NT;
+                const double* ap = Ls + (mt * 16 + r16) * ldL + g4;
+                const double* bp = Bs + g4 * ldB + nt * 16 + r16;
+                f64x4 c = acc[q2];
+#pragma unroll 8
+                for (int k0 = 0; k0 < TJ; k0 += 4) c = mma_f64(ap[k0], bp[k0 * ldB], c);
+                acc[q2] = c;
+              }
+            }
+          }
+          if (report) {  // residual of these columns with the current core n
+            const double* Zn = Zs + zoffN;
+            for (int x = tid; x < Kn * TJ; x += kPsThreads) {
+              const int i = x / TJ, jj = x % TJ;
+              if (jj < jn) {
+                double psi = 0.0;
+                for (int a = 0; a < Ra; ++a) {
+                  const double* zr = Zn + ((int64_t)a * Kn + i) * Rb;
+                  const double* br = Bs + jj * ldB + a * Rb;
+                  for (int b = 0; b < Rb; ++b) psi += zr[b] * br[b];
+                }
+                const double d = Ls[i * ldL + jj] - psi;
+                rsum += d * d;
+              }
+            }
+          }
+        }
+        double* out = g.part + (int64_t)blockIdx.x * g.rec;
+        {
+          const int r16 = lane & 15, g4 = lane >> 4;
+#pragma unroll
+          for (int q2 = 0; q2 < 2; ++q2) {
+            const int q = wid + 8 * q2;
+            if (q < ntM) {
+              const int mt = q / NT, nt = q % NT;
+              const int col = nt * 16 + r16;
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int row = mt * 16 + 4 * r + g4;
+                if (row < Kn && col < RR) out[row * RR + col] = last ? 0.0 : acc[q2][r];
+              }
+            }
+          }
+        }
+        rsum = block_sum(rsum, wred);
+        if (tid == 0) out[nM] = rsum;
+      }
+      if (!ps_grid_sync(g.bar, nblk, epoch, g.spin_limit, g.status, &s_fail)) return;
+      // ---- B: fixed-order sum of the records, element slices over all work-groups ------
+      {
+        const int nv = nM + 1;
+        const int per = (nv + (int)nblk - 1) / (int)nblk;
+        const int e0 = (int)blockIdx.x * per;
+        const int e1 = min(nv, e0 + per);
+        double* cb = U;  // kPsThreads doubles
+        for (int base = e0; base < e1; base += kPsThreads) {
+          const int cnt = min(e1 - base, kPsThreads);
+          const int ngrp = kPsThreads / cnt;
+          const int le = tid % cnt, grp = tid / cnt;
+          double acc = 0.0;
+          if (grp < ngrp)
+            for (int r = grp; r < nrec; r += ngrp) acc += g.part[(int64_t)r * g.rec + base + le];
+          cb[tid] = acc;
+          __syncthreads();
+          if (tid < cnt) {
+            double t = 0.0;
+            for (int q = 0; q < ngrp; ++q) t += cb[q * cnt + tid];
+            g.red[base + tid] = t;
+          }
+          __syncthreads();
+        }
+      }
+      if (!ps_grid_sync(g.bar, nblk, epoch, g.spin_limit, g.status, &s_fail)) return;
+      // ---- C: the error of the sweep before, the stopping test, the solve ---------------
+      if (report) {
+        const double e = sqrt(g.red[nM] / pn2);
+        if (blockIdx.x == 0 && tid == 0) {
+          g.trace[s - 1] = e;
+          *g.sweeps_run = s;
+        }
+        if (g.tol > 0.0 && s >= 2 && fabs(e - eprev) < g.tol) stop = true;
+        eprev = e;
+        if (stop || last) break;
+      }
+      {
+        double* Mt = U;
+        double* Gm = Mt + nM;
+        double* X = Gm + RR * RR;
+        double* rowbuf = X + RR * Kn;
+        double* colbuf = rowbuf + 512;
+        for (int x = tid; x < nM; x += kPsThreads) Mt[x] = g.red[x];
+        for (int x = tid; x < RR * RR; x += kPsThreads) Gm[x] = g.gram[x];
+        __syncthreads();
+        if (gauss_jordan<QMAX>(Gm, Mt, X, rowbuf, colbuf, RR, Kn, &s_gj)) {
+          __syncthreads();
+          for (int x = tid; x < nM; x += kPsThreads) {
+            const int i = x / RR, r = x % RR;
+            const int a = r / Rb, b = r % Rb;
+            Zs[zoffN + ((int64_t)a * Kn + i) * Rb + b] = X[r * Kn + i];
+          }
+        } else if (blockIdx.x == 0 && tid == 0) {
+          atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
+        }
+        __syncthreads();
+      }
+    }
+  }
+  if (blockIdx.x == 0)
+    for (int64_t x = tid; x < g.ztotal; x += kPsThreads) g.Z[x] = Zs[x];
+}
+
+__global__ void als_persist_begin_kernel(unsigned* bar, int* sweeps_run) {
+  *bar = 0u;
+  *sweeps_run = 0;
+}
+
+namespace {
+int ps_tj(const AlsPersistArgs& g) { return g.TJ; }
+
+int64_t ps_words(int TJ, int maxK, int maxRR, int tdim, int64_t ztotal) {
+  const int64_t a = (int64_t)TJ * (pad16(maxRR) + 1) + (int64_t)pad16(maxK) * (TJ + 1);
+  const int64_t gram = 3 * (int64_t)tdim * tdim + 64 * (int64_t)tdim;
+  const int64_t c = (int64_t)maxK * maxRR * 2 + (int64_t)maxRR * maxRR + 1024;
+  const int64_t b = kPsThreads;
+  return zwords(ztotal) + std::max(std::max(a, gram), std::max(c, b));
+}
+
+template <int RM, int QMAX>
+const void* ps_fn(int TJ) {
+  return TJ == 128 ? (const void*)als_persist_kernel<RM, QMAX, 128>
+                   : (const void*)als_persist_kernel<RM, QMAX, 64>;
+}
+}  // namespace
+
+// Plans the persistent launch; false if the shape is outside what it takes (the caller then
+// runs the two-kernel updates).  Fills TJ, G, rec, tdim, lds (bytes).
+bool als_persist_plan(AlsPersistArgs* g, size_t* lds) {
+  int maxK = 0, rmax = 0, maxRR = 0, maxNe = 0;
+  for (int n = 0; n < g->N; ++n) {
+    const int Kn = g->K[n], RR = g->R[n] * g->R[(n + 1) % g->N];
+    maxK = std::max(maxK, Kn);
+    rmax = std::max(rmax, g->R[n]);
+    maxRR = std::max(maxRR, RR);
+    if (RR + Kn > 256) return false;
+    maxNe = std::max(maxNe, RR * (RR + Kn));
+  }
+  if (rmax > 6 || maxK > 64 || g->ztotal > kZldsMax || g->total >= (1LL << 31)) return false;
+  if (maxNe > kPsThreads * 8) return false;
+  g->tdim = als2_tdim(rmax);
+  int tj = 0;
+  for (int t = 128; t >= 64; t /= 2)
+    if (ps_words(t, maxK, maxRR, g->tdim, g->ztotal) * 8 <= 150 * 1024) {
+      tj = t;
+      break;
+    }
+  if (!tj) return false;
+  g->TJ = tj;
+  int64_t maxTiles = 1;
+  for (int n = 0; n < g->N; ++n) {
+    const int64_t J = g->total / g->K[n];
+    maxTiles = std::max(maxTiles, (J + tj - 1) / tj);
+  }
+  g->G = (int)std::min<int64_t>(maxTiles, 128);
+  g->rec = (int64_t)64 * 36 + 1;
+  {
+    int64_t r = 1;
+    for (int n = 0; n < g->N; ++n)
+      r = std::max(r, (int64_t)g->K[n] * g->R[n] * g->R[(n + 1) % g->N] + 1);
+    g->rec = r;
+  }
+  *lds = (size_t)ps_words(tj, maxK, maxRR, g->tdim, g->ztotal) * 8;
+  g->maxNe = maxNe;
+  return true;
+}
+
+hipError_t launch_als_persist(const AlsPersistArgs& ga, size_t lds, hipStream_t s) {
+  AlsPersistArgs g = ga;
+  const bool q4 = g.maxNe <= kPsThreads * 4;
+  const void* fn = q4 ? ps_fn<8, 4>(g.TJ) : ps_fn<8, 8>(g.TJ);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0, per_cu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPsThreads, lds)) != hipSuccess)
+    return e;
+  if ((int64_t)per_cu * cus < g.G + 1) return hipErrorCooperativeLaunchTooLarge;
+  hipLaunchKernelGGL(als_persist_begin_kernel, dim3(1), dim3(1), 0, s, g.bar, g.sweeps_run);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  prof_begin("als_persist", s);
+  void* args[] = {&g};
+  e = hipLaunchCooperativeKernel(fn, dim3((unsigned)(g.G + 1)), dim3(kPsThreads), args,
+                                 (unsigned)lds, s);
   prof_end(s);
   if (e != hipSuccess) return e;
   return hipGetLastError();

@@ -170,6 +170,34 @@ int64_t als2_parts(int Kn, int RR, int64_t J, int64_t ztotal);
 hipError_t launch_als_accum(AlsArgs2 g, int rmax, hipStream_t s);
 hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s);
 
+// One cooperative launch for a whole TR-ALS decomposition (als2.hip, als_persist_kernel).
+struct AlsPersistArgs {
+  const double* P;        // K_1 x .. x K_N row-major
+  double* Z;              // packed cores: the initial cores in, the result out
+  const double* pn2;      // ||P||_F^2
+  double* part;           // [G][rec] partial records
+  double* red;            // [rec] summed record
+  double* gram;           // RR x RR Gram of the current update
+  unsigned* bar;          // grid-barrier arrival counter (zeroed before the launch)
+  unsigned* status;
+  double* trace;
+  int* sweeps_run;
+  double tol;
+  int max_sweeps;
+  int N;
+  int K[8], R[8];
+  int64_t zoff[8];
+  int64_t strideP[8];
+  int64_t total;
+  int64_t ztotal;
+  unsigned spin_limit;    // bound of a barrier wait (in sleeps of ~128 cycles)
+  // filled by als_persist_plan
+  int TJ, G, tdim, maxNe;
+  int64_t rec;
+};
+bool als_persist_plan(AlsPersistArgs* g, size_t* lds);
+hipError_t launch_als_persist(const AlsPersistArgs& g, size_t lds, hipStream_t s);
+
 __device__ __forceinline__ int64_t cyc_base_of(int N, const int* cycK, const int64_t* cycStride,
                                                int64_t j) {
   int64_t base = 0;

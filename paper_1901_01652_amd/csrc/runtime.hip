@@ -46,6 +46,7 @@ struct rtr_context {
   hipEvent_t pending_e0 = nullptr;
   int ws_epoch = 0;  // bumped whenever the workspace moves (cached graphs point into it)
   void* scratch = nullptr;  // device address of this device's no-allocation scratch
+  int als_launch = 0;       // 0: single cooperative launch where supported, 1: per-update launches
   // batched TR-ALS: device item array, pinned staging for its upload
   void* items_dev = nullptr;
   size_t items_cap = 0;
@@ -254,7 +255,7 @@ namespace rtr {
 static bool streams_x(const char* name) {
   static const char* const kNames[] = {"sketch_partial", "power_partial", "ttm_first",
                                        "residual", "sketch_fused", "power_fused",
-                                       "compress_fused", "read_probe"};
+                                       "compress_fused", "read_probe", "als_persist"};
   for (const char* k : kNames)
     if (std::strcmp(k, name) == 0) return true;
   return false;
@@ -688,6 +689,55 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
   CHECK_DEV(Z, zoff[order] * sizeof(double), "Z");
   CHECK_DEV(err_trace, (size_t)opts->max_sweeps * sizeof(double), "err_trace");
   CHECK_DEV(sweeps_run, sizeof(int32_t), "sweeps_run");
+  if (h->als_launch == 0) {  // the whole decomposition in one cooperative launch
+    rtr::AlsPersistArgs pa{};
+    pa.N = order;
+    for (int n = 0; n < order; ++n) {
+      pa.K[n] = Kp[n];
+      pa.R[n] = R[n];
+      pa.zoff[n] = (int64_t)zoff[n];
+      pa.strideP[n] = strideP[n];
+    }
+    pa.total = total;
+    pa.ztotal = (int64_t)zoff[order];
+    size_t plds = 0;
+    if (rtr::als_persist_plan(&pa, &plds)) {
+      int maxRR = 1;
+      for (int n = 0; n < order; ++n) maxRR = std::max(maxRR, (int)(R[n] * R[(n + 1) % order]));
+      Carve plan(nullptr);
+      plan.take<double>((size_t)pa.G * pa.rec);
+      plan.take<double>((size_t)pa.rec);
+      plan.take<double>((size_t)maxRR * maxRR);
+      plan.take<double>(1024);
+      plan.take<double>(1);
+      plan.take<unsigned>(1);
+      if ((st = ensure_ws(h, plan.off + 256))) return st;
+      Carve cv(h->ws);
+      pa.part = cv.take<double>((size_t)pa.G * pa.rec);
+      pa.red = cv.take<double>((size_t)pa.rec);
+      pa.gram = cv.take<double>((size_t)maxRR * maxRR);
+      double* red = cv.take<double>(1024);
+      double* pn2 = cv.take<double>(1);
+      pa.bar = cv.take<unsigned>(1);
+      if (Z != Z_init)
+        HIP_TRY(hipMemcpyAsync(Z, Z_init, zoff[order] * sizeof(double), hipMemcpyDeviceToDevice, s),
+                "hipMemcpyAsync");
+      HIP_TRY(rtr::launch_sumsq(false, P, total, red, pn2, s), "sumsq");
+      pa.P = P;
+      pa.Z = Z;
+      pa.pn2 = pn2;
+      pa.status = h->status;
+      pa.trace = err_trace;
+      pa.sweeps_run = sweeps_run;
+      pa.tol = opts->tol;
+      pa.max_sweeps = opts->max_sweeps;
+      pa.spin_limit = 1u << 24;
+      const hipError_t e = rtr::launch_als_persist(pa, plds, s);
+      if (e == hipSuccess) return RTR_OK;
+      if (e != hipErrorCooperativeLaunchTooLarge) return hip_fail(h, e, "single-launch TR-ALS");
+      (void)hipGetLastError();  // not enough co-resident work-groups: per-update launches
+    }
+  }
   int rmax = 0;
   for (int n = 0; n < order; ++n) rmax = std::max(rmax, (int)R[n]);
   // Gram from transfer matrices when every rank is at most 7 and the cores fit the solve's
@@ -1632,6 +1682,12 @@ rtr_status rtr_status_sync(rtr_handle h, void* stream, uint32_t* bits) try {
   return v ? fail(h, RTR_ERR_NUMERICAL, "device status bits set") : RTR_OK;
 } catch (...) {
   return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+rtr_status rtr_set_als_launch(rtr_handle h, int32_t mode) {
+  if (!h || mode < 0 || mode > 1) return RTR_ERR_INVALID_ARG;
+  h->als_launch = mode;
+  return RTR_OK;
 }
 
 rtr_status rtr_profile_enable(rtr_handle h, int32_t on) {

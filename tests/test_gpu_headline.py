@@ -88,12 +88,18 @@ def als_case(dims, R, seed, noise=0.05):
     ((64, 10, 10, 10), (7, 7, 7, 7), 6),      # mode 1: ne = 49 * 113 -> <8>; others <4>
     ((250, 6, 6), (4, 4, 4), 6),              # mode 1: 16 + 250 > 256 -> Cholesky fallback
 ])
-def test_als_solve_tiers(h, dims, R, sweeps):
-    say("als tiers", dims, R)
+@pytest.mark.parametrize("launch", [0, 1])
+def test_als_solve_tiers(h, dims, R, sweeps, launch):
+    """launch 0 takes the single cooperative launch where the ranks allow (R <= 6), launch 1
+    the two-kernel updates whose solve tiers are listed above."""
+    say("als tiers", dims, R, "launch", launch)
+    rt.rtr_set_als_launch(h, launch)
     P, Z0 = als_case(dims, R, 21)
     Zo, tro = orc.tr_als(P, Z0, sweeps)
     Z, tr, ns = rt.rtr_decompose(h, torch.as_tensor(P).to(DEV), R, rt.pack(Z0, DEV), sweeps)
-    assert rt.rtr_status_sync(h) == 0
+    bits = rt.rtr_status_sync(h)
+    rt.rtr_set_als_launch(h, 0)
+    assert bits == 0
     assert int(ns.item()) == sweeps
     Zg = [z.cpu().numpy() for z in rt.unpack(Z, rt.core_shapes(dims, R))]
     e_tr = C.rel(tr.cpu().numpy(), tro)

@@ -143,27 +143,37 @@ def als_case(dims, R, seed, noise=0.05):
                                            ((12, 10, 11), (1, 1, 1), 5),
                                            ((60, 16, 12), (10, 10, 10), 4),
                                            ((70, 9, 8), (3, 4, 3), 4)])
-def test_als_fp64(h, dims, R, sweeps):
-    say("als f64", dims, R)
+@pytest.mark.parametrize("launch", [0, 1])
+def test_als_fp64(h, dims, R, sweeps, launch):
+    """launch 0: one cooperative launch for the whole decomposition (ranks <= 6), 1: two
+    launches per core update."""
+    say("als f64", dims, R, "launch", launch)
+    rt.rtr_set_als_launch(h, launch)
     P, Z0 = als_case(dims, R, 11)
     Zo, tro = orc.tr_als(P, Z0, sweeps)
     Z, tr, ns = rt.rtr_decompose(h, torch.as_tensor(P).to(DEV), R, rt.pack(Z0, DEV), sweeps)
     assert rt.rtr_status_sync(h) == 0
     assert int(ns.item()) == sweeps
     Zg = [z.cpu().numpy() for z in rt.unpack(Z, rt.core_shapes(dims, R))]
+    rt.rtr_set_als_launch(h, 0)
     assert rel(tr.cpu().numpy(), tro) < 1e-10
     assert rel(ot.tr_full(Zg), ot.tr_full(Zo)) < 1e-10
 
 
-def test_als_tolerance_stop(h):
+@pytest.mark.parametrize("launch", [0, 1])
+def test_als_tolerance_stop(h, launch):
     dims, R = (7, 6, 8), (2, 2, 2)
-    say("als tol", dims, R)
+    say("als tol", dims, R, "launch", launch)
+    rt.rtr_set_als_launch(h, launch)
     P, Z0 = als_case(dims, R, 13, noise=0.3)
     Zo, tro = orc.tr_als(P, Z0, 60, tol=1e-4)
     Z, tr, ns = rt.rtr_decompose(h, torch.as_tensor(P).to(DEV), R, rt.pack(Z0, DEV), 60, tol=1e-4)
     n = int(ns.item())
+    rt.rtr_set_als_launch(h, 0)
     assert n == len(tro) and n < 60
     assert rel(tr.cpu().numpy()[:n], tro) < 1e-10
+    Zg = [z.cpu().numpy() for z in rt.unpack(Z, rt.core_shapes(dims, R))]
+    assert rel(ot.tr_full(Zg), ot.tr_full(Zo)) < 1e-10
 
 
 @pytest.mark.parametrize("dims,K,R", [((13, 11, 9, 10), (5, 4, 3, 6), (2, 3, 2, 3)),
@@ -271,13 +281,18 @@ def test_invalid_arguments(h):
     assert e.value.code == 1
 
 
-def test_cholesky_failure_flag(h):
+@pytest.mark.parametrize("launch", [0, 1])
+def test_cholesky_failure_flag(h, launch):
     """A zero core makes the subchain of the first update vanish, so its Gram matrix is
     exactly zero: the status bit is set, the update skipped, and no kernel faults."""
     dims, R = (5, 6, 7), (2, 2, 2)
-    say("cholesky flag")
+    say("cholesky flag", "launch", launch)
+    rt.rtr_set_als_launch(h, launch)
     P = torch.as_tensor(rand_tensor(dims, 8)).to(DEV)
     Z0 = [np.ones((2, 5, 2)), np.zeros((2, 6, 2)), np.ones((2, 7, 2))]
     rt.rtr_decompose(h, P, R, rt.pack(Z0, DEV), 1)
-    assert rt.rtr_status_sync(h) & rt.RTR_STATUS_CHOLESKY_FAILED
+    bits = rt.rtr_status_sync(h)
+    rt.rtr_set_als_launch(h, 0)
+    assert bits & rt.RTR_STATUS_CHOLESKY_FAILED
+    assert not bits & rt.RTR_STATUS_SYNC_TIMEOUT
     assert rt.rtr_status_sync(h) == 0
