@@ -583,249 +583,421 @@ hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s) {
 // ---------------------------------------------------------------------------------------
 // TR-ALS in one cooperative launch: every sweep and core update of one decomposition.
 //
-// Each work-group keeps all cores in LDS.  Work-groups 0..G-1 accumulate M = P_<n> B over
-// tiles of TJ columns (tile t goes to work-group t mod G); work-group G forms the
-// transfer-matrix Gram of core n beside them.  Per core update:
-//   A  each accumulating work-group writes its partial M (and, on the first update of a
-//      sweep, the residual ||P - Psi(Z)||^2 of its columns with the cores of the sweep
-//      before) to its record in ``part``
+// Each work-group keeps all cores in LDS.  Per core update n, with the columns j of P_<n>
+// cut into tiles of TJ (tile t on work-group t mod G):
+//   A  each work-group forms the subchain rows B of its tiles from the LDS cores and
+//      accumulates M = P_<n> B and the Gram B^T B on the FP64 matrix cores into its record
+//      in ``part``; on the first update of a sweep it also accumulates the residual
+//      ||P - Psi(Z)||^2 of its columns with the cores of the sweep before (Psi tile = Z_n B^T,
+//      also on the matrix cores)
 //   -- grid barrier --
-//   B  the records are summed in a fixed order; the elements are split over all work-groups
+//   B  the records are summed in a fixed order, the elements split over the work-groups
 //   -- grid barrier --
-//   C  every work-group reads the summed M and the Gram and solves the normal equations by
-//      Gauss-Jordan itself; the arithmetic is identical in each, so every LDS copy of core n
-//      receives the same new values and no third barrier is needed.
-// The grid barrier is an agent-scope release/acquire on a monotonic arrival counter (zero at
-// launch).  Its wait is bounded: a barrier that does not complete sets
-// RTR_STATUS_SYNC_TIMEOUT and every work-group leaves the launch.
+//   C  every work-group reads the summed M and Gram and solves the normal equations by
+//      Gauss-Jordan itself; the arithmetic is identical in each, so all LDS copies of core n
+//      receive the same values and no third barrier is needed.
+// The P tile of the next update is loaded into registers before the solve, so its latency
+// overlaps the solve.  A grid barrier is an agent-scope release/acquire on a monotonic
+// arrival counter (zero at launch); its wait is bounded: a barrier that does not complete
+// sets RTR_STATUS_SYNC_TIMEOUT and every work-group leaves the launch.
 constexpr int kPsThreads = 512;  // 8 wavefronts
+constexpr int kPsTiles = 4;      // 16x16 FP64 output tiles per wavefront (M and Gram)
+constexpr int kPsRowBuf = 256;   // pivot-row buffer of the solve (W + CW <= 256)
 
 __device__ __forceinline__ bool ps_grid_sync(unsigned* bar, unsigned nblk, unsigned& epoch,
                                              unsigned limit, unsigned* status, int* s_fail) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have reached the L2
   __syncthreads();
   if (threadIdx.x == 0 && !*s_fail) {
+    // release: the XCD's L2 written back, then the arrival; the wait polls with relaxed
+    // loads (no cache maintenance per poll) and acquires once, invalidating stale lines
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     ++epoch;
     const unsigned target = epoch * nblk;
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
       if (++spins > limit) {
         *s_fail = 1;
         atomicOr(status, (unsigned)RTR_STATUS_SYNC_TIMEOUT);
         break;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return *s_fail == 0;
 }
 
-template <int RM, int QMAX, int TJ>
+// Output tile qq of the accumulation: M tiles (mt, nt) first, then the Gram's upper
+// block-triangle (nt >= mt) row by row.
+__device__ __forceinline__ void ps_tile(int qq, int ntM, int NT, int& mt, int& nt) {
+  if (qq < ntM) {
+    mt = qq / NT;
+    nt = qq % NT;
+    return;
+  }
+  int q2 = qq - ntM, row = 0;
+  while (q2 >= NT - row) {
+    q2 -= NT - row;
+    ++row;
+  }
+  mt = row;
+  nt = row + q2;
+}
+
+// Geometry of core update n (the cyclic order after n, and the subchain's cores).
+struct PsGeom {
+  int Kn, Ra, Rb, RR, nM, J, ntiles, strideN;
+  int cycK[7], chI[7], chRb[7];
+  int cycStride[7], chOff[7];
+  int zoffN;
+};
+
+__device__ __forceinline__ PsGeom ps_geom(const AlsPersistArgs& g, int n, int TJ) {
+  PsGeom q;
+  const int N = g.N;
+  q.Kn = g.K[n];
+  q.Ra = g.R[n];
+  q.Rb = g.R[(n + 1) % N];
+  q.RR = q.Ra * q.Rb;
+  q.nM = q.Kn * q.RR;
+  q.J = (int)(g.total / q.Kn);
+  q.ntiles = (q.J + TJ - 1) / TJ;
+  q.strideN = (int)g.strideP[n];
+  q.zoffN = (int)g.zoff[n];
+#pragma unroll
+  for (int t = 0; t < 7; ++t) {
+    const int m = (n + 1 + t) % N;
+    q.cycK[t] = g.K[m];
+    q.cycStride[t] = (int)g.strideP[m];
+    q.chI[t] = g.K[m];
+    q.chRb[t] = g.R[(m + 1) % N];
+    q.chOff[t] = (int)g.zoff[m];
+  }
+  return q;
+}
+
+// P_<n>[:, tile t] into registers: element x = tid + e * kPsThreads is (i, jj) = (x / TJ, x % TJ),
+// KPER * kPsThreads >= K'_n TJ.
+template <int TJ, int KPER>
+__device__ __forceinline__ void ps_load_p(const AlsPersistArgs& g, const PsGeom& q, int t,
+                                          double (&pv)[KPER]) {
+  static_assert(kPsThreads % TJ == 0, "a thread's elements share one column of the tile");
+  const int tid = threadIdx.x, N = g.N;
+  const int j0 = t * TJ, jn = min(TJ, q.J - j0);
+  const int jj = tid % TJ, i0 = tid / TJ;
+  constexpr int kRows = kPsThreads / TJ;  // rows between a thread's elements
+  const bool col_ok = t < q.ntiles && jj < jn;
+  int base = 0;
+  if (col_ok) {
+    int rem = j0 + jj;
+#pragma unroll
+    for (int u = 6; u >= 0; --u) {
+      if (u <= N - 2) {
+        const int d = q.cycK[u];
+        const int qq = rem / d;
+        base += (rem - qq * d) * q.cycStride[u];
+        rem = qq;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < KPER; ++e) {
+    const int i = i0 + kRows * e;
+    pv[e] = (col_ok && i < q.Kn) ? g.P[base + i * q.strideN] : 0.0;
+  }
+}
+
+// Gauss-Jordan elimination on [Gram | M^T] (RR x W, W = RR + K'_n) without pivoting (the Gram
+// is symmetric positive definite: every pivot block is a Schur complement of it, itself
+// positive definite), two pivots per step, by the whole work-group.  Thread (r, cb) owns row
+// r, columns cb*CW .. cb*CW+CW-1 in registers, loaded straight from the summed record ``red``
+// (M at 0, K'_n x RR; Gram at gofs, RR x RR).  Step k (pivot rows and columns k, k+1, or k
+// alone for the last of an odd count): the owners of those rows and columns publish them
+// (double-buffered LDS), one barrier, then each thread forms the 2x2 pivot block's inverse, the
+// scaled pivot rows over its columns, and updates its entries.  The solution columns are
+// written into core n (Zn, LDS).  Returns false, leaving the core unchanged, if a pivot block
+// is not positive definite.
+template <int CW>
+__device__ bool ps_solve(const double* red, int gofs, int RR, int Kn, int Rb, double* Zn,
+                         double* rowbuf, double* colbuf) {
+  const int W = RR + Kn;
+  const int nb = (W + CW - 1) / CW;
+  const int t = threadIdx.x;
+  const int r = t / nb, c0 = (t % nb) * CW;
+  const bool own = r < RR;
+  double a[CW];
+#pragma unroll
+  for (int u = 0; u < CW; ++u) {
+    const int c = c0 + u;
+    a[u] = 0.0;
+    if (own && c < W) a[u] = c < RR ? red[gofs + r * RR + c] : red[(c - RR) * RR + r];
+  }
+  int par = 0;
+  for (int k = 0; k < RR; k += 2, par ^= 1) {
+    const bool two = k + 1 < RR;
+    double* rb0 = rowbuf + par * 2 * kPsRowBuf;
+    double* rb1 = rb0 + kPsRowBuf;
+    double* cb0 = colbuf + par * 2 * 64;
+    double* cb1 = cb0 + 64;
+    if (own && (r == k || r == k + 1)) {
+      double* dst = r == k ? rb0 : rb1;
+#pragma unroll
+      for (int u = 0; u < CW; ++u) dst[c0 + u] = a[u];
+    }
+#pragma unroll
+    for (int u = 0; u < CW; ++u) {
+      if (own && c0 + u == k) cb0[r] = a[u];
+      if (own && c0 + u == k + 1) cb1[r] = a[u];
+    }
+    __syncthreads();
+    const int rs = own ? r : 0;
+    const double p00 = rb0[k], p01 = rb0[k + 1], p10 = rb1[k], p11 = rb1[k + 1];
+    const double x0 = cb0[rs], x1 = cb1[rs];
+    double r0[CW], r1[CW];
+#pragma unroll
+    for (int u = 0; u < CW; ++u) {
+      r0[u] = rb0[c0 + u];
+      r1[u] = rb1[c0 + u];
+    }
+    if (two) {
+      const double det = p00 * p11 - p01 * p10;
+      if (!(p00 > 0.0) || !(det > 0.0)) return false;
+      const double id = 1.0 / det;
+      const double i00 = p11 * id, i01 = -p01 * id, i10 = -p10 * id, i11 = p00 * id;
+      const bool pk = r == k, pk1 = r == k + 1, piv = pk || pk1;
+      // a <- (pivot rows) scaled, or a - [x0 x1] (scaled pivot rows)
+      const double g0 = piv ? 0.0 : x0, g1 = piv ? 0.0 : x1;
+      const double s = piv ? 0.0 : 1.0;
+      const double h0 = pk ? 1.0 : 0.0, h1 = pk1 ? 1.0 : 0.0;
+#pragma unroll
+      for (int u = 0; u < CW; ++u) {
+        const double q0 = fma(i00, r0[u], i01 * r1[u]);
+        const double q1 = fma(i10, r0[u], i11 * r1[u]);
+        const double rest = fma(-g1, q1, fma(-g0, q0, a[u] * s));
+        a[u] = fma(h0, q0, fma(h1, q1, rest));
+      }
+    } else {
+      if (!(p00 > 0.0)) return false;
+      const double inv = 1.0 / p00;
+      const bool pk = r == k;
+      const double gm = pk ? 0.0 : x0 * inv;
+      const double sm = pk ? inv : 1.0;
+#pragma unroll
+      for (int u = 0; u < CW; ++u) a[u] = fma(-gm, r0[u], a[u] * sm);
+    }
+  }
+  __syncthreads();  // every read of the last step is done before the core changes
+  if (own) {
+    const int ai = r / Rb, b = r % Rb;
+#pragma unroll
+    for (int u = 0; u < CW; ++u) {
+      const int c = c0 + u;
+      if (c >= RR && c < W) Zn[(ai * Kn + (c - RR)) * Rb + b] = a[u];
+    }
+  }
+  return true;
+}
+
+// Columns per thread of ps_solve: the smallest CW with RR * ceil(W / CW) <= kPsThreads.
+static __host__ __device__ inline int ps_cw(int RR, int W) {
+  for (int cw = 4; cw <= 16; cw *= 2)
+    if (RR * ((W + cw - 1) / cw) <= kPsThreads) return cw;
+  return 0;
+}
+
+// RM: rank bound of the subchain registers; CW: columns per thread of the solve; TJ: tile
+// width; KT: bound of K'_n (sizes the register tile of P).
+template <int RM, int CW, int TJ, int KT>
 __global__ __launch_bounds__(kPsThreads) void als_persist_kernel(AlsPersistArgs g) {
   extern __shared__ __align__(16) double sm[];
   __shared__ double wred[16];
-  __shared__ int s_fail, s_gj;
+  __shared__ int s_fail;
+  constexpr int KPER = (KT * TJ + kPsThreads - 1) / kPsThreads;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int r16 = lane & 15, g4 = lane >> 4;
   const int N = g.N, G = g.G;
-  const unsigned nblk = (unsigned)G + 1;
-  const bool gram_wg = (int)blockIdx.x == G;
+  const unsigned nblk = (unsigned)G;
   double* Zs = sm;
   double* U = sm + zwords(g.ztotal);
-  for (int64_t x = tid; x < g.ztotal; x += kPsThreads) Zs[x] = g.Z[x];
-  if (tid == 0) {
-    s_fail = 0;
-    s_gj = 0;
-  }
-  __syncthreads();
+  for (int x = tid; x < (int)g.ztotal; x += kPsThreads) Zs[x] = g.Z[x];
+  // the tile buffers start at zero: rows of B beyond a partial tile are rewritten as zeros by
+  // every build, and padding rows and columns only feed outputs that are discarded
+  for (int x = tid; x < (int)g.ubuf; x += kPsThreads) U[x] = 0.0;
+  if (tid == 0) s_fail = 0;
   const double pn2 = g.pn2[0];
   unsigned epoch = 0;
   double eprev = 0.0;
   bool stop = false;
   const int S = g.max_sweeps;
+  double pv[KPER];
+  {
+    const PsGeom q0 = ps_geom(g, 0, TJ);
+    ps_load_p<TJ, KPER>(g, q0, blockIdx.x, pv);
+  }
+  __syncthreads();
   for (int s = 0; s <= S && !stop; ++s) {
     for (int n = 0; n < N; ++n) {
       const bool last = s == S;  // the closing pass: the residual of the final sweep only
       if (last && n > 0) break;
       const bool report = n == 0 && s > 0;
-      const int Kn = g.K[n], Ra = g.R[n], Rb = g.R[(n + 1) % N], RR = Ra * Rb;
-      const int nM = Kn * RR;
-      const int J = (int)(g.total / Kn);
-      const int ntiles = (J + TJ - 1) / TJ;
-      const int nrec = ntiles < G ? ntiles : G;
-      const int64_t zoffN = g.zoff[n];
-      // ---- A: partial M (and residual) over this work-group's tiles; Gram beside --------
-      if (gram_wg) {
-        if (!last)
-          transfer_gram(nullptr, g.ztotal, N, n, g.zoff, g.K, g.R, g.tdim, Ra, Rb, U, g.gram, Zs);
-      } else if ((int)blockIdx.x < nrec) {
-        int cycK[7], chI[7], chRb[7];
-        int64_t cycStride[7], chOff[7];
-#pragma unroll
-        for (int t = 0; t < 7; ++t) {
-          const int m = (n + 1 + t) % N;
-          cycK[t] = g.K[m];
-          cycStride[t] = g.strideP[m];
-          chI[t] = g.K[m];
-          chRb[t] = g.R[(m + 1) % N];
-          chOff[t] = g.zoff[m];
-        }
-        const int strideN = (int)g.strideP[n];
-        const int NT = pad16(RR) / 16, MT = pad16(Kn) / 16, ntM = MT * NT;
-        const int ldB = pad16(RR) + 1, ldL = TJ + 1;
-        double* Bs = U;                   // [TJ][ldB]
-        double* Ls = Bs + TJ * ldB;       // [pad16(Kn)][ldL]
-        for (int x = tid; x < TJ * ldB; x += kPsThreads) Bs[x] = 0.0;
-        f64x4 acc[2] = {f64x4{0.0, 0.0, 0.0, 0.0}, f64x4{0.0, 0.0, 0.0, 0.0}};
-        double rsum = 0.0;
-        for (int t = blockIdx.x; t < ntiles; t += G) {
-          const int j0 = t * TJ;
-          const int jn = min(TJ, J - j0);
-          __syncthreads();
-          {  // P_<n>[:, tile] into Ls, rows zero-padded to a multiple of 16
-            constexpr int kPer = (64 * TJ + kPsThreads - 1) / kPsThreads;
-            double pv[kPer];
-#pragma unroll
-            for (int e = 0; e < kPer; ++e) {
-              const int x = tid + e * kPsThreads;
-              const int i = x / TJ, jj = x % TJ;
-              pv[e] = 0.0;
-              if (i < Kn && jj < jn) {
-                int rem = j0 + jj, base = 0;
-#pragma unroll
-                for (int u = 6; u >= 0; --u) {
-                  if (u <= N - 2) {
-                    const int d = cycK[u];
-                    const int q = rem / d;
-                    base += (rem - q * d) * (int)cycStride[u];
-                    rem = q;
-                  }
-                }
-                pv[e] = g.P[base + i * strideN];
-              }
-            }
-#pragma unroll
-            for (int e = 0; e < kPer; ++e) {
-              const int x = tid + e * kPsThreads;
-              const int i = x / TJ, jj = x % TJ;
-              if (i < MT * 16) Ls[i * ldL + jj] = pv[e];
-            }
+      const PsGeom q = ps_geom(g, n, TJ);
+      const int Kn = q.Kn, Ra = q.Ra, Rb = q.Rb, RR = q.RR, nM = q.nM;
+      const int nrec = q.ntiles < G ? q.ntiles : G;
+      const int NT = pad16(RR) / 16, MT = pad16(Kn) / 16;
+      const int ntM = MT * NT, ntot = ntM + NT * (NT + 1) / 2;
+      const int ldB = pad16(RR) + 1, ldL = TJ + 1;
+      const int rec_g = nM;            // Gram offset in a record
+      const int rec_r = nM + RR * RR;  // residual slot
+      // ---- A ---------------------------------------------------------------------------
+      if ((int)blockIdx.x < nrec) {
+        double* Bs = U;                  // [TJ][ldB], columns >= RR stay zero
+        double* Ls = Bs + TJ * ldB;      // [pad16(Kn)][ldL]
+        double* Zr = Ls + pad16(Kn) * ldL;  // core n as [pad16(Kn)][ldB] (rows i, cols (a,b))
+        if (report)
+          for (int x = tid; x < pad16(Kn) * ldB; x += kPsThreads) {
+            const int i = x / ldB, r = x % ldB;
+            double v = 0.0;
+            if (i < Kn && r < RR) v = Zs[q.zoffN + ((r / Rb) * Kn + i) * Rb + (r % Rb)];
+            Zr[x] = v;
           }
-          // subchain rows: item (jl, b) forms row b of S_j from the LDS cores
+        f64x4 acc[kPsTiles];
+#pragma unroll
+        for (int u = 0; u < kPsTiles; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+        double rsum = 0.0;
+        for (int t = blockIdx.x; t < q.ntiles; t += G) {
+          const int j0 = t * TJ, jn = min(TJ, q.J - j0);
+          __syncthreads();
+          if (t != (int)blockIdx.x) ps_load_p<TJ, KPER>(g, q, t, pv);
+#pragma unroll
+          for (int e = 0; e < KPER; ++e) {
+            const int x = tid + e * kPsThreads;
+            const int i = x / TJ, jj = x % TJ;
+            if (i < MT * 16) Ls[i * ldL + jj] = pv[e];
+          }
+          for (int x = KT * TJ + tid; x < MT * 16 * TJ; x += kPsThreads)  // rows KT.. (none)
+            Ls[(x / TJ) * ldL + x % TJ] = 0.0;
+          // subchain rows: item (jl, b) forms row b of S_j; every load is in range (clamped
+          // indices, zero weights beyond the ranks), so the loads issue without branches
           for (int x = tid; x < TJ * Rb; x += kPsThreads) {
             const int jl = x / Rb, b = x % Rb;
             double v[RM], w[RM];
+            int rem = j0 + (jl < jn ? jl : 0);
+            int idx[7];
 #pragma unroll
-            for (int a = 0; a < RM; ++a) v[a] = 0.0;
-            if (jl < jn) {
-              int rem = j0 + jl;
-              int idx[7];
-#pragma unroll
-              for (int u = 6; u >= 0; --u) {
-                if (u <= N - 2) {
-                  idx[u] = rem % chI[u];
-                  rem /= chI[u];
-                }
+            for (int u = 6; u >= 0; --u) {
+              if (u <= N - 2) {
+                idx[u] = rem % q.chI[u];
+                rem /= q.chI[u];
               }
-              {
-                const int cRb = chRb[0];
-                const double* G0 = Zs + chOff[0] + ((int64_t)b * chI[0] + idx[0]) * cRb;
+            }
+            {
+              const int cR = q.chRb[0];
+              const double* G0 = Zs + q.chOff[0] + (b * q.chI[0] + idx[0]) * cR;
 #pragma unroll
-                for (int c = 0; c < RM; ++c) v[c] = c < cRb ? G0[c] : 0.0;
+              for (int c = 0; c < RM; ++c) {
+                const double t0 = G0[c < cR ? c : cR - 1];
+                v[c] = c < cR ? t0 : 0.0;
               }
-              int cur = chRb[0];
+            }
+            int cur = q.chRb[0];
 #pragma unroll
-              for (int u = 1; u < 7; ++u) {
-                if (u < N - 1) {
-                  const int cRb = chRb[u];
-                  const double* Gm = Zs + chOff[u] + (int64_t)idx[u] * cRb;
-                  const int rs = chI[u] * cRb;
+            for (int u = 1; u < 7; ++u) {
+              if (u < N - 1) {
+                const int cR = q.chRb[u];
+                const int rs = q.chI[u] * cR;
+                const double* Gm = Zs + q.chOff[u] + idx[u] * cR;
 #pragma unroll
-                  for (int c = 0; c < RM; ++c) w[c] = 0.0;
+                for (int c = 0; c < RM; ++c) w[c] = 0.0;
 #pragma unroll
-                  for (int a = 0; a < RM; ++a) {
-                    if (a < cur) {
-                      const double va = v[a];
-                      const double* gr = Gm + a * rs;
+                for (int a = 0; a < RM; ++a) {
+                  const double* gr = Gm + (a < cur ? a : cur - 1) * rs;
 #pragma unroll
-                      for (int c = 0; c < RM; ++c)
-                        if (c < cRb) w[c] += va * gr[c];
-                    }
-                  }
-#pragma unroll
-                  for (int c = 0; c < RM; ++c) v[c] = w[c];
-                  cur = cRb;
+                  for (int c = 0; c < RM; ++c) w[c] = fma(v[a], gr[c < cR ? c : cR - 1], w[c]);
                 }
+#pragma unroll
+                for (int c = 0; c < RM; ++c) v[c] = c < cR ? w[c] : 0.0;
+                cur = cR;
               }
             }
 #pragma unroll
             for (int a = 0; a < RM; ++a)
-              if (a < Ra) Bs[jl * ldB + a * Rb + b] = v[a];
+              if (a < Ra) Bs[jl * ldB + a * Rb + b] = jl < jn ? v[a] : 0.0;
           }
           __syncthreads();
-          if (!last) {  // M += P tile * B tile on the FP64 matrix cores
-            const int r16 = lane & 15, g4 = lane >> 4;
+          if (!last) {  // M += P tile B tile, Gram += B tile^T B tile (FP64 matrix cores)
 #pragma unroll
-            for (int q2 = 0; q2 < 2; ++q2) {
-              const int q = wid + 8 * q2;
-              if (q < ntM) {
-                const int mt = q / NT, nt = q % NT;
-                const double* ap = Ls + (mt * 16 + r16) * ldL + g4;
+            for (int u = 0; u < kPsTiles; ++u) {
+              const int qq = wid + 8 * u;
+              if (qq < ntot) {
+                const bool isM = qq < ntM;
+                int mt, nt;
+                ps_tile(qq, ntM, NT, mt, nt);
+                const double* ap = isM ? Ls + (mt * 16 + r16) * ldL + g4
+                                       : Bs + g4 * ldB + mt * 16 + r16;
+                const int ast = isM ? 1 : ldB;
                 const double* bp = Bs + g4 * ldB + nt * 16 + r16;
-                f64x4 c = acc[q2];
+                f64x4 c = acc[u];
 #pragma unroll 8
-                for (int k0 = 0; k0 < TJ; k0 += 4) c = mma_f64(ap[k0], bp[k0 * ldB], c);
-                acc[q2] = c;
+                for (int k0 = 0; k0 < TJ; k0 += 4) c = mma_f64(ap[k0 * ast], bp[k0 * ldB], c);
+                acc[u] = c;
               }
             }
           }
-          if (report) {  // residual of these columns with the current core n
-            const double* Zn = Zs + zoffN;
-            for (int x = tid; x < Kn * TJ; x += kPsThreads) {
-              const int i = x / TJ, jj = x % TJ;
-              if (jj < jn) {
-                double psi = 0.0;
-                for (int a = 0; a < Ra; ++a) {
-                  const double* zr = Zn + ((int64_t)a * Kn + i) * Rb;
-                  const double* br = Bs + jj * ldB + a * Rb;
-                  for (int b = 0; b < Rb; ++b) psi += zr[b] * br[b];
+          if (report) {  // (P - Z_n B^T)^2 over this tile; Psi tile on the matrix cores
+            const int JT = TJ / 16;
+            for (int qq = wid; qq < MT * JT; qq += 8) {
+              const int mt = qq / JT, jt = qq % JT;
+              const double* ap = Zr + (mt * 16 + r16) * ldB + g4;
+              const double* bp = Bs + (jt * 16 + r16) * ldB + g4;
+              f64x4 c = {0.0, 0.0, 0.0, 0.0};
+              for (int k0 = 0; k0 < pad16(RR); k0 += 4) c = mma_f64(ap[k0], bp[k0], c);
+              const int col = jt * 16 + r16;
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int row = mt * 16 + 4 * r + g4;
+                if (row < Kn && col < jn) {
+                  const double d = Ls[row * ldL + col] - c[r];
+                  rsum = fma(d, d, rsum);
                 }
-                const double d = Ls[i * ldL + jj] - psi;
-                rsum += d * d;
               }
             }
           }
         }
         double* out = g.part + (int64_t)blockIdx.x * g.rec;
-        {
-          const int r16 = lane & 15, g4 = lane >> 4;
 #pragma unroll
-          for (int q2 = 0; q2 < 2; ++q2) {
-            const int q = wid + 8 * q2;
-            if (q < ntM) {
-              const int mt = q / NT, nt = q % NT;
-              const int col = nt * 16 + r16;
+        for (int u = 0; u < kPsTiles; ++u) {
+          const int qq = wid + 8 * u;
+          if (qq < ntot) {
+            const bool isM = qq < ntM;
+            int mt, nt;
+            ps_tile(qq, ntM, NT, mt, nt);
+            const int col = nt * 16 + r16;
 #pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int row = mt * 16 + 4 * r + g4;
-                if (row < Kn && col < RR) out[row * RR + col] = last ? 0.0 : acc[q2][r];
+            for (int r = 0; r < 4; ++r) {
+              const int row = mt * 16 + 4 * r + g4;
+              if (isM) {
+                if (row < Kn && col < RR) out[row * RR + col] = acc[u][r];
+              } else if (row < RR && col < RR) {
+                out[rec_g + row * RR + col] = acc[u][r];
+                if (nt != mt) out[rec_g + col * RR + row] = acc[u][r];  // the mirrored tile
               }
             }
           }
         }
         rsum = block_sum(rsum, wred);
-        if (tid == 0) out[nM] = rsum;
+        if (tid == 0) out[rec_r] = rsum;
       }
       if (!ps_grid_sync(g.bar, nblk, epoch, g.spin_limit, g.status, &s_fail)) return;
-      // ---- B: fixed-order sum of the records, element slices over all work-groups ------
+      // ---- B: fixed-order sum of the records, element slices over the work-groups ------
       {
-        const int nv = nM + 1;
-        const int per = (nv + (int)nblk - 1) / (int)nblk;
+        const int nv = rec_r + 1;
+        const int per = (nv + G - 1) / G;
         const int e0 = (int)blockIdx.x * per;
         const int e1 = min(nv, e0 + per);
-        double* cb = U;  // kPsThreads doubles
+        double* cb = U + g.ubuf;  // kPsThreads doubles
         for (int base = e0; base < e1; base += kPsThreads) {
           const int cnt = min(e1 - base, kPsThreads);
           const int ngrp = kPsThreads / cnt;
@@ -837,7 +1009,7 @@ __global__ __launch_bounds__(kPsThreads) void als_persist_kernel(AlsPersistArgs 
           __syncthreads();
           if (tid < cnt) {
             double t = 0.0;
-            for (int q = 0; q < ngrp; ++q) t += cb[q * cnt + tid];
+            for (int qq = 0; qq < ngrp; ++qq) t += cb[qq * cnt + tid];
             g.red[base + tid] = t;
           }
           __syncthreads();
@@ -846,7 +1018,7 @@ __global__ __launch_bounds__(kPsThreads) void als_persist_kernel(AlsPersistArgs 
       if (!ps_grid_sync(g.bar, nblk, epoch, g.spin_limit, g.status, &s_fail)) return;
       // ---- C: the error of the sweep before, the stopping test, the solve ---------------
       if (report) {
-        const double e = sqrt(g.red[nM] / pn2);
+        const double e = sqrt(g.red[rec_r] / pn2);
         if (blockIdx.x == 0 && tid == 0) {
           g.trace[s - 1] = e;
           *g.sweeps_run = s;
@@ -856,30 +1028,21 @@ __global__ __launch_bounds__(kPsThreads) void als_persist_kernel(AlsPersistArgs 
         if (stop || last) break;
       }
       {
-        double* Mt = U;
-        double* Gm = Mt + nM;
-        double* X = Gm + RR * RR;
-        double* rowbuf = X + RR * Kn;
-        double* colbuf = rowbuf + 512;
-        for (int x = tid; x < nM; x += kPsThreads) Mt[x] = g.red[x];
-        for (int x = tid; x < RR * RR; x += kPsThreads) Gm[x] = g.gram[x];
-        __syncthreads();
-        if (gauss_jordan<QMAX>(Gm, Mt, X, rowbuf, colbuf, RR, Kn, &s_gj)) {
-          __syncthreads();
-          for (int x = tid; x < nM; x += kPsThreads) {
-            const int i = x / RR, r = x % RR;
-            const int a = r / Rb, b = r % Rb;
-            Zs[zoffN + ((int64_t)a * Kn + i) * Rb + b] = X[r * Kn + i];
-          }
-        } else if (blockIdx.x == 0 && tid == 0) {
+        // the next update's first P tile, in flight during the solve
+        const int nn = n + 1 < N ? n + 1 : 0;
+        const PsGeom qn = ps_geom(g, nn, TJ);
+        ps_load_p<TJ, KPER>(g, qn, blockIdx.x, pv);
+        double* rowbuf = U + g.ubuf;
+        double* colbuf = rowbuf + 4 * kPsRowBuf;
+        if (!ps_solve<CW>(g.red, rec_g, RR, Kn, Rb, Zs + q.zoffN, rowbuf, colbuf) &&
+            blockIdx.x == 0 && tid == 0)
           atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
-        }
         __syncthreads();
       }
     }
   }
   if (blockIdx.x == 0)
-    for (int64_t x = tid; x < g.ztotal; x += kPsThreads) g.Z[x] = Zs[x];
+    for (int x = tid; x < (int)g.ztotal; x += kPsThreads) g.Z[x] = Zs[x];
 }
 
 __global__ void als_persist_begin_kernel(unsigned* bar, int* sweeps_run) {
@@ -888,41 +1051,59 @@ __global__ void als_persist_begin_kernel(unsigned* bar, int* sweeps_run) {
 }
 
 namespace {
-int ps_tj(const AlsPersistArgs& g) { return g.TJ; }
-
-int64_t ps_words(int TJ, int maxK, int maxRR, int tdim, int64_t ztotal) {
-  const int64_t a = (int64_t)TJ * (pad16(maxRR) + 1) + (int64_t)pad16(maxK) * (TJ + 1);
-  const int64_t gram = 3 * (int64_t)tdim * tdim + 64 * (int64_t)tdim;
-  const int64_t c = (int64_t)maxK * maxRR * 2 + (int64_t)maxRR * maxRR + 1024;
-  const int64_t b = kPsThreads;
-  return zwords(ztotal) + std::max(std::max(a, gram), std::max(c, b));
+// Tile buffers (B, the P tile, core n reshaped) and, past them, the buffers of the record sum
+// and the solve.
+int64_t ps_ubuf(int TJ, int maxK, int maxRR) {
+  const int ldB = pad16(maxRR) + 1;
+  return (int64_t)TJ * ldB + (int64_t)pad16(maxK) * (TJ + 1) + (int64_t)pad16(maxK) * ldB;
 }
 
-template <int RM, int QMAX>
-const void* ps_fn(int TJ) {
-  return TJ == 128 ? (const void*)als_persist_kernel<RM, QMAX, 128>
-                   : (const void*)als_persist_kernel<RM, QMAX, 64>;
+int64_t ps_words(int TJ, int maxK, int maxRR, int64_t ztotal) {
+  const int64_t c = std::max<int64_t>(4 * kPsRowBuf + 4 * 64, kPsThreads);
+  return zwords(ztotal) + ps_ubuf(TJ, maxK, maxRR) + c;
+}
+
+template <int RM, int CW, int KT>
+const void* ps_fn3(int TJ) {
+  return TJ == 128 ? (const void*)als_persist_kernel<RM, CW, 128, KT>
+                   : (const void*)als_persist_kernel<RM, CW, 64, KT>;
+}
+
+template <int RM, int CW>
+const void* ps_fn2(int TJ, int maxK) {
+  return maxK <= 32 ? ps_fn3<RM, CW, 32>(TJ) : ps_fn3<RM, CW, 64>(TJ);
+}
+
+template <int RM>
+const void* ps_fn(int TJ, int cw, int maxK) {
+  return cw == 4 ? ps_fn2<RM, 4>(TJ, maxK) : cw == 8 ? ps_fn2<RM, 8>(TJ, maxK)
+                                                     : ps_fn2<RM, 16>(TJ, maxK);
 }
 }  // namespace
 
-// Plans the persistent launch; false if the shape is outside what it takes (the caller then
-// runs the two-kernel updates).  Fills TJ, G, rec, tdim, lds (bytes).
+// Plans the single launch; false if the shape is outside what it takes (the caller then runs
+// the two-kernel updates).  Fills TJ, G, rec, maxNe, rmax and the LDS bytes.
 bool als_persist_plan(AlsPersistArgs* g, size_t* lds) {
   int maxK = 0, rmax = 0, maxRR = 0, maxNe = 0;
+  int64_t rec = 1;
   for (int n = 0; n < g->N; ++n) {
     const int Kn = g->K[n], RR = g->R[n] * g->R[(n + 1) % g->N];
     maxK = std::max(maxK, Kn);
     rmax = std::max(rmax, g->R[n]);
     maxRR = std::max(maxRR, RR);
-    if (RR + Kn > 256) return false;
-    maxNe = std::max(maxNe, RR * (RR + Kn));
+    if (RR > 64 || RR + Kn + 16 > kPsRowBuf) return false;
+    maxNe = std::max(maxNe, ps_cw(RR, RR + Kn));
+    if (!ps_cw(RR, RR + Kn)) return false;
+    rec = std::max(rec, (int64_t)Kn * RR + (int64_t)RR * RR + 1);
   }
-  if (rmax > 6 || maxK > 64 || g->ztotal > kZldsMax || g->total >= (1LL << 31)) return false;
-  if (maxNe > kPsThreads * 8) return false;
-  g->tdim = als2_tdim(rmax);
+  if (rmax > 8 || maxK > 64 || g->ztotal > kZldsMax || g->total >= (1LL << 31)) return false;
+  {  // output tiles of M and the Gram per wavefront
+    const int NT = pad16(maxRR) / 16, MT = pad16(maxK) / 16;
+    if (MT * NT + NT * (NT + 1) / 2 > 8 * kPsTiles) return false;
+  }
   int tj = 0;
   for (int t = 128; t >= 64; t /= 2)
-    if (ps_words(t, maxK, maxRR, g->tdim, g->ztotal) * 8 <= 150 * 1024) {
+    if (ps_words(t, maxK, maxRR, g->ztotal) * 8 <= 150 * 1024) {
       tj = t;
       break;
     }
@@ -934,22 +1115,21 @@ bool als_persist_plan(AlsPersistArgs* g, size_t* lds) {
     maxTiles = std::max(maxTiles, (J + tj - 1) / tj);
   }
   g->G = (int)std::min<int64_t>(maxTiles, 128);
-  g->rec = (int64_t)64 * 36 + 1;
-  {
-    int64_t r = 1;
-    for (int n = 0; n < g->N; ++n)
-      r = std::max(r, (int64_t)g->K[n] * g->R[n] * g->R[(n + 1) % g->N] + 1);
-    g->rec = r;
-  }
-  *lds = (size_t)ps_words(tj, maxK, maxRR, g->tdim, g->ztotal) * 8;
+  g->rec = rec;
   g->maxNe = maxNe;
+  g->rmax = rmax;
+  g->maxK = maxK;
+  g->ubuf = ps_ubuf(tj, maxK, maxRR);
+  *lds = (size_t)ps_words(tj, maxK, maxRR, g->ztotal) * 8;
   return true;
 }
 
 hipError_t launch_als_persist(const AlsPersistArgs& ga, size_t lds, hipStream_t s) {
   AlsPersistArgs g = ga;
-  const bool q4 = g.maxNe <= kPsThreads * 4;
-  const void* fn = q4 ? ps_fn<8, 4>(g.TJ) : ps_fn<8, 8>(g.TJ);
+  // maxNe holds the largest columns-per-thread tier of the solve over the updates
+  const void* fn = g.rmax <= 4 ? ps_fn<4>(g.TJ, g.maxNe, g.maxK)
+                 : g.rmax <= 6 ? ps_fn<6>(g.TJ, g.maxNe, g.maxK)
+                               : ps_fn<8>(g.TJ, g.maxNe, g.maxK);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int dev = 0, cus = 0, per_cu = 0;
@@ -958,13 +1138,12 @@ hipError_t launch_als_persist(const AlsPersistArgs& ga, size_t lds, hipStream_t 
     return e;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPsThreads, lds)) != hipSuccess)
     return e;
-  if ((int64_t)per_cu * cus < g.G + 1) return hipErrorCooperativeLaunchTooLarge;
+  if ((int64_t)per_cu * cus < g.G) return hipErrorCooperativeLaunchTooLarge;
   hipLaunchKernelGGL(als_persist_begin_kernel, dim3(1), dim3(1), 0, s, g.bar, g.sweeps_run);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   prof_begin("als_persist", s);
   void* args[] = {&g};
-  e = hipLaunchCooperativeKernel(fn, dim3((unsigned)(g.G + 1)), dim3(kPsThreads), args,
-                                 (unsigned)lds, s);
+  e = hipLaunchCooperativeKernel(fn, dim3((unsigned)g.G), dim3(kPsThreads), args, (unsigned)lds, s);
   prof_end(s);
   if (e != hipSuccess) return e;
   return hipGetLastError();

@@ -177,7 +177,6 @@ struct AlsPersistArgs {
   const double* pn2;      // ||P||_F^2
   double* part;           // [G][rec] partial records
   double* red;            // [rec] summed record
-  double* gram;           // RR x RR Gram of the current update
   unsigned* bar;          // grid-barrier arrival counter (zeroed before the launch)
   unsigned* status;
   double* trace;
@@ -192,8 +191,9 @@ struct AlsPersistArgs {
   int64_t ztotal;
   unsigned spin_limit;    // bound of a barrier wait (in sleeps of ~128 cycles)
   // filled by als_persist_plan
-  int TJ, G, tdim, maxNe;
-  int64_t rec;
+  int TJ, G, maxNe, rmax, maxK;
+  int64_t ubuf;           // doubles of the per-work-group tile buffers
+  int64_t rec;            // record length: K_n R R' (M) + (R R')^2 (Gram) + 1 (residual)
 };
 bool als_persist_plan(AlsPersistArgs* g, size_t* lds);
 hipError_t launch_als_persist(const AlsPersistArgs& g, size_t lds, hipStream_t s);

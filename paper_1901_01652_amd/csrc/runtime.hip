@@ -702,12 +702,9 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
     pa.ztotal = (int64_t)zoff[order];
     size_t plds = 0;
     if (rtr::als_persist_plan(&pa, &plds)) {
-      int maxRR = 1;
-      for (int n = 0; n < order; ++n) maxRR = std::max(maxRR, (int)(R[n] * R[(n + 1) % order]));
       Carve plan(nullptr);
       plan.take<double>((size_t)pa.G * pa.rec);
       plan.take<double>((size_t)pa.rec);
-      plan.take<double>((size_t)maxRR * maxRR);
       plan.take<double>(1024);
       plan.take<double>(1);
       plan.take<unsigned>(1);
@@ -715,7 +712,6 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
       Carve cv(h->ws);
       pa.part = cv.take<double>((size_t)pa.G * pa.rec);
       pa.red = cv.take<double>((size_t)pa.rec);
-      pa.gram = cv.take<double>((size_t)maxRR * maxRR);
       double* red = cv.take<double>(1024);
       double* pn2 = cv.take<double>(1);
       pa.bar = cv.take<unsigned>(1);
@@ -731,7 +727,7 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
       pa.sweeps_run = sweeps_run;
       pa.tol = opts->tol;
       pa.max_sweeps = opts->max_sweeps;
-      pa.spin_limit = 1u << 24;
+      pa.spin_limit = 1u << 22;
       const hipError_t e = rtr::launch_als_persist(pa, plds, s);
       if (e == hipSuccess) return RTR_OK;
       if (e != hipErrorCooperativeLaunchTooLarge) return hip_fail(h, e, "single-launch TR-ALS");

@@ -16,14 +16,15 @@ __device__ bool gauss_jordan(const double* G, const double* M, double* X, double
   const int tid = threadIdx.x, nth = blockDim.x;
   const int W = RR + Kn, ne = RR * W;
   double a[QMAX];
-  int rr[QMAX], cc[QMAX];
+  int rr[QMAX], cc[QMAX];  // row (-1: no element) and column of each owned element
 #pragma unroll
   for (int q = 0; q < QMAX; ++q) {
     const int e = tid + nth * q;
-    rr[q] = e < ne ? e / W : -1;
-    cc[q] = e % W;
+    const bool ok = e < ne;
+    rr[q] = ok ? e / W : -1;
+    cc[q] = ok ? e % W : 0;
     a[q] = 0.0;
-    if (e < ne) a[q] = cc[q] < RR ? G[rr[q] * RR + cc[q]] : M[(cc[q] - RR) * RR + rr[q]];
+    if (ok) a[q] = cc[q] < RR ? G[rr[q] * RR + cc[q]] : M[(cc[q] - RR) * RR + rr[q]];
   }
   for (int k = 0; k < RR; ++k) {
     double* rb = rowbuf + (k & 1) * 256;
@@ -34,7 +35,15 @@ __device__ bool gauss_jordan(const double* G, const double* M, double* X, double
       if (cc[q] == k && rr[q] >= 0) cb[rr[q]] = a[q];
     }
     __syncthreads();
+    // every read of the step at once (indices of absent elements point at valid entries),
+    // then one wait: the step costs one LDS round trip, not one per element
     const double piv = rb[k];
+    double rv[QMAX], cv[QMAX];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      rv[q] = rb[cc[q]];
+      cv[q] = cb[rr[q] > 0 ? rr[q] : 0];
+    }
     if (!(piv > 0.0)) {
       if (tid == 0) *failed = 1;
       return false;
@@ -42,10 +51,9 @@ __device__ bool gauss_jordan(const double* G, const double* M, double* X, double
     const double inv = 1.0 / piv;
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      if (rr[q] >= 0) {
-        const double rk = rb[cc[q]] * inv;  // new row k entry
-        a[q] = (rr[q] == k) ? rk : a[q] - cb[rr[q]] * rk;
-      }
+      const double rk = rv[q] * inv;  // new row k entry
+      const double up = (rr[q] == k) ? rk : fma(-cv[q], rk, a[q]);
+      a[q] = rr[q] >= 0 ? up : a[q];
     }
   }
 #pragma unroll
