@@ -47,6 +47,15 @@ int64_t fast_pass_grid(Arith ar, const ModeView& v, int K, int op, const void* X
 hipError_t launch_fast_pass(Arith ar, int op, const void* X, const ModeView& v, int K,
                             uint64_t seed, uint32_t stream_word, uint32_t tensor_id,
                             const double* Q, void* partial, int64_t grid, hipStream_t s);
+// ---- slab.hip: BF16 sketch (op 0) / power step (op 1) of the last two modes in one pass ---
+// X viewed as A contiguous slabs of Ip x Iq; partials [grid][Ip][Kp] and [grid][Iq][Kq] (FP32).
+bool slab_pass_supported(int64_t A, int64_t Ip, int64_t Iq, int Kp, int Kq, const void* X,
+                         int op);
+int64_t slab_pass_grid(int64_t A);
+hipError_t launch_slab_pass(int op, const void* X, int64_t A, int64_t Ip, int64_t Iq, int Kp,
+                            int Kq, uint64_t seed, uint32_t swp, uint32_t swq, uint32_t tensor_id,
+                            const double* Qp, const double* Qq, float* partp, float* partq,
+                            int64_t grid, hipStream_t s);
 // Fixed-order sum of partials into column-major Ycol (K x In storage, Ycol[k*In+i]).
 hipError_t launch_reduce_partials(Arith ar, const void* partial, int64_t chunks, int64_t In,
                                   int K, double* Ycol, hipStream_t s);
@@ -74,6 +83,10 @@ bool compress_slab_supported(Arith ar, int64_t A, int64_t I1, int64_t I2, int K1
 hipError_t launch_compress_slab(Arith ar, const void* X, int64_t A, int64_t I1, int64_t I2,
                                 int K1, int K2, const double* Q1, const double* Q2, double* T,
                                 hipStream_t s);
+// BF16 path with FP32 refinement, one wavefront per slab (compress_wave.hip): same output.
+bool compress_wave_supported(int64_t A, int64_t Ip, int64_t Iq, int Kp, int Kq, const void* X);
+hipError_t launch_compress_wave(const void* X, int64_t A, int64_t Ip, int64_t Iq, int Kp, int Kq,
+                                const double* Qp, const double* Qq, double* T, hipStream_t s);
 // Sum of squares of n values (FP64/FP32) into out[0] (FP64); ``partial`` holds 1024 FP64.
 hipError_t launch_sumsq(bool f32, const void* x, int64_t n, double* partial, double* out,
                         hipStream_t s);

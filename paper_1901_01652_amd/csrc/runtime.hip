@@ -255,7 +255,8 @@ namespace rtr {
 static bool streams_x(const char* name) {
   static const char* const kNames[] = {"sketch_partial", "power_partial", "ttm_first",
                                        "residual", "sketch_fused", "power_fused",
-                                       "compress_fused", "read_probe", "als_persist"};
+                                       "compress_fused", "read_probe", "als_persist",
+                                       "sketch_slab", "power_slab"};
   for (const char* k : kNames)
     if (std::strcmp(k, name) == 0) return true;
   return false;
@@ -376,9 +377,25 @@ rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t
   CHECK_DEV(Q, q_bytes(dims, K, order), "Q");
   hipStream_t s = (hipStream_t)stream;
 
+  // BF16 path: the last two modes share one slab pass per step (sketch, and each power round)
+  // when both are projected and the slab shape fits the kernel
+  const int sp = order - 2, sq = order - 1;
+  int64_t slabA = 1;
+  for (int n = 0; n < sp; ++n) slabA *= dims[n];
+  const bool slab_ok = ar == rtr::kBF16 && order >= 2 && keff(dims, K, sp) < dims[sp] &&
+                       keff(dims, K, sq) < dims[sq];
+  const bool slab0 = slab_ok && rtr::slab_pass_supported(slabA, dims[sp], dims[sq], (int)keff(dims, K, sp),
+                                                         (int)keff(dims, K, sq), X, 0);
+  const bool slab1 = slab_ok && power_iters > 0 &&
+                     rtr::slab_pass_supported(slabA, dims[sp], dims[sq], (int)keff(dims, K, sp),
+                                              (int)keff(dims, K, sq), X, 1);
+  const int64_t slab_grid = (slab0 || slab1) ? rtr::slab_pass_grid(slabA) : 0;
+  const size_t slab_part = (size_t)slab_grid *
+                           (size_t)(dims[sp] * keff(dims, K, sp) + dims[sq] * keff(dims, K, sq)) *
+                           sizeof(float);
   // workspace: partial sums (largest mode), then per mode Ycol and Qwork
   const size_t pelem = (ar == rtr::kF64) ? sizeof(double) : sizeof(float);
-  size_t pmax = 0;
+  size_t pmax = (slab0 || slab1) ? slab_part : 0;
   for (int n = 0; n < order; ++n) {
     const int64_t k = keff(dims, K, n);
     if (k == dims[n]) continue;
@@ -434,6 +451,16 @@ rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t
   }
 
   rtr::QrJobs jobs{};
+  // partial sums of the two slab modes (FP32) and the reduction of both into Ycol
+  float* partp = (float*)partial;
+  float* partq = partp + (size_t)slab_grid * dims[sp] * keff(dims, K, sp);
+  auto reduce_slab = [&]() -> rtr_status {
+    HIP_TRY(rtr::launch_reduce_partials(rtr::kF32, partp, slab_grid, dims[sp], (int)keff(dims, K, sp),
+                                        Ycol[sp], s), "reduce_partials");
+    HIP_TRY(rtr::launch_reduce_partials(rtr::kF32, partq, slab_grid, dims[sq], (int)keff(dims, K, sq),
+                                        Ycol[sq], s), "reduce_partials");
+    return RTR_OK;
+  };
   for (int n = 0; n < order; ++n) {
     const int64_t k = keff(dims, K, n);
     if (k == dims[n]) {
@@ -441,7 +468,16 @@ rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t
       continue;
     }
     rtr::ModeView v = mode_view(dims, order, n);
-    if (rtr::fast_pass_supported(ar, v, (int)k, 0)) {
+    if (slab0 && (n == sp || n == sq)) {
+      if (n == sp) {
+        HIP_TRY(rtr::launch_slab_pass(0, X, slabA, dims[sp], dims[sq], (int)keff(dims, K, sp),
+                                      (int)keff(dims, K, sq), seed, rtr::omega_stream(sp),
+                                      rtr::omega_stream(sq), tensor_id, nullptr, nullptr, partp,
+                                      partq, slab_grid, s),
+                "sketch_slab");
+        if ((st = reduce_slab())) return st;
+      }
+    } else if (rtr::fast_pass_supported(ar, v, (int)k, 0)) {
       const int64_t grid = rtr::fast_pass_grid(ar, v, (int)k, 0, X);
       HIP_TRY(rtr::launch_fast_pass(ar, 0, X, v, (int)k, seed, rtr::omega_stream(n), tensor_id,
                                     nullptr, partial, grid, s),
@@ -469,7 +505,15 @@ rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t
       const int64_t k = keff(dims, K, n);
       if (k == dims[n]) continue;
       rtr::ModeView v = mode_view(dims, order, n);
-      if (rtr::fast_pass_supported(ar, v, (int)k, 1)) {
+      if (slab1 && (n == sp || n == sq)) {
+        if (n == sp) {
+          HIP_TRY(rtr::launch_slab_pass(1, X, slabA, dims[sp], dims[sq], (int)keff(dims, K, sp),
+                                        (int)keff(dims, K, sq), 0, 0, 0, 0, Qn[sp], Qn[sq], partp,
+                                        partq, slab_grid, s),
+                  "power_slab");
+          if ((st = reduce_slab())) return st;
+        }
+      } else if (rtr::fast_pass_supported(ar, v, (int)k, 1)) {
         const int64_t grid = rtr::fast_pass_grid(ar, v, (int)k, 1, X);
         HIP_TRY(rtr::launch_fast_pass(ar, 1, X, v, (int)k, 0, 0, 0, Qn[n], partial, grid, s),
                 "power_fused");
@@ -553,10 +597,15 @@ rtr_status rtr_compress(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t 
   // product per remaining mode (mode 1 first).  Each step maps ``cur`` dims to new dims.
   int64_t A = 1;
   for (int n = 0; n < order - 2; ++n) A *= dims[n];
+  // BF16: one wavefront per slab (compress_wave.hip); else the work-group slab kernel
+  const bool wavek =
+      order >= 2 && ar == rtr::kBF16 &&
+      rtr::compress_wave_supported(A, dims[order - 2], dims[order - 1], (int)keff(dims, K, order - 2),
+                                   (int)keff(dims, K, order - 1), X);
   const bool fused =
-      order >= 2 && rtr::compress_slab_supported(ar, A, dims[order - 2], dims[order - 1],
-                                                 (int)keff(dims, K, order - 2),
-                                                 (int)keff(dims, K, order - 1));
+      order >= 2 && (wavek || rtr::compress_slab_supported(ar, A, dims[order - 2], dims[order - 1],
+                                                           (int)keff(dims, K, order - 2),
+                                                           (int)keff(dims, K, order - 1)));
   int64_t cur[RTR_MAX_ORDER];
   for (int n = 0; n < order; ++n) cur[n] = dims[n];
   size_t maxmid = 1;
@@ -591,9 +640,14 @@ rtr_status rtr_compress(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t 
   if (fused) {
     const int K1 = (int)keff(dims, K, order - 2), K2 = (int)keff(dims, K, order - 1);
     double* out = (nmodes == 0) ? P : buf[nb];
-    HIP_TRY(rtr::launch_compress_slab(ar, X, A, dims[order - 2], dims[order - 1], K1, K2,
-                                      Q + qoffs[order - 2], Q + qoffs[order - 1], out, s),
-            "compress_fused");
+    if (wavek)
+      HIP_TRY(rtr::launch_compress_wave(X, A, dims[order - 2], dims[order - 1], K1, K2,
+                                        Q + qoffs[order - 2], Q + qoffs[order - 1], out, s),
+              "compress_fused");
+    else
+      HIP_TRY(rtr::launch_compress_slab(ar, X, A, dims[order - 2], dims[order - 1], K1, K2,
+                                        Q + qoffs[order - 2], Q + qoffs[order - 1], out, s),
+              "compress_fused");
     cur[order - 2] = K1;
     cur[order - 1] = K2;
     in = out;

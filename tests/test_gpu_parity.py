@@ -87,7 +87,13 @@ def test_sketch_fp64(h, dims, K, q):
                                       ((13, 7, 9, 11), (5, 3, 4, 6), 0),
                                       ((24, 36, 40), (9, 20, 12), 1),
                                       ((13, 7, 9, 11), (5, 3, 4, 6), 1),
-                                      ((200, 12, 16), (40, 6, 8), 1)])
+                                      ((200, 12, 16), (40, 6, 8), 1),
+                                      # BF16: the last two modes in one slab pass (ragged strips
+                                      # and 32-wide chunks, K = 32, K < 16)
+                                      ((300, 52, 28), (9, 20, 12), 0),
+                                      ((300, 52, 28), (9, 20, 12), 1),
+                                      ((17, 19, 36, 44), (5, 6, 20, 32), 1),
+                                      ((16, 17, 64, 64), (4, 4, 7, 20), 1)])
 def test_sketch_low_precision(h, compute, tol, dims, K, q):
     say("sketch", compute, dims, K, q)
     X = rand_tensor(dims, 2).astype(np.float32)
@@ -117,7 +123,11 @@ def test_compress_fp64(h, dims, K):
 @pytest.mark.parametrize("compute,tol", [("f32", 1e-5), ("bf16", 3e-3)])
 @pytest.mark.parametrize("dims,K", [((33, 20, 17, 12), (8, 7, 6, 5)), ((300, 40, 52), (9, 20, 12)),
                                     ((260, 33, 29), (5, 30, 7)), ((16, 17, 40, 36), (3, 4, 17, 9)),
-                                    ((9, 8, 30, 20), (4, 4, 6, 5))])
+                                    ((9, 8, 30, 20), (4, 4, 6, 5)),
+                                    # BF16: one wavefront per slab (>= 512 slabs): ragged strips
+                                    # and chunks, slabs of the dense workload's shape, K = 32
+                                    ((600, 30, 44), (9, 20, 12)), ((520, 200, 200), (5, 20, 20)),
+                                    ((1024, 16, 28), (4, 16, 7)), ((8, 80, 36, 64), (3, 5, 32, 32))])
 def test_compress_low_precision(h, compute, tol, dims, K):
     say("compress", compute, dims, K)
     X = rand_tensor(dims, 6).astype(np.float32)
