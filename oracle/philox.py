@@ -18,7 +18,7 @@ Stream layout (the contract shared with the GPU side):
   element e of a stream comes from call c = e >> 2, lane e & 3; lanes 0,1 are the
   Box-Muller pair of words (w0, w1), lanes 2,3 the pair of words (w2, w3)
   uniform u(w) = (w + 1/2) 2^-32, so u is never 0 or 1
-  stream_word = tag << 24 | mode << 16 (mode is 0-based)
+  stream_word = tag << 24 | mode << 16 | factor << 8 (mode, factor 0-based)
 
 Parity: pinned by the published Philox known-answer vectors and by distribution tests.
 """
@@ -31,9 +31,12 @@ W1 = 0xBB67AE85
 _MASK = np.uint64(0xFFFFFFFF)
 
 TAG_OMEGA = 1  # Gaussian test matrices of Alg. 1 step 4
+TAG_KR = 3     # Gaussian factors of the Khatri-Rao structured test matrices
 
-def stream_word(tag, mode):
-    return ((tag & 0xFF) << 24) | ((mode & 0xFF) << 16)
+def stream_word(tag, mode, factor=0):
+    """stream_word = tag << 24 | mode << 16 | factor << 8 (factor: the other mode whose
+    Gaussian factor a Khatri-Rao test matrix draws; 0 otherwise)."""
+    return ((tag & 0xFF) << 24) | ((mode & 0xFF) << 16) | ((factor & 0xFF) << 8)
 
 
 def philox4x32_10(ctr, key):

@@ -18,6 +18,16 @@ Readings of the paper (each applies where the text is silent, ambiguous or garbl
 * Power iterations (the option named after Alg. 1, Halko et al. 2011 Alg. 4.4): after
   Q = qr(Y), repeat q times W = qr(X_(n)^T Q), Q = qr(X_(n) W).
 * RSE (Sec. 4) = ||X - Y||_F / ||X||_F, not squared.
+
+Projection variants (the remark after Alg. 1 names structured test matrices as an option; the
+loop of steps 3-8 also admits a sequential reading):
+* Khatri-Rao test matrix: M_n is the column-wise Kronecker product of one Gaussian factor
+  F_m (I_m x K_n, i.i.d. N(0,1), stream (TAG_KR, mode n, factor m)) per other mode m, rows in
+  the column order of X_(n): M_n[j, k] = prod_{m != n} F_m[i_m, k].  It needs sum_{m!=n} I_m
+  K_n normals instead of prod_{m!=n} I_m K_n.
+* Sequential: the sketch of mode n is taken of the tensor already compressed in modes
+  1..n-1, P^(n-1) = X x_1 Q_1^T .. x_{n-1} Q_{n-1}^T (M then has prod_{i<n} K'_i
+  prod_{i>n} I_i rows); P is P^(N).
 """
 import numpy as np
 import scipy.linalg
@@ -35,6 +45,23 @@ def gaussian_test_matrix(seed, n, rows, K, tensor_id=0):
     return z.reshape(rows, K)
 
 
+def khatri_rao_test_matrix(seed, n, dims, K, tensor_id=0):
+    """Structured test matrix for mode n (0-based): the Khatri-Rao product of Gaussian factors
+    F_m (dims[m] x K) over the other modes m in increasing order, the first of them varying
+    slowest (the column order of X_(n)).
+
+    Parity: pinned by the entry-wise definition written as explicit loops over the multi-index,
+    by exact range capture for unfoldings of rank <= K, and by its moments."""
+    M = np.ones((1, K))
+    for m in range(len(dims)):
+        if m == n:
+            continue
+        F = philox.normals(seed, philox.stream_word(philox.TAG_KR, n, m), tensor_id, 0,
+                           dims[m] * K).reshape(dims[m], K)
+        M = (M[:, None, :] * F[None, :, :]).reshape(-1, K)
+    return M
+
+
 def qr_pos(Y):
     """Alg. 1 step 6: economy QR (Householder, LAPACK) with R_ii >= 0.
 
@@ -44,8 +71,9 @@ def qr_pos(Y):
     return Q * s[None, :], R * s[:, None]
 
 
-def range_basis(X, n, K, q=0, seed=0, tensor_id=0):
+def range_basis(X, n, K, q=0, seed=0, tensor_id=0, test="gaussian"):
     """Q_n of Alg. 1 steps 4-6, with q power iterations (Halko et al. 2011, Alg. 4.4).
+    ``test`` = "khatri_rao" takes the structured test matrix instead of the Gaussian one.
 
     Parity: pinned by the exact-arithmetic identity Q = qr((A A^T)^q A M) and the range
     captured for matrices with known singular values."""
@@ -53,7 +81,10 @@ def range_basis(X, n, K, q=0, seed=0, tensor_id=0):
     if K >= In:
         return np.eye(In)
     A = unfold(X, n)
-    M = gaussian_test_matrix(seed, n, A.shape[1], K, tensor_id)
+    if test == "khatri_rao":
+        M = khatri_rao_test_matrix(seed, n, X.shape, K, tensor_id)
+    else:
+        M = gaussian_test_matrix(seed, n, A.shape[1], K, tensor_id)
     Q, _ = qr_pos(A @ M)
     for _ in range(q):
         W, _ = qr_pos(A.T @ Q)
@@ -69,6 +100,28 @@ def compress(X, Qs):
     for n, Q in enumerate(Qs):
         P = mode_product(P, Q.T, n)
     return P
+
+
+def sequential_bases(X, K, seed=0, tensor_id=0):
+    """Alg. 1 steps 3-8 with step 7 read sequentially: mode n is sketched (Gaussian M of the
+    same stream as the independent reading, rows = columns of the current unfolding) from
+    P^(n-1), then P^(n) = P^(n-1) x_n Q_n^T.  Returns (Q_1..Q_N, P).
+
+    Parity: pinned by mode 1 equal to the independent reading, by the independent reading
+    whenever every earlier mode is kept (K_m >= I_m), and by exact recovery of tensors of low
+    multilinear rank."""
+    P = np.asarray(X, dtype=np.float64)
+    Qs = []
+    for n in range(P.ndim):
+        In = P.shape[n]
+        if K[n] >= In:
+            Q = np.eye(In)
+        else:
+            A = unfold(P, n)
+            Q, _ = qr_pos(A @ gaussian_test_matrix(seed, n, A.shape[1], K[n], tensor_id))
+        Qs.append(Q)
+        P = mode_product(P, Q.T, n)
+    return Qs, P
 
 
 def core_shapes(K, ranks):
