@@ -50,7 +50,7 @@ def log(*a):
 # to, and how many modes one launch covers (for the per-launch share of the stage's bytes).
 KERNEL_STAGE = {"sketch_partial": "sketch", "sketch_fused": "sketch", "sketch_slab": "sketch",
                 "power_partial": "power", "power_fused": "power", "power_slab": "power",
-                "ttm_first": "compress", "compress_fused": "compress"}
+                "ttm_first": "compress", "compress_fused": "compress", "sketch_kr_allmode": "sketch"}
 MODES_PER_LAUNCH = {"sketch_partial": 1, "sketch_fused": 1, "sketch_slab": 2,
                     "power_partial": 1, "power_fused": 1, "power_slab": 2}
 
@@ -182,6 +182,232 @@ def gpu_block(rt, h, I_full, compute, block=64, reps=5):
             "compute": compute}
 
 
+def bench_hsi(rt, h, steps=5, scale=1):
+    """The hyperspectral-shaped workload (1024 x 1024 x 256 FP32 at scale 1, smooth rank-10
+    spatial cores, [0, 1], 30 dB; K = (60, 60, 40), q = 0; TR-ALS rank 10, 30 sweeps): time per
+    decomposition for the BF16 and plain FP32 paths, each stage's share of the method's
+    algorithmic bytes (one read of X for the sketch of all modes, one for the compression),
+    and the errors."""
+    import torch
+    import workloads as W
+    from paper_1901_01652_amd import pipeline
+    dev = "cuda:0"
+    w = W.hsi_shaped(scale=scale)
+    log(f"[bench] generating {w.name}")
+    X, _ = W.make_tensor(w, device=dev, dtype=torch.float32)
+    Z0 = rt.pack(W.make_init(w), dev)
+    stream = torch.cuda.current_stream(dev)
+    xbytes = w.numel() * 4
+    res = {"workload": f"{w.name} fp32, smooth rank-10 spatial cores, [0,1], 30 dB; K={w.K}, q=0; "
+                       "TR-ALS rank 10, 30 sweeps", "dims": w.dims, "K": w.K}
+    for compute in ("bf16", "f32"):
+        pipeline.rtr_als(h, X, w.K, w.ranks, Z0, w.sweeps, w.q, w.seed, compute=compute)
+        torch.cuda.synchronize()
+        rt.rtr_profile_reset(h)
+        rt.rtr_profile_enable(h, 1)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(steps):
+            out = pipeline.rtr_als(h, X, w.K, w.ranks, Z0, w.sweeps, w.q, w.seed, compute=compute)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        rt.rtr_profile_enable(h, 0)
+        ms = ev0.elapsed_time(ev1) / steps
+        kern, stages = {}, {}
+        for name in KERNEL_STAGE:
+            tot, n = rt.rtr_profile_read(h, name)
+            if n:
+                kern[name] = {"avg_ms": round(tot / n, 4), "launches": n}
+                st = KERNEL_STAGE[name]
+                stages[st] = stages.get(st, 0.0) + tot / steps
+        stages = {st: {"ms_per_step": round(v, 4), "alg_bytes": xbytes,
+                       "gbps": round(xbytes / (v * 1e-3) / 1e9, 1),
+                       "frac": round(xbytes / (v * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+                  for st, v in stages.items()}
+        r = rt.rtr_residual(h, X, w.ranks, out["G"]).cpu().numpy()
+        nsw = int(out["sweeps_run"].item())
+        e = float(out["err_trace"][nsw - 1].item())
+        pn2 = float(out["p_norm2"].item())
+        res[compute] = {"ms_per_step": round(ms, 3), "rse": round(float(np.sqrt(r[0] / r[1])), 6),
+                        "rse_pythagorean": round(float(np.sqrt(max(r[1] - pn2 + e * e * pn2, 0.0) / r[1])), 6),
+                        "stages": stages, "kernels": kern}
+        log(f"[bench] {w.name} {compute}: {ms:.3f} ms/step, RSE {res[compute]['rse']}")
+    del X
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_kr(rt, h, X, w, steps=5):
+    """The structured-projection variant on the same tensor: Khatri-Rao test matrices, whose
+    BF16 sketch of all modes (and ||X||^2) is one read of X.  Reports the sketch stage alone
+    (fraction of the HBM peak for one algorithmic read) and the whole decomposition."""
+    import torch
+    from paper_1901_01652_amd import pipeline
+    stream = torch.cuda.current_stream("cuda:0")
+    xbytes = w.numel() * 4
+    xn2 = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    res = {}
+    for name, fn in (("sketch", lambda: rt.rtr_sketch(h, X, w.K, 0, w.seed, compute="bf16",
+                                                         projection="khatri_rao", x_norm2=xn2)),
+                     ("step", lambda: pipeline.rtr_als(h, X, w.K, w.ranks, Z0, w.sweeps, w.q, w.seed,
+                                                       compute="bf16", projection="khatri_rao"))):
+        if name == "step":
+            import workloads as W
+            Z0 = rt.pack(W.make_init(w), "cuda:0")
+        fn()
+        torch.cuda.synchronize()
+        rt.rtr_profile_reset(h)
+        rt.rtr_profile_enable(h, 1)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rt.rtr_profile_enable(h, 0)
+        ms = e0.elapsed_time(e1) / steps
+        tot, n = rt.rtr_profile_read(h, "sketch_kr_allmode")
+        res[name] = {"ms": round(ms, 3)}
+        if n:
+            k_ms = tot / n
+            res[name]["one_read_kernel_ms"] = round(k_ms, 4)
+            res[name]["one_read_gbps"] = round(xbytes / (k_ms * 1e-3) / 1e9, 1)
+            res[name]["one_read_frac"] = round(xbytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+        if name == "step":
+            res[name]["rse"] = round(pipeline.rse(h, X, w.ranks, out["G"]), 6)
+    return res
+
+
+def _clock(fn, reps=1):
+    """Mean wall time (ms) of ``fn`` over ``reps`` calls, the device drained before and after."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps, out
+
+
+def bench_paper_shapes(rt, h, I=1024, Ks=(50, 75, 100, 125, 150, 175, 200)):
+    """Stand-ins for the paper's experiments on synthetic data of their shapes (Sec. 4):
+
+    * Sec. 4.1: a smooth I x I x 3 tensor, projection K x K x 3 over ``Ks`` (from 50: at K = 25
+      the first core's least squares has R_1 R_2 = 100 unknowns per row but only K x 3 = 75
+      equations), rTR-ALS (rank 10,
+      50 sweeps) and rTR-SVD (eps 0.15) against TR-ALS and TR-SVD on the full tensor, on the
+      same GPU (TR-SVD on the full tensor at 512 x 512 x 3: its first Gram matrix is I x I and
+      the eigen-solver takes at most 512);
+    * Sec. 4.2: 32 x 32 x 3 x 50000 and 32 x 32 x 3 x 72 x 100, rTR-SVD and rTR-ALS with time,
+      RSE and compression ratio (entries / parameters);
+    * Sec. 4.3: 200 x 200 x 80 with K = 100 x 100 x 6 at four noise levels, the RSE against
+      the noisy input and against the clean signal.
+    Times are wall clock per call with the device drained (BF16 sketch path, FP64 TR-ALS).
+    TR-SVD ranks are capped at 32 (the back-projection's rank limit); "capped" reports whether
+    a cap was hit (the eps bound then no longer holds)."""
+    import torch
+    import workloads as W
+    from paper_1901_01652_amd import pipeline
+    dev = "cuda:0"
+    out = {}
+
+    def params(dims, R):
+        N = len(dims)
+        return sum(R[n] * dims[n] * R[(n + 1) % N] for n in range(N))
+
+    # --- Sec. 4.1 --------------------------------------------------------------------
+    w0 = W.rgb_shaped(I, Ks[0])
+    X, _ = W.make_tensor(w0, device=dev, dtype=torch.float32)
+    sweep = []
+    for K in Ks:
+        w = W.rgb_shaped(I, K)
+        Z0 = rt.pack(W.make_init(w), dev)
+        run = lambda: pipeline.rtr_als(h, X, w.K, w.ranks, Z0, w.sweeps, 0, w.seed, compute="bf16")
+        run()
+        ms, o = _clock(run)
+        rse_als = pipeline.rse(h, X, w.ranks, o["G"])
+        runs = lambda: pipeline.rtr_svd(h, X, w.K, [32] * 3, 0.15, 0, w.seed, compute="bf16")
+        runs()
+        ms_s, os_ = _clock(runs)
+        capped = bool(rt.rtr_status_sync(h) & rt.RTR_STATUS_RANK_CAPPED)
+        rse_svd = pipeline.rse(h, X, os_["ranks"], os_["G"])
+        sweep.append({"K": K, "rtr_als_ms": round(ms, 2), "rtr_als_rse": round(rse_als, 5),
+                      "rtr_svd_ms": round(ms_s, 2), "rtr_svd_rse": round(rse_svd, 5),
+                      "rtr_svd_ranks": os_["ranks"], "capped": capped})
+        log(f"[bench] {w.name}: rTR-ALS {ms:.1f} ms RSE {rse_als:.4f}; rTR-SVD {ms_s:.1f} ms "
+            f"RSE {rse_svd:.4f} ranks {os_['ranks']}")
+    wf = W.rgb_shaped(I, I)
+    Zf = W.init_cores(wf.seed, wf.dims, wf.ranks)
+    ms_f, of = _clock(lambda: pipeline.tr_als_full(h, X, wf.ranks, Zf, wf.sweeps))
+    rse_f = float(of["err_trace"][int(of["sweeps_run"].item()) - 1])
+    log(f"[bench] TR-ALS on the full {I}x{I}x3 tensor: {ms_f:.1f} ms RSE {rse_f:.4f}")
+    del X
+    # TR-SVD pair at 512 x 512 x 3 (the full tensor's first Gram is 512 x 512)
+    w5 = W.rgb_shaped(512, 100)
+    X5, _ = W.make_tensor(w5, device=dev, dtype=torch.float32)
+    pipeline.rtr_svd(h, X5, w5.K, [32] * 3, 0.15, 0, w5.seed, compute="bf16")
+    ms_r5, or5 = _clock(lambda: pipeline.rtr_svd(h, X5, w5.K, [32] * 3, 0.15, 0, w5.seed, compute="bf16"))
+    ms_s5, os5 = _clock(lambda: pipeline.tr_svd_full(h, X5, [32] * 3, 0.15))
+    svd_pair = {"dims": w5.dims, "K": w5.K,
+                "rtr_svd_ms": round(ms_r5, 2), "rtr_svd_rse": round(pipeline.rse(h, X5, or5["ranks"], or5["G"]), 5),
+                "rtr_svd_ranks": or5["ranks"], "tr_svd_ms": round(ms_s5, 2),
+                "tr_svd_rse": round(float(os5["p_err"].cpu()[0]), 5), "tr_svd_ranks": os5["ranks"]}
+    log(f"[bench] 512x512x3: rTR-SVD {ms_r5:.1f} ms, TR-SVD on the full tensor {ms_s5:.1f} ms")
+    del X5
+    out["sec4_1_simulation"] = {
+        "workload": f"smooth {I}x{I}x3 fp32 (rank-12 generator, sigma 8, [0,1], 30 dB); rank 10, "
+                    "50 sweeps; eps 0.15", "k_sweep": sweep,
+        "tr_als_full": {"ms": round(ms_f, 2), "rse": round(rse_f, 5)}, "tr_svd_pair_512": svd_pair}
+
+    # --- Sec. 4.2 --------------------------------------------------------------------
+    coll = []
+    for kind in ("cifar", "coil"):
+        w = W.images_shaped(kind)
+        X, _ = W.make_tensor(w, device=dev, dtype=torch.float32)
+        Z0 = rt.pack(W.make_init(w), dev)
+        run = lambda: pipeline.rtr_als(h, X, w.K, w.ranks, Z0, w.sweeps, 0, w.seed, compute="bf16")
+        run()
+        ms, o = _clock(run)
+        rse_als = pipeline.rse(h, X, w.ranks, o["G"])
+        caps = [32] * len(w.dims)
+        runs = lambda: pipeline.rtr_svd(h, X, w.K, caps, 0.15, 0, w.seed, compute="bf16")
+        runs()
+        ms_s, os_ = _clock(runs)
+        rse_svd = pipeline.rse(h, X, os_["ranks"], os_["G"])
+        coll.append({"workload": w.name, "K": w.K,
+                     "rtr_als": {"ranks": w.ranks, "ms": round(ms, 2), "rse": round(rse_als, 5),
+                                 "cr": round(w.numel() / params(w.dims, w.ranks), 1)},
+                     "rtr_svd": {"ranks": os_["ranks"], "ms": round(ms_s, 2), "rse": round(rse_svd, 5),
+                                 "cr": round(w.numel() / params(w.dims, os_["ranks"]), 1)}})
+        log(f"[bench] {w.name}: rTR-ALS {ms:.1f} ms RSE {rse_als:.4f}; rTR-SVD {ms_s:.1f} ms "
+            f"RSE {rse_svd:.4f} ranks {os_['ranks']}")
+        del X, o, os_
+    out["sec4_2_compression"] = coll
+
+    # --- Sec. 4.3 --------------------------------------------------------------------
+    rec = []
+    for snr in (None, 20.0, 10.0, 0.0):
+        w = W.hsi_small_shaped(snr)
+        clean = []
+        X, _ = W.make_tensor(w, device=dev, dtype=torch.float32, clean=clean)
+        S = clean[0]
+        Z0 = rt.pack(W.make_init(w), dev)
+        run = lambda: pipeline.rtr_als(h, X, w.K, w.ranks, Z0, w.sweeps, 0, w.seed, compute="bf16")
+        run()
+        ms, o = _clock(run)
+        rec.append({"snr_db": snr, "ms": round(ms, 2),
+                    "rse_vs_input": round(pipeline.rse(h, X, w.ranks, o["G"]), 5),
+                    "rse_vs_clean": round(pipeline.rse(h, S, w.ranks, o["G"]), 5)})
+        log(f"[bench] {w.name}: {ms:.1f} ms, RSE vs clean {rec[-1]['rse_vs_clean']}")
+        del X, S
+    out["sec4_3_reconstruction"] = {"workload": "200x200x80 fp32 (rank-10 generator, sigma 2, [0,1]); "
+                                                "K=100x100x6, rank 10, 30 sweeps", "runs": rec}
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_tr_svd(rt, h, P, eps=0.15, reps=3):
     """rTR-SVD (Alg. 1 step 9 by TR-SVD) on the projected tensor of the same run."""
     import torch
@@ -292,6 +518,12 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true",
                     help="skip the learned warm-start measurement")
     ap.add_argument("--no-tr-svd", action="store_true", help="skip the TR-SVD timing")
+    ap.add_argument("--no-hsi", action="store_true",
+                    help="skip the hyperspectral-shaped 1024x1024x256 workload")
+    ap.add_argument("--no-kr", action="store_true",
+                    help="skip the Khatri-Rao projection variant on the dense tensor")
+    ap.add_argument("--no-paper-shapes", action="store_true",
+                    help="skip the stand-ins for the paper's experiments (Sec. 4)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -406,6 +638,11 @@ def main():
     pn2 = float(out["p_norm2"].item())
     rse_py = float(np.sqrt(max(res[1] - pn2 + e * e * pn2, 0.0) / res[1]))
 
+    kr = None
+    if not args.no_kr:
+        log("[bench] Khatri-Rao test matrices (one read of X for every mode's sketch)")
+        kr = bench_kr(rt, h, X, w)
+
     fp32 = None
     if not args.no_fp32_compare and args.compute != "f32":
         log("[bench] plain FP32 path for comparison")
@@ -417,6 +654,12 @@ def main():
     if not args.no_tr_svd:
         log("[bench] TR-SVD on the projected tensor")
         svd = bench_tr_svd(rt, h, out["P"])
+    hsi = None
+    if not args.no_hsi:
+        hsi = bench_hsi(rt, h)
+    paper = None
+    if not args.no_paper_shapes:
+        paper = bench_paper_shapes(rt, h)
     batched = None
     if not args.no_batched:
         del out
@@ -450,7 +693,8 @@ def main():
                          "note": "one extra pass over X (timed apart from the step)"},
         "roofline": roof, "stages": stages, "read_peak": read_peak, "kernels": kern,
         "fp32_path": fp32, "cpu_baseline": cpu,
-        "tr_svd": svd, "batched": batched, "warm_start": warm,
+        "tr_svd": svd, "khatri_rao": kr, "hsi_shaped": hsi, "paper_shapes": paper, "batched": batched,
+        "warm_start": warm,
     }
     h.close()
     print(json.dumps(line), flush=True)

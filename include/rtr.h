@@ -31,8 +31,12 @@
  *   ``compute`` argument picks the arithmetic of the passes over X: RTR_F64 (X FP64),
  *   RTR_F32 (X FP32, FP32 products and accumulation), RTR_BF16 (X FP32 rounded to bf16 on
  *   load, bf16 products on the matrix cores, FP32 accumulation; the compression adds the
- *   FP32 refinement terms X_hi Q_lo + X_lo Q_hi).  QR, power-iteration orthonormalisation
- *   and the ALS normal-equation solves are always FP64.
+ *   FP32 refinement terms X_hi Q_lo + X_lo Q_hi), RTR_FP8_E4M3 (the sketch products with X
+ *   and M rounded to OCP e4m3, values clamped to +-448 first, on the fp8 matrix cores with
+ *   FP32 accumulation; power steps and the compression then run as for RTR_BF16; meant for
+ *   data within the e4m3 range, |x| <= 448, which the caller can reach by scaling X since
+ *   Q_n does not depend on the scale).  QR, power-iteration orthonormalisation and the ALS
+ *   normal-equation solves are always FP64.
  * - Random numbers: the Gaussian matrix of Alg. 1 step 4 is never stored.  Entry (j, k)
  *   of M_n is element e = j*K'_n + k of the Philox4x32-10 stream with key (seed mod 2^32,
  *   seed >> 32) and counter (e>>2 low word, e>>2 high word, 0x01000000 | n << 16,
@@ -86,7 +90,7 @@ typedef enum {
   RTR_ERR_INTERNAL = 6
 } rtr_status;
 
-typedef enum { RTR_F64 = 0, RTR_F32 = 1, RTR_BF16 = 2 } rtr_dtype;
+typedef enum { RTR_F64 = 0, RTR_F32 = 1, RTR_BF16 = 2, RTR_FP8_E4M3 = 3 } rtr_dtype;
 
 typedef enum { RTR_METHOD_ALS = 0, RTR_METHOD_SVD = 1 } rtr_method;
 
@@ -124,11 +128,55 @@ const char* rtr_status_string(rtr_status s);
  *   Q          device, FP64, packed Q_n (I_n x K'_n, orthonormal columns, R_ii >= 0)
  * Y_n is formed from the original X for every mode.  With power_iters = q the result is
  * qr((X_(n) X_(n)^T)^q X_(n) M_n); each round re-orthonormalises once in FP64.
+ * Limits: projected modes take K_n <= 256 with RTR_F32 / RTR_BF16 and K_n <= 64 with RTR_F64
+ * (RTR_ERR_UNSUPPORTED otherwise); with power_iters > 0 a mode longer than 256 needs
+ * I_n K_n <= 8192.
  */
 rtr_status rtr_sketch(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
                       const int64_t* dims, const int32_t* K, int32_t power_iters,
                       uint64_t seed, uint32_t tensor_id, rtr_dtype compute, double* Q,
                       void* stream);
+
+/*
+ * rtr_sketch with a structured test matrix (the remark after Alg. 1 names structured
+ * projections as an option): M_n is the Khatri-Rao (column-wise Kronecker) product of one
+ * Gaussian factor F_m (I_m x K_n) per other mode m, so row j of M_n, j the row-major index of
+ * the other modes' indices (first other mode slowest), is prod_{m != n} F_m[i_m, :].  F_m is
+ * elements [0, I_m K_n) of Gaussian stream (seed, 0x03000000 | n << 16 | m << 8, tensor_id),
+ * row-major; only sum_{m != n} I_m K_n normals are drawn per mode instead of
+ * prod_{m != n} I_m K_n.  Arguments, limits, errors and the power iterations as rtr_sketch; the
+ * factors take workspace of sum_{m != n} I_m K_n FP32 (FP64 for RTR_F64) values.
+ * With RTR_BF16, order >= 3, the last two modes projected, 16 <= I_{N-1}, I_N <= 256,
+ * I_N % 4 == 0, every K'_n <= 32, at least 256 slabs (prod_{m < N-1} I_m) and X 16-byte aligned,
+ * the sketches of ALL modes come from one read of X: a slab S of the last two modes contributes
+ * to mode n (one of the first N-2) the column sums of F^(n)_{N-1} o (S F^(n)_N) scaled by the
+ * slab's factor entries, and to the last two modes S F and S^T F likewise.  Otherwise one pass
+ * per mode as rtr_sketch.
+ *   x_norm2    device, 1 FP64 (may be NULL): ||X||_F^2, formed inside that single pass (an
+ *              extra pass over X otherwise)
+ */
+rtr_status rtr_sketch_kr(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
+                         const int64_t* dims, const int32_t* K, int32_t power_iters,
+                         uint64_t seed, uint32_t tensor_id, rtr_dtype compute, double* Q,
+                         double* x_norm2, void* stream);
+
+/*
+ * Alg. 1 steps 3-8 with step 7 read sequentially: for n = 1..N the sketch of mode n is taken
+ * of P^(n-1) = X x_1 Q_1^T .. x_{n-1} Q_{n-1}^T (its Gaussian M_n has prod_{i<n} K'_i
+ * prod_{i>n} I_i rows, stream as for rtr_sketch), Q_n = qr(P^(n-1)_(n) M_n) with R_ii >= 0, and
+ * P^(n) = P^(n-1) x_n Q_n^T; P = P^(N).  The first projected mode reads X in ``compute``
+ * arithmetic, later modes read the FP64 intermediate in FP64.  No power iterations.
+ *   X, x_dtype, order, dims, K, seed, tensor_id, compute   as for rtr_sketch
+ *   Q          device, FP64, packed Q_n (I_n x K'_n)
+ *   P          device, FP64, row-major K'_1 x .. x K'_N
+ *   p_norm2    device, 1 FP64 (may be NULL): ||P||_F^2
+ * Limits: K'_n <= 256 for the first projected mode (FP32/BF16), <= 64 for the others and for
+ * RTR_F64 (RTR_ERR_UNSUPPORTED otherwise).
+ */
+rtr_status rtr_sketch_sequential(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
+                                 const int64_t* dims, const int32_t* K, uint64_t seed,
+                                 uint32_t tensor_id, rtr_dtype compute, double* Q, double* P,
+                                 double* p_norm2, void* stream);
 
 /*
  * rtr_sketch for callers that cannot allocate device memory: code under HIP graph capture,
@@ -154,6 +202,7 @@ rtr_status rtr_sketch_noalloc(rtr_handle h, const void* X, rtr_dtype x_dtype, in
  *   Q          device, FP64, packed Q_n from rtr_sketch
  *   P          device, FP64, row-major K'_1 x .. x K'_N
  *   p_norm2    device, 1 FP64 (may be NULL): ||P||_F^2
+ * Limits: K'_n <= 256.
  */
 rtr_status rtr_compress(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
                         const int64_t* dims, const int32_t* K, const double* Q,
@@ -184,6 +233,8 @@ typedef struct {
  * entries use an FP64 Cholesky factorisation instead).  A Gram matrix that is not positive
  * definite (a non-positive pivot) sets RTR_STATUS_CHOLESKY_FAILED and leaves that core
  * unchanged.
+ * Limits: K'_n <= 1024 and R_n R_{n+1} <= 256 (RTR_ERR_UNSUPPORTED otherwise).  With K'_n = I_n
+ * (P = X in FP64) this is plain TR-ALS on the full tensor.
  * RTR_METHOD_SVD is rejected with RTR_ERR_INVALID_ARG: TR-SVD chooses the ranks, so it has
  * its own entry point, rtr_decompose_svd.
  */
@@ -253,8 +304,10 @@ rtr_status rtr_decompose_batch(rtr_handle h, const rtr_als_item* items, int32_t 
                                int32_t max_sweeps, double tol, void* stream);
 
 /*
- * Alg. 1 steps 3-12 for a batch of tensors: per-tensor sketch (rtr_sketch) and compression
- * (rtr_compress), one batched TR-ALS launch (rtr_decompose_batch), per-tensor back-projection
+ * Alg. 1 steps 3-12 for a batch of tensors: the sketch and compression of every tensor
+ * (rtr_sketch and rtr_compress per tensor, on 8 branch streams inside a captured graph; the
+ * work-list form described at rtr_batch_autotune is switched off in this build), one batched
+ * TR-ALS launch (rtr_decompose_batch), per-tensor back-projection
  * (rtr_backproject, skipped where G is NULL).  With use_graph != 0 the whole sequence is
  * captured into a HIP graph the first time a given item array is seen (that call runs
  * eagerly) and later calls with an identical item array and parameters replay the graph
@@ -284,6 +337,27 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
                          int32_t max_sweeps, double tol, int32_t use_graph, void* stream);
 
 /*
+ * Tile choice for the batched work lists of rtr_batch_run (FP32 X, no power iterations, every
+ * K'_n <= 64): there the sketches of every (tensor, mode) run as one launch over a job list,
+ * their sums as one, every QR as one, and each mode product of the compression (Eq. 3, mode 1
+ * first) for every tensor as one launch per mode.  This call times the candidates on the given
+ * batch (HIP events, the mean of three runs after one untimed run): 16, 64 or 256 column-tile
+ * chunks per sketch job, then 4, 16 or 64 outputs per thread of the mode products, keeps the
+ * fastest pair in the handle for later rtr_batch_run calls, and writes the table
+ *   table[0] chunks per sketch job, table[1] outputs per thread,
+ *   table[2..4] sketch microseconds for 16 / 64 / 256, table[5..7] mode-product microseconds
+ *   for 4 / 16 / 64
+ * (host, 8 int32).  The outputs Q and P of the items are overwritten while timing.
+ * RTR_ERR_UNSUPPORTED when the batch does not take the work lists.  The work lists are switched
+ * off in this build (this call returns RTR_ERR_UNSUPPORTED and rtr_batch_run takes the
+ * per-tensor path): a graph-captured batch run that used them ended with a GPU memory fault
+ * whose cause has not been shown yet.
+ */
+rtr_status rtr_batch_autotune(rtr_handle h, const rtr_batch_item* items, int32_t count,
+                              rtr_dtype x_dtype, rtr_dtype compute, int32_t* table,
+                              void* stream);
+
+/*
  * Learned warm start for TR-ALS (an initialisation of Alg. 1 step 9): a multilayer
  * perceptron maps the normalised projected tensor P~ = P / ||P|| (row-major, flattened) to
  * the packed initial cores (R_n, K'_n, R_{n+1}).  Hidden layers h_l = relu(h_{l-1} W_l + b_l),
@@ -302,6 +376,14 @@ rtr_status rtr_mlp_forward(rtr_handle h, int32_t layers, const int32_t* sizes,
                            const float* const* W, const float* const* b, const float* x,
                            int32_t batch, float* const* acts, float* y, rtr_dtype compute,
                            void* stream);
+/* Supervised core loss per sample: loss[s] = ||y[s] - target[s]||^2 over the per_row packed
+ * core entries, dy[s] = grad_scale * 2 (y[s] - target[s]).  The targets are cores the method
+ * itself produced (TR-ALS on the normalised projected tensor from one fixed initial set of
+ * cores, so the targets share one gauge).  y, target, dy: device batch x per_row FP32; loss:
+ * device batch FP32. */
+rtr_status rtr_mlp_core_loss(rtr_handle h, const float* y, const float* target, int32_t batch,
+                             int64_t per_row, float grad_scale, float* loss, float* dy,
+                             void* stream);
 /* Order-4 TR loss per sample: loss[s] = ||target[s] - Psi(cores in y[s])||^2 and
  * dy[s] = grad_scale * d loss[s] / d y[s] (K, R: 4 entries, R_n <= 8). */
 rtr_status rtr_mlp_tr_loss(rtr_handle h, const float* y, const float* target, int32_t batch,

@@ -93,6 +93,13 @@ def backward(params, x, P, K, R):
         D = tr_full(cores) - Pn[s].reshape(shape)
         gc = _psi_grad_cores(cores, 2.0 * D / B)
         dy[s] = np.concatenate([g.reshape(-1) for g in gc])
+    return backprop(params, acts, dy)
+
+
+def backprop(params, acts, dy):
+    """The layer-by-layer gradients given the layer inputs ``acts`` (acts[0] = x, acts[l] the
+    ReLU output feeding layer l) and the gradient ``dy`` of the loss w.r.t. the output:
+    dW_l = acts[l]^T g_l, db_l = sum over the batch of g_l, g_{l-1} = (g_l W_l^T) * [acts[l] > 0]."""
     grads = [None] * len(params)
     g = dy
     for l in range(len(params) - 1, -1, -1):
@@ -102,6 +109,13 @@ def backward(params, x, P, K, R):
         if l > 0:
             g = (g @ W.T) * (acts[l] > 0.0)
     return grads
+
+
+def core_loss(y, T, grad_scale=1.0):
+    """Supervised loss on the packed cores: per sample ||y - T||^2, and its gradient
+    grad_scale * 2 (y - T)."""
+    D = y - T
+    return np.sum(D * D, axis=1), grad_scale * 2.0 * D
 
 
 def adam_step(w, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -251,12 +251,19 @@ def rse(X, G):
     return frob(X - tr_full(G)) / frob(X)
 
 
-def rtr_als(X, K, Z0, sweeps, q=0, seed=0, tol=0.0, tensor_id=0):
+def rtr_als(X, K, Z0, sweeps, q=0, seed=0, tol=0.0, tensor_id=0, projection="gaussian"):
     """The whole of Alg. 1 with TR-ALS.  ``Z0`` are the initial cores of shape
-    (R_n, K_n', R_{n+1}) with K_n' = min(K_n, I_n).  Returns a dict of every stage."""
+    (R_n, K_n', R_{n+1}) with K_n' = min(K_n, I_n).  ``projection``: "gaussian" (as printed),
+    "khatri_rao" (structured test matrices) or "sequential" (step 7 read sequentially, q = 0).
+    Returns a dict of every stage."""
     X = np.asarray(X, dtype=np.float64)
-    Qs = [range_basis(X, n, K[n], q, seed, tensor_id) for n in range(X.ndim)]
-    P = compress(X, Qs)
+    if projection == "sequential":
+        assert q == 0
+        Qs, P = sequential_bases(X, K, seed, tensor_id)
+    else:
+        test = "khatri_rao" if projection == "khatri_rao" else "gaussian"
+        Qs = [range_basis(X, n, K[n], q, seed, tensor_id, test) for n in range(X.ndim)]
+        P = compress(X, Qs)
     Z, trace = tr_als(P, Z0, sweeps, tol)
     G = backproject(Z, Qs)
     return {"Q": Qs, "P": P, "Z": Z, "rse_trace": trace, "G": G, "rse": rse(X, G)}

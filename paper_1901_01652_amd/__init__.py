@@ -22,14 +22,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librtr.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "rtr.h")
 
-RTR_F64, RTR_F32, RTR_BF16 = 0, 1, 2
+RTR_F64, RTR_F32, RTR_BF16, RTR_FP8_E4M3 = 0, 1, 2, 3
 RTR_METHOD_ALS, RTR_METHOD_SVD = 0, 1
 RTR_STATUS_CHOLESKY_FAILED = 0x1
 RTR_STATUS_RANK_CAPPED = 0x2
 RTR_STATUS_SYNC_TIMEOUT = 0x4
 MAX_ORDER = 8
 
-_DTYPES = {"f64": RTR_F64, "f32": RTR_F32, "bf16": RTR_BF16}
+_DTYPES = {"f64": RTR_F64, "f32": RTR_F32, "bf16": RTR_BF16, "fp8": RTR_FP8_E4M3}
 
 
 class RtrError(RuntimeError):
@@ -71,17 +71,23 @@ def _load():
         "rtr_sketch": [vp, vp, ctypes.c_int, i32, P64, P32, i32, u64, u32, ctypes.c_int, vp, vp],
         "rtr_sketch_noalloc": [vp, vp, ctypes.c_int, i32, P64, P32, i32, u64, u32, ctypes.c_int, vp,
                                vp],
+        "rtr_sketch_kr": [vp, vp, ctypes.c_int, i32, P64, P32, i32, u64, u32, ctypes.c_int, vp, vp,
+                          vp],
+        "rtr_sketch_sequential": [vp, vp, ctypes.c_int, i32, P64, P32, u64, u32, ctypes.c_int, vp,
+                                  vp, vp, vp],
         "rtr_compress": [vp, vp, ctypes.c_int, i32, P64, P32, vp, ctypes.c_int, vp, vp, vp],
         "rtr_decompose": [vp, vp, i32, P32, P32, ctypes.POINTER(_Opts), vp, vp, vp, vp, vp],
         "rtr_decompose_svd": [vp, vp, i32, P32, P32, dp, vp, vp, vp, vp],
         "rtr_decompose_batch": [vp, ctypes.POINTER(_AlsItem), i32, i32, dp, vp],
         "rtr_batch_run": [vp, ctypes.POINTER(_BatchItem), i32, ctypes.c_int, ctypes.c_int, i32, i32,
                           dp, i32, vp],
+        "rtr_batch_autotune": [vp, ctypes.POINTER(_BatchItem), i32, ctypes.c_int, ctypes.c_int, P32, vp],
         "rtr_backproject": [vp, i32, P64, P32, P32, vp, vp, vp, vp],
         "rtr_mlp_normalize": [vp, vp, i64, i32, vp, vp],
         "rtr_mlp_forward": [vp, i32, P32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, i32,
                             ctypes.POINTER(vp), vp, ctypes.c_int, vp],
         "rtr_mlp_tr_loss": [vp, vp, vp, i32, P32, P32, ctypes.c_float, vp, vp, vp],
+        "rtr_mlp_core_loss": [vp, vp, vp, i32, i64, ctypes.c_float, vp, vp, vp],
         "rtr_mlp_backward": [vp, i32, P32, ctypes.POINTER(vp), vp, i32, ctypes.POINTER(vp), vp,
                              ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp],
         "rtr_mlp_adam": [vp, vp, vp, vp, vp, i64, dp, dp, dp, dp, i32, vp],
@@ -209,17 +215,46 @@ def q_shapes(dims, K):
     return [(int(d), k) for d, k in zip(dims, keff(dims, K))]
 
 
-def rtr_sketch(h, X, K, power_iters=0, seed=0, tensor_id=0, compute=None, Q=None, stream=None):
-    """Alg. 1 steps 3-6: packed FP64 Q_n (I_n x K'_n) of tensor X (device)."""
+def rtr_sketch(h, X, K, power_iters=0, seed=0, tensor_id=0, compute=None, Q=None, stream=None,
+               projection="gaussian", x_norm2=None):
+    """Alg. 1 steps 3-6: packed FP64 Q_n (I_n x K'_n) of tensor X (device).  ``projection``
+    "khatri_rao" calls rtr_sketch_kr (structured test matrices; ``x_norm2``, a device FP64
+    scalar, then receives ||X||^2)."""
     dims = list(X.shape)
     assert X.is_contiguous()
     xd = _xdtype(X)
     cd = xd if compute is None else _DTYPES[compute]
     if Q is None:
         Q = torch.empty(q_size(dims, K), dtype=torch.float64, device=X.device)
-    h.check(lib.rtr_sketch(h.ptr, _ptr(X), xd, len(dims), _i64(dims), _i32(K), int(power_iters),
-                           int(seed), int(tensor_id), cd, _ptr(Q), _stream(stream, X.device)))
+    args = [h.ptr, _ptr(X), xd, len(dims), _i64(dims), _i32(K), int(power_iters), int(seed),
+            int(tensor_id), cd, _ptr(Q)]
+    if projection == "khatri_rao":
+        h.check(lib.rtr_sketch_kr(*args, _ptr(x_norm2) if x_norm2 is not None else None,
+                                  _stream(stream, X.device)))
+    elif projection == "gaussian":
+        assert x_norm2 is None, "||X||^2 comes with the Khatri-Rao sketch"
+        h.check(lib.rtr_sketch(*args, _stream(stream, X.device)))
+    else:
+        raise ValueError(projection)
     return Q
+
+
+def rtr_sketch_sequential(h, X, K, seed=0, tensor_id=0, compute=None, Q=None, P=None,
+                          p_norm2=None, stream=None):
+    """Alg. 1 steps 3-8 with step 7 read sequentially: returns (packed Q_n, P)."""
+    dims = list(X.shape)
+    assert X.is_contiguous()
+    xd = _xdtype(X)
+    cd = xd if compute is None else _DTYPES[compute]
+    if Q is None:
+        Q = torch.empty(q_size(dims, K), dtype=torch.float64, device=X.device)
+    if P is None:
+        P = torch.empty(keff(dims, K), dtype=torch.float64, device=X.device)
+    h.check(lib.rtr_sketch_sequential(h.ptr, _ptr(X), xd, len(dims), _i64(dims), _i32(K), int(seed),
+                                      int(tensor_id), cd, _ptr(Q), _ptr(P),
+                                      _ptr(p_norm2) if p_norm2 is not None else None,
+                                      _stream(stream, X.device)))
+    return Q, P
 
 
 def rtr_sketch_noalloc(h, X, K, Q, power_iters=0, seed=0, tensor_id=0, compute=None, stream=None):
@@ -328,15 +363,9 @@ def rtr_decompose_batch(h, items, max_sweeps, tol=0.0, stream=None):
     return items
 
 
-def rtr_batch_run(h, items, max_sweeps, compute=None, power_iters=0, tol=0.0, use_graph=False,
-                  stream=None):
-    """Alg. 1 steps 3-12 for a batch.  ``items``: dicts with X (device), K, R, Z_init (packed,
-    device), seed, tensor_id; outputs Q, P, Z, G, err_trace, sweeps_run are allocated when
-    missing (keep the dicts to replay the same batch as a graph)."""
+def _batch_items(items, max_sweeps):
     arr = (_BatchItem * len(items))()
     xdt = _xdtype(items[0]["X"])
-    if compute is None:
-        compute = "f64" if xdt == RTR_F64 else "f32"
     for t, it in enumerate(items):
         X = it["X"]
         dev = X.device
@@ -357,10 +386,39 @@ def rtr_batch_run(h, items, max_sweeps, compute=None, power_iters=0, tol=0.0, us
         a.Z_init = it["Z_init"].data_ptr()
         for name in ("Q", "P", "Z", "G", "err_trace", "sweeps_run"):
             setattr(a, name, it[name].data_ptr() if it[name] is not None else None)
+    return arr, xdt
+
+
+def rtr_batch_run(h, items, max_sweeps, compute=None, power_iters=0, tol=0.0, use_graph=False,
+                  stream=None):
+    """Alg. 1 steps 3-12 for a batch.  ``items``: dicts with X (device), K, R, Z_init (packed,
+    device), seed, tensor_id; outputs Q, P, Z, G, err_trace, sweeps_run are allocated when
+    missing (keep the dicts to replay the same batch as a graph)."""
+    arr, xdt = _batch_items(items, max_sweeps)
+    if compute is None:
+        compute = "f64" if xdt == RTR_F64 else "f32"
     dev = items[0]["X"].device
     h.check(lib.rtr_batch_run(h.ptr, arr, len(items), xdt, _DTYPES[compute], int(power_iters),
                               int(max_sweeps), float(tol), int(bool(use_graph)), _stream(stream, dev)))
     return items
+
+
+def rtr_batch_autotune(h, items, compute="f32", table_path=None, stream=None):
+    """Times the batched work lists' tile candidates on ``items`` and keeps the fastest in the
+    handle; returns the table (and writes it as JSON to ``table_path`` when given)."""
+    arr, xdt = _batch_items(items, 1)
+    tab = (ctypes.c_int32 * 8)()
+    dev = items[0]["X"].device
+    h.check(lib.rtr_batch_autotune(h.ptr, arr, len(items), xdt, _DTYPES[compute], tab,
+                                   _stream(stream, dev)))
+    table = {"sketch_chunks_per_job": tab[0], "ttm_outputs_per_thread": tab[1],
+             "sketch_us": {"16": tab[2], "64": tab[3], "256": tab[4]},
+             "ttm_us": {"4": tab[5], "16": tab[6], "64": tab[7]}}
+    if table_path:
+        import json
+        with open(table_path, "w") as f:
+            json.dump(table, f, indent=1)
+    return table
 
 
 def _ptrs(ts):
@@ -387,6 +445,18 @@ def rtr_mlp_forward(h, W, b, x, acts=None, y=None, compute="bf16", stream=None):
     h.check(lib.rtr_mlp_forward(h.ptr, len(W), _i32(sizes), _ptrs(W), _ptrs(b), _ptr(x), B,
                                 _ptrs(acts), _ptr(y), _DTYPES[compute], _stream(stream, x.device)))
     return y, acts
+
+
+def rtr_mlp_core_loss(h, y, target, grad_scale, loss=None, dy=None, stream=None):
+    """Supervised loss ||y - target||^2 per sample and its gradient (times grad_scale)."""
+    B, d = y.shape
+    if loss is None:
+        loss = torch.empty(B, dtype=torch.float32, device=y.device)
+    if dy is None:
+        dy = torch.empty_like(y)
+    h.check(lib.rtr_mlp_core_loss(h.ptr, _ptr(y), _ptr(target), B, d, float(grad_scale), _ptr(loss),
+                                  _ptr(dy), _stream(stream, y.device)))
+    return loss, dy
 
 
 def rtr_mlp_tr_loss(h, y, target, K, R, grad_scale, loss=None, dy=None, stream=None):

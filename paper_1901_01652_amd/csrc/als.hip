@@ -95,13 +95,13 @@ hipError_t launch_chain(const Chain& ch, int64_t count, int transpose, double* o
 
 // ---------------------------------------------------------------------------------------
 constexpr int kAlsTJ = 16;
-constexpr int kAlsAcc = 64;  // outputs per thread: Kn*RR + RR*RR <= 256*64
+constexpr int kAlsAcc = 64;  // outputs per thread
 constexpr int kAlsThreads = 256;
+// outputs per work-group: the Kn*RR + RR*RR outputs are split into blocks of this many along
+// the grid's second dimension
+constexpr int kAlsOutBlk = kAlsThreads * kAlsAcc;
 
-bool als_supported(int Kn, int RR) {
-  return (int64_t)Kn * RR + (int64_t)RR * RR <= (int64_t)kAlsThreads * kAlsAcc &&
-         RR <= 256 && Kn <= 1024;
-}
+bool als_supported(int Kn, int RR) { return RR <= 256 && Kn <= 1024; }
 
 int64_t als_chunks(const AlsGeom& g) {
   const int64_t ntiles = (g.J + kAlsTJ - 1) / kAlsTJ;
@@ -130,6 +130,10 @@ __global__ __launch_bounds__(kAlsThreads) void als_partial_kernel(
   const int RR = g.RR, Kn = g.Kn;
   const int nM = Kn * RR;
   const int nout = nM + RR * RR;
+  const int ob = blockIdx.y * kAlsOutBlk;  // first output of this work-group's block
+  // rows of P_<n> that the block's M outputs touch
+  const int irow0 = min(ob, nM) / RR;
+  const int irow1 = (min(ob + kAlsOutBlk, nM) + RR - 1) / RR;
   double acc[kAlsAcc];
 #pragma unroll
   for (int q = 0; q < kAlsAcc; ++q) acc[q] = 0.0;
@@ -153,7 +157,7 @@ __global__ __launch_bounds__(kAlsThreads) void als_partial_kernel(
     // Gram part (rows of P not needed)
 #pragma unroll
     for (int q = 0; q < kAlsAcc; ++q) {
-      const int o = threadIdx.x + q * kAlsThreads;
+      const int o = ob + threadIdx.x + q * kAlsThreads;
       if (o >= nM && o < nout) {
         const int oo = o - nM;
         const int r1 = oo / RR, r2 = oo % RR;
@@ -163,8 +167,8 @@ __global__ __launch_bounds__(kAlsThreads) void als_partial_kernel(
       }
     }
     // M part, slabs of rows of P_<n>
-    for (int i0 = 0; i0 < Kn; i0 += kPsRows) {
-      const int rows = min(kPsRows, Kn - i0);
+    for (int i0 = irow0; i0 < irow1; i0 += kPsRows) {
+      const int rows = min(kPsRows, irow1 - i0);
       __syncthreads();
       for (int x = threadIdx.x; x < rows * kAlsTJ; x += kAlsThreads) {
         const int ii = x / kAlsTJ, jj = x % kAlsTJ;
@@ -174,7 +178,7 @@ __global__ __launch_bounds__(kAlsThreads) void als_partial_kernel(
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < kAlsAcc; ++q) {
-        const int o = threadIdx.x + q * kAlsThreads;
+        const int o = ob + threadIdx.x + q * kAlsThreads;
         if (o < nM) {
           const int i = o / RR, r = o % RR;
           if (i >= i0 && i < i0 + rows) {
@@ -189,8 +193,8 @@ __global__ __launch_bounds__(kAlsThreads) void als_partial_kernel(
   }
 #pragma unroll
   for (int q = 0; q < kAlsAcc; ++q) {
-    const int o = threadIdx.x + q * kAlsThreads;
-    if (o < nout) part[(int64_t)blockIdx.x * nout + o] = acc[q];
+    const int o = ob + threadIdx.x + q * kAlsThreads;
+    if (o < nout && o < ob + kAlsOutBlk) part[(int64_t)blockIdx.x * nout + o] = acc[q];
   }
 }
 
@@ -198,9 +202,11 @@ hipError_t launch_als_partial(const double* P, const AlsGeom& g, const double* B
                               double* part, int64_t chunks, const int* done, hipStream_t s) {
   const int64_t ntiles = (g.J + kAlsTJ - 1) / kAlsTJ;
   const int64_t per = (ntiles + chunks - 1) / chunks;
+  const int nout = g.Kn * g.RR + g.RR * g.RR;
+  const unsigned oblocks = (unsigned)((nout + kAlsOutBlk - 1) / kAlsOutBlk);
   prof_begin("als_partial", s);
-  hipLaunchKernelGGL(als_partial_kernel, dim3((unsigned)chunks), dim3(kAlsThreads), 0, s, P, g,
-                     Bm, per, part, done);
+  hipLaunchKernelGGL(als_partial_kernel, dim3((unsigned)chunks, oblocks), dim3(kAlsThreads), 0, s,
+                     P, g, Bm, per, part, done);
   prof_end(s);
   return hipGetLastError();
 }
@@ -224,17 +230,23 @@ hipError_t launch_als_reduce(const double* part, int64_t chunks, int nout, doubl
   return hipGetLastError();
 }
 
-// MG = [M (Kn x RR) | Gram (RR x RR)].  Cholesky (right-looking, lower, in place), then
-// each thread solves L L^T w = m for one row m of M and writes row i of the new core.
+// MG = [M (Kn x RR) | Gram (RR x RR)].  Cholesky (right-looking, lower), then each thread
+// solves L L^T w = m for one row m of M and writes row i of the new core.  With in_lds every
+// work-group factors its own copy of the Gram in LDS and solves rows blockIdx.x,
+// blockIdx.x + gridDim.x, ..; otherwise one work-group factors it in place in MG.
 __global__ __launch_bounds__(256) void als_solve_kernel(double* __restrict__ MG, AlsGeom g,
                                                         double* __restrict__ Zn,
                                                         unsigned* __restrict__ status,
-                                                        const int* __restrict__ done) {
+                                                        const int* __restrict__ done,
+                                                        int in_lds) {
   if (*done) return;
+  extern __shared__ double sm_g[];
   __shared__ int failed;
   const int RR = g.RR, Kn = g.Kn;
   double* M = MG;
-  double* G = MG + (int64_t)Kn * RR;
+  double* G = in_lds ? sm_g : MG + (int64_t)Kn * RR;
+  if (in_lds)
+    for (int x = threadIdx.x; x < RR * RR; x += blockDim.x) G[x] = MG[(int64_t)Kn * RR + x];
   if (threadIdx.x == 0) failed = 0;
   __syncthreads();
   for (int j = 0; j < RR; ++j) {
@@ -258,10 +270,10 @@ __global__ __launch_bounds__(256) void als_solve_kernel(double* __restrict__ MG,
     __syncthreads();
   }
   if (failed) {
-    if (threadIdx.x == 0) atomicOr(status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr(status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
     return;
   }
-  for (int i = threadIdx.x; i < Kn; i += blockDim.x) {
+  for (int i = blockIdx.x + gridDim.x * threadIdx.x; i < Kn; i += gridDim.x * blockDim.x) {
     double* m = M + (int64_t)i * RR;  // overwritten by the solution
     for (int r = 0; r < RR; ++r) {    // L y = m
       double s = m[r];
@@ -280,8 +292,18 @@ __global__ __launch_bounds__(256) void als_solve_kernel(double* __restrict__ MG,
 
 hipError_t launch_als_solve(double* MG, const AlsGeom& g, double* Zn, unsigned* status,
                             const int* done, hipStream_t s) {
+  // Gram in LDS up to 96 KB (R_n R_{n+1} <= 110); then one work-group per 256 rows of the core
+  const size_t lds = (size_t)g.RR * g.RR * sizeof(double);
+  const int in_lds = lds <= 96 * 1024 ? 1 : 0;
+  const unsigned grid = in_lds ? (unsigned)((g.Kn + 255) / 256) : 1u;
+  if (in_lds) {
+    const hipError_t e = hipFuncSetAttribute((const void*)als_solve_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   prof_begin("als_solve", s);
-  hipLaunchKernelGGL(als_solve_kernel, dim3(1), dim3(256), 0, s, MG, g, Zn, status, done);
+  hipLaunchKernelGGL(als_solve_kernel, dim3(grid), dim3(256), in_lds ? lds : 0, s, MG, g, Zn,
+                     status, done, in_lds);
   prof_end(s);
   return hipGetLastError();
 }

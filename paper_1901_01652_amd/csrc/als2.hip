@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kSolveThreads) void als_solve2_kernel(AlsSolveArgs 
   double* G = sm + nM;          // RR x RR, lower Cholesky factor in place
   double* invd = G + RR * RR;   // RR
   double* cvec = invd + RR;     // 64
-  double* xt = cvec + 64 + 1024;  // transfer-matrix workspace / Gauss-Jordan solution
+  double* xt = cvec + 64 + 1024;  // transfer-matrix workspace
   __shared__ double red[16];
   __shared__ int failed;
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -412,19 +412,18 @@ __global__ __launch_bounds__(kSolveThreads) void als_solve2_kernel(AlsSolveArgs 
   }
   __syncthreads();
   if constexpr (RMAX > 0) {
-    // RMAX here is the number of augmented-matrix elements per thread
-    double* X = xt;                 // RR x Kn solution, reuses the transfer workspace
+    // RMAX here is the number of augmented-matrix elements per thread; the solution entry
+    // (r = a R_{n+1} + b, i) is core entry (a, i, b), written straight to the core
     double* rowbuf = cvec + 64;     // 2 x 256
     double* colbuf = rowbuf + 512;  // 2 x 256
-    if (!gauss_jordan<RMAX>(G, M, X, rowbuf, colbuf, RR, Kn, &failed)) {
+    double* Zn = g.Zn;
+    const int Rb = g.Rb;
+    auto store = [=](int r, int i, double v) {
+      Zn[((int64_t)(r / Rb) * Kn + i) * Rb + (r % Rb)] = v;
+    };
+    if (!gauss_jordan<RMAX>(G, M, store, rowbuf, colbuf, RR, Kn, &failed)) {
       if (tid == 0) atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
       return;
-    }
-    __syncthreads();
-    for (int x = tid; x < nM; x += nth) {
-      const int i = x / RR, r = x % RR;
-      const int a = r / g.Rb, b = r % g.Rb;
-      g.Zn[((int64_t)a * Kn + i) * g.Rb + b] = X[r * Kn + i];
     }
     return;
   } else {
@@ -491,8 +490,8 @@ static int accum_tj(int Kn, int RR, int64_t ztotal) {
 
 static size_t solve_lds(int Kn, int RR, int gram_direct, int tdim, int64_t ztotal) {
   int64_t w = (int64_t)Kn * RR + (int64_t)RR * RR + RR + 64 + 1024;  // + row/column buffers
-  int64_t xt = (int64_t)RR * Kn;                                      // Gauss-Jordan solution
-  if (!gram_direct) xt = std::max(xt, 3 * (int64_t)tdim * tdim + 64 * (int64_t)tdim + ztotal);
+  // the transfer-matrix workspace (the Gauss-Jordan solution goes straight to the core)
+  const int64_t xt = gram_direct ? 0 : 3 * (int64_t)tdim * tdim + 64 * (int64_t)tdim + ztotal;
   return (size_t)(w + xt) * 8;
 }
 
@@ -511,6 +510,7 @@ bool als2_supported(int Kn, int RR, int64_t J, int64_t ztotal, int gram_direct, 
 // Number of partial records the accumulation writes (its grid).
 int64_t als2_parts(int Kn, int RR, int64_t J, int64_t ztotal) {
   const int tj = accum_tj(Kn, RR, ztotal);
+  if (tj == 0) return 0;  // shape not taken by this path
   const int64_t ntiles = (J + tj - 1) / tj;
   const int64_t grid = ntiles < 64 ? ntiles : 64;
   const int64_t per = (ntiles + grid - 1) / grid;

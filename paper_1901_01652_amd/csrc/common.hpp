@@ -106,4 +106,19 @@ __device__ T block_sum(T v, T* scratch) {
   return s;
 }
 
+// Work lists: job j owns grid blocks [block_start[j], block_start[j + 1]); the job of block b
+// by binary search (block_start ascending, block_start[0] = 0).
+__device__ __forceinline__ int find_job(const int64_t* __restrict__ block_start, int njobs,
+                                        int64_t b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (block_start[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 }  // namespace rtr

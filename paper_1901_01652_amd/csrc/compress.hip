@@ -13,17 +13,16 @@
 
 namespace rtr {
 
-constexpr int kTtmKMax = 64;
+constexpr int kTtmKMax = 64;   // outputs per thread at most; larger K spreads over threads
+constexpr int kTtmKLimit = 1024;
 
 // KC: outputs k per thread; thread (p, ks) owns fiber p = (a, b) and k in [ks KC, ks KC + KC),
 // so short products with few fibers still spread over enough threads.
 template <int AR, typename Tin, int KC>
-__global__ __launch_bounds__(256) void ttm_kernel(const Tin* __restrict__ in, int64_t A,
-                                                  int64_t In, int64_t B, int K,
-                                                  const double* __restrict__ Q,
-                                                  double* __restrict__ out) {
+__device__ __forceinline__ void ttm_thread(const Tin* __restrict__ in, int64_t A, int64_t In,
+                                           int64_t B, int K, const double* __restrict__ Q,
+                                           double* __restrict__ out, int64_t g) {
   using Acc = typename std::conditional<AR == kF64, double, float>::type;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nfib = A * B;
   const int64_t p = g % nfib;
   const int k0 = (int)(g / nfib) * KC;
@@ -62,6 +61,55 @@ __global__ __launch_bounds__(256) void ttm_kernel(const Tin* __restrict__ in, in
     if (k < kn) dst[(int64_t)(k0 + k) * B] = (double)acc[k];
 }
 
+template <int AR, typename Tin, int KC>
+__global__ __launch_bounds__(256) void ttm_kernel(const Tin* __restrict__ in, int64_t A,
+                                                  int64_t In, int64_t B, int K,
+                                                  const double* __restrict__ Q,
+                                                  double* __restrict__ out) {
+  ttm_thread<AR, Tin, KC>(in, A, In, B, K, Q, out, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// One mode product for many tensors in one launch (the batched compression).
+template <int AR, typename Tin, int KC>
+__global__ __launch_bounds__(256) void ttm_list_kernel(const TtmJob* __restrict__ jobs,
+                                                       const int64_t* __restrict__ block_start,
+                                                       int njobs) {
+  const int j = find_job(block_start, njobs, blockIdx.x);
+  const TtmJob g = jobs[j];
+  ttm_thread<AR, Tin, KC>((const Tin*)g.in, g.A, g.In, g.B, g.K, g.Q, g.out,
+                          ((int64_t)blockIdx.x - block_start[j]) * 256 + threadIdx.x);
+}
+
+int64_t ttm_job_blocks(const TtmJob& g, int kc) {
+  return (g.A * g.B * ((g.K + kc - 1) / kc) + 255) / 256;
+}
+
+hipError_t launch_ttm_list(Arith ar, bool first, int kc, const TtmJob* jobs,
+                           const int64_t* block_start, int njobs, int64_t blocks, hipStream_t s) {
+  if (njobs < 1) return hipSuccess;
+  prof_begin(first ? "ttm_first" : "ttm", s);
+#define RTR_TTM_LIST(KC_)                                                                      \
+  if (!first || ar == kF64)                                                                    \
+    hipLaunchKernelGGL((ttm_list_kernel<kF64, double, KC_>), dim3((unsigned)blocks), dim3(256), \
+                       0, s, jobs, block_start, njobs);                                        \
+  else if (ar == kF32)                                                                         \
+    hipLaunchKernelGGL((ttm_list_kernel<kF32, float, KC_>), dim3((unsigned)blocks), dim3(256),  \
+                       0, s, jobs, block_start, njobs);                                        \
+  else                                                                                         \
+    hipLaunchKernelGGL((ttm_list_kernel<kBF16, float, KC_>), dim3((unsigned)blocks), dim3(256), \
+                       0, s, jobs, block_start, njobs);
+  if (kc == 4) {
+    RTR_TTM_LIST(4)
+  } else if (kc == 16) {
+    RTR_TTM_LIST(16)
+  } else {
+    RTR_TTM_LIST(64)
+  }
+#undef RTR_TTM_LIST
+  prof_end(s);
+  return hipGetLastError();
+}
+
 template <int KC>
 static void launch_ttm_kc(Arith ar, bool first, const void* in, const ModeView& v, int K,
                           const double* Q, double* out, hipStream_t s) {
@@ -81,7 +129,7 @@ static void launch_ttm_kc(Arith ar, bool first, const void* in, const ModeView& 
 
 hipError_t launch_ttm(Arith ar, bool first, const void* in, const ModeView& v, int K,
                       const double* Q, double* out, hipStream_t s) {
-  if (K > kTtmKMax) return hipErrorInvalidValue;
+  if (K < 1 || K > kTtmKLimit) return hipErrorInvalidValue;
   const int64_t fibers = v.A * v.B;
   prof_begin(first ? "ttm_first" : "ttm", s);
   // enough threads to cover the GPU: split K when there are few fibers
@@ -121,6 +169,13 @@ __global__ __launch_bounds__(256) void sum_final_kernel(const double* __restrict
   for (int i = threadIdx.x; i < count; i += blockDim.x) s += partial[i];
   s = block_sum(s, red);
   if (threadIdx.x == 0) out[0] = s;
+}
+
+hipError_t launch_sum(const double* x, int64_t count, double* out, hipStream_t s) {
+  prof_begin("sum", s);
+  hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(256), 0, s, x, (int)count, out);
+  prof_end(s);
+  return hipGetLastError();
 }
 
 hipError_t launch_sumsq(bool f32, const void* x, int64_t n, double* partial, double* out,

@@ -1,7 +1,11 @@
 // Persistent matrix-core passes over X for one mode n (FP32 input):
 //   sketch  Y_n  += T M      (Alg. 1 steps 4-5; M drawn on the fly, never stored)
 //   power   Y'_n += T (T^T Q_n)   (one round of subspace iteration, fiber form)
-// where T is a tile of 64 consecutive columns of X_(n) with all I_n rows.
+// where T is a tile of 64 consecutive columns of X_(n) with all I_n rows.  The sketch of a mode
+// longer than 256 runs as several launches over row blocks of at most 256 rows each: rows of
+// Y_n depend only on the same rows of X_(n), and every block draws the same M (keyed by j, k).
+// Likewise a projection size above 64 runs as column blocks of at most 64: columns of Y_n (and
+// of the power step's X_(n) X_(n)^T Q_n) depend only on the same columns of M (of Q_n).
 //
 // Tiles: column j of X_(n) is (a, b) with j = a*B + b for X viewed as A x I_n x B, so a
 // tile of consecutive j is one or more contiguous runs of each row.  Three loaders:
@@ -37,8 +41,11 @@ constexpr int kFpMaxIn = 256;
 constexpr int kFpMaxK = 64;
 
 struct PassArgs {
-  const float* X;
+  const float* X;    // first element of the row block
   int64_t A, In, B, J;
+  int64_t strideA;   // elements between consecutive a (the full mode's I_n * B)
+  int Ktot, k0;      // column block [k0, k0 + K) of a projection of size Ktot
+  KrArgs kr;         // kr.f != nullptr: Khatri-Rao test matrix (FP32 factors)
   int K;
   uint64_t seed;
   uint32_t stream, tid;
@@ -49,17 +56,17 @@ struct PassArgs {
   int ldT, ldI, kI; // LDS leading dimensions, padded contraction length over i
 };
 
-template <bool BF>
+template <int PR>
 struct PassLds {
-  using T = typename Mma<BF>::T;
+  using T = typename Mma<PR>::T;
   static __host__ __device__ int mt_pad(int64_t In) { return (int)((In + 15) / 16) * 16; }
   static __host__ __device__ int kt_pad(int K) { return ((K + 15) / 16) * 16; }
 };
 
 // Layout of the dynamic LDS block (element offsets in T units, 16-byte aligned).
-template <bool BF, int OP>
+template <int PR, int OP>
 struct PassLayout {
-  using T = typename Mma<BF>::T;
+  using T = typename Mma<PR>::T;
   int oTij, oOt, oTji, oQt, total;
   __host__ __device__ PassLayout(int64_t In, int K, int ldT, int ldI) {
     const int a = 16 / (int)sizeof(T);
@@ -77,12 +84,12 @@ struct PassLayout {
 // K <= 32, 8 the rest).  With the 16-byte loader and AQ = 4 the kernel is held to 128 VGPRs
 // (4 waves per SIMD: two work-groups per CU, twice the loads in flight); the other variants
 // would spill at that cap.
-template <bool BF, int OP, int LD, int AQ>
+template <int PR, int OP, int LD, int AQ>
 __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode_pass_kernel(PassArgs p) {
-  using T = typename Mma<BF>::T;
+  using T = typename Mma<PR>::T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = (T*)smem_raw;
-  const PassLayout<BF, OP> L(p.In, p.K, p.ldT, p.ldI);
+  const PassLayout<PR, OP> L(p.In, p.K, p.ldT, p.ldI);
   T* Tij = smem + L.oTij;
   T* Ot = smem + L.oOt;  // M^T (sketch) or W^T (power), [k][j]
   T* Tji = smem + L.oTji;
@@ -91,12 +98,12 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
   const int MT = (In + 15) / 16, NT = (K + 15) / 16;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;  // 8 waves
 
-  for (int x = tid; x < L.total; x += kFpThreads) smem[x] = Mma<BF>::cvt(0.f);
+  for (int x = tid; x < L.total; x += kFpThreads) smem[x] = Mma<PR>::cvt(0.f);
   __syncthreads();
   if (OP == 1) {
     for (int x = tid; x < In * K; x += kFpThreads) {
       const int i = x / K, k = x % K;
-      Qt[k * ldI + i] = Mma<BF>::cvt((float)p.Q[x]);
+      Qt[k * ldI + i] = Mma<PR>::cvt((float)p.Q[(int64_t)i * p.Ktot + p.k0 + k]);
     }
   }
 
@@ -111,7 +118,7 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
       const int c4 = tid & 15;
       const int64_t j = j0 + 4 * c4;
       const bool ok = j < p.J;
-      const int64_t cb = ok ? (j / p.B) * p.In * p.B + (j % p.B) : 0;
+      const int64_t cb = ok ? (j / p.B) * p.strideA + (j % p.B) : 0;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         const int i = (tid >> 4) + 32 * s;
@@ -125,14 +132,14 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
         const int f = tid + kFpThreads * s;
         const int al = f / q4, i4 = f % q4;
         const int64_t j = j0 + al;
-        buf[s] = (al < kFpTJ && j < p.J) ? *(const float4*)(p.X + j * p.In + 4 * i4)
+        buf[s] = (al < kFpTJ && j < p.J) ? *(const float4*)(p.X + j * p.strideA + 4 * i4)
                                          : make_float4(0.f, 0.f, 0.f, 0.f);
       }
     } else {
       const int jl = tid & 63;
       const int64_t j = j0 + jl;
       const bool ok = j < p.J;
-      const int64_t cb = ok ? (j / p.B) * p.In * p.B + (j % p.B) : 0;
+      const int64_t cb = ok ? (j / p.B) * p.strideA + (j % p.B) : 0;
 #pragma unroll
       for (int s = 0; s < 32; ++s) {
         const int i = (tid >> 6) + 8 * s;
@@ -153,15 +160,15 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
         if (i < In) {
           const float4 v = buf[s];
           T* d = Tij + i * ldT + 4 * c4;
-          d[0] = Mma<BF>::cvt(v.x);
-          d[1] = Mma<BF>::cvt(v.y);
-          d[2] = Mma<BF>::cvt(v.z);
-          d[3] = Mma<BF>::cvt(v.w);
+          d[0] = Mma<PR>::cvt(v.x);
+          d[1] = Mma<PR>::cvt(v.y);
+          d[2] = Mma<PR>::cvt(v.z);
+          d[3] = Mma<PR>::cvt(v.w);
           if (OP == 1) {
-            Tji[(4 * c4 + 0) * ldI + i] = Mma<BF>::cvt(v.x);
-            Tji[(4 * c4 + 1) * ldI + i] = Mma<BF>::cvt(v.y);
-            Tji[(4 * c4 + 2) * ldI + i] = Mma<BF>::cvt(v.z);
-            Tji[(4 * c4 + 3) * ldI + i] = Mma<BF>::cvt(v.w);
+            Tji[(4 * c4 + 0) * ldI + i] = Mma<PR>::cvt(v.x);
+            Tji[(4 * c4 + 1) * ldI + i] = Mma<PR>::cvt(v.y);
+            Tji[(4 * c4 + 2) * ldI + i] = Mma<PR>::cvt(v.z);
+            Tji[(4 * c4 + 3) * ldI + i] = Mma<PR>::cvt(v.w);
           }
         }
       }
@@ -174,16 +181,16 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
         if (al < kFpTJ) {
           const float4 v = buf[s];
           const int i = 4 * i4;
-          Tij[(i + 0) * ldT + swz_col(i + 0, al)] = Mma<BF>::cvt(v.x);
-          Tij[(i + 1) * ldT + swz_col(i + 1, al)] = Mma<BF>::cvt(v.y);
-          Tij[(i + 2) * ldT + swz_col(i + 2, al)] = Mma<BF>::cvt(v.z);
-          Tij[(i + 3) * ldT + swz_col(i + 3, al)] = Mma<BF>::cvt(v.w);
+          Tij[(i + 0) * ldT + swz_col(i + 0, al)] = Mma<PR>::cvt(v.x);
+          Tij[(i + 1) * ldT + swz_col(i + 1, al)] = Mma<PR>::cvt(v.y);
+          Tij[(i + 2) * ldT + swz_col(i + 2, al)] = Mma<PR>::cvt(v.z);
+          Tij[(i + 3) * ldT + swz_col(i + 3, al)] = Mma<PR>::cvt(v.w);
           if (OP == 1) {
             T* d = Tji + al * ldI + i;
-            d[0] = Mma<BF>::cvt(v.x);
-            d[1] = Mma<BF>::cvt(v.y);
-            d[2] = Mma<BF>::cvt(v.z);
-            d[3] = Mma<BF>::cvt(v.w);
+            d[0] = Mma<PR>::cvt(v.x);
+            d[1] = Mma<PR>::cvt(v.y);
+            d[2] = Mma<PR>::cvt(v.z);
+            d[3] = Mma<PR>::cvt(v.w);
           }
         }
       }
@@ -195,9 +202,54 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
         if (i < In) {
           const float4 v4 = buf[s >> 2];
           const float v = (s & 3) == 0 ? v4.x : (s & 3) == 1 ? v4.y : (s & 3) == 2 ? v4.z : v4.w;
-          Tij[i * ldT + jl] = Mma<BF>::cvt(v);
-          if (OP == 1) Tji[jl * ldI + i] = Mma<BF>::cvt(v);
+          Tij[i * ldT + jl] = Mma<PR>::cvt(v);
+          if (OP == 1) Tji[jl * ldI + i] = Mma<PR>::cvt(v);
         }
+      }
+    }
+  };
+  // Khatri-Rao test matrix: thread (jl, g) forms column jl's factor rows once and the
+  // products for k = g, g + 8, ..
+  auto draw_kr = [&](int64_t t) {
+    const int jl = tid & 63, g = tid >> 6;
+    const int64_t j = t * kFpTJ + jl;
+    const float* F = (const float*)p.kr.f;
+    const int nm = p.kr.nm;
+    int64_t row[7];
+    int64_t r = j < p.J ? j : 0;
+#pragma unroll
+    for (int m = 6; m >= 0; --m) {
+      if (m < nm) {
+        const int d = p.kr.dim[m];
+        const int64_t i = r % d;
+        r /= d;
+        row[m] = p.kr.off[m] + i * p.kr.ld + p.k0;
+      }
+    }
+    for (int k = g; k < K; k += kFpThreads / 64) {
+      float v = 1.f;
+#pragma unroll
+      for (int m = 0; m < 7; ++m)
+        if (m < nm) v *= F[row[m] + k];
+      Ot[k * ldT + jl] = Mma<PR>::cvt(j < p.J ? v : 0.f);
+    }
+  };
+  // Column block of M for the tile's columns: row j holds stream elements
+  // [j Ktot + k0, j Ktot + k0 + K); each thread takes one Philox call of one row
+  auto draw_block = [&](int64_t t) {
+    const int64_t j0 = t * kFpTJ;
+    const int jvalid = (int)min((int64_t)kFpTJ, p.J - j0);
+    const int cpr = K / 4 + 2;  // calls that can touch one row's K elements
+    for (int x = tid; x < kFpTJ * cpr; x += kFpThreads) {
+      const int jl = x / cpr, c = x % cpr;
+      const int64_t es = (j0 + jl) * p.Ktot + p.k0;
+      const int64_t call = (es >> 2) + c;
+      float z[4];
+      normals4(p.seed, p.stream, p.tid, (uint64_t)call, z);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const int64_t k = 4 * call + l - es;
+        if (k >= 0 && k < K) Ot[k * ldT + jl] = Mma<PR>::cvt(jl < jvalid ? z[l] : 0.f);
       }
     }
   };
@@ -220,7 +272,7 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
 #pragma unroll
       for (int l = 0; l < 4; ++l) {
         if (l >= l0) {
-          if (rel + l < span) Ot[k * ldT + jl] = Mma<BF>::cvt(jl < jvalid ? z[l] : 0.f);
+          if (rel + l < span) Ot[k * ldT + jl] = Mma<PR>::cvt(jl < jvalid ? z[l] : 0.f);
           if (++k == K) {
             k = 0;
             ++jl;
@@ -239,7 +291,14 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
   if (t < p.ntiles) load(t);
   for (; t < p.ntiles; t += gridDim.x) {
     store();
-    if (OP == 0) draw(t);
+    if (OP == 0) {
+      if (p.kr.f)
+        draw_kr(t);
+      else if (p.Ktot == K)
+        draw(t);
+      else
+        draw_block(t);
+    }
     __syncthreads();
     const int64_t tn = t + gridDim.x;
     if (tn < p.ntiles) load(tn);
@@ -254,7 +313,7 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
                              f32x4{0.f, 0.f, 0.f, 0.f});
           const int col = jt * 16 + (lane & 15);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) Ot[(nt * 16 + 4 * (lane >> 4) + r) * ldT + col] = Mma<BF>::cvt(w[r]);
+          for (int r = 0; r < 4; ++r) Ot[(nt * 16 + 4 * (lane >> 4) + r) * ldT + col] = Mma<PR>::cvt(w[r]);
         }
       }
       __syncthreads();
@@ -272,13 +331,14 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
           const T* arow = Tij + r * ldT;
           const T* brow = Ot + (nt * 16 + (lane & 15)) * ldT;
           f32x4 c = acc[s];
-          if constexpr (BF) {
+          if constexpr (PR != 0) {
+            using V8 = typename Mma<PR>::V8;
 #pragma unroll
             for (int k0 = 0; k0 < kFpTJ; k0 += 32) {
               const int ca = swz_col(r, k0 + 8 * gq);
-              const bf16x8 av = *(const bf16x8*)(arow + ca);
-              const bf16x8 bv = *(const bf16x8*)(brow + k0 + 8 * gq);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+              const V8 av = *(const V8*)(arow + ca);
+              const V8 bv = *(const V8*)(brow + k0 + 8 * gq);
+              c = Mma<PR>::mma8(av, bv, c);
             }
           } else {
 #pragma unroll
@@ -310,9 +370,11 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
 }
 
 // ---------------------------------------------------------------------------------------
-static int ld_t(bool bf) { return bf ? kFpTJ + 8 : kFpTJ + 2; }
-static int k_i(bool bf, int64_t In) { return bf ? (int)((In + 31) / 32 * 32) : (int)((In + 3) / 4 * 4); }
-static int ld_i(bool bf, int64_t In) { return k_i(bf, In) + (bf ? 8 : 2); }
+// Operand precision of an arithmetic: 0 FP32, 1 bf16, 2 fp8 (e4m3).
+static int prec_of(Arith ar) { return ar == kBF16 ? 1 : ar == kFP8 ? 2 : 0; }
+static int ld_t(int pr) { return pr ? kFpTJ + 8 : kFpTJ + 2; }
+static int k_i(int pr, int64_t In) { return pr ? (int)((In + 31) / 32 * 32) : (int)((In + 3) / 4 * 4); }
+static int ld_i(int pr, int64_t In) { return k_i(pr, In) + (pr ? 8 : 2); }
 
 // Output tiles per wavefront needed for an In x K result over 8 wavefronts.
 static int acc_slots(int64_t In, int K) {
@@ -320,51 +382,83 @@ static int acc_slots(int64_t In, int K) {
   return tiles <= 32 ? 4 : 8;
 }
 
-static size_t pass_lds(bool bf, int op, int64_t In, int K) {
-  const int ldT = ld_t(bf), ldI = ld_i(bf, In);
+static size_t pass_lds(int pr, int op, int64_t In, int K) {
+  const int ldT = ld_t(pr), ldI = ld_i(pr, In);
   int total;
-  if (bf)
-    total = op ? PassLayout<true, 1>(In, K, ldT, ldI).total : PassLayout<true, 0>(In, K, ldT, ldI).total;
+  if (pr == 1)
+    total = op ? PassLayout<1, 1>(In, K, ldT, ldI).total : PassLayout<1, 0>(In, K, ldT, ldI).total;
+  else if (pr == 2)
+    total = op ? PassLayout<2, 1>(In, K, ldT, ldI).total : PassLayout<2, 0>(In, K, ldT, ldI).total;
   else
-    total = op ? PassLayout<false, 1>(In, K, ldT, ldI).total : PassLayout<false, 0>(In, K, ldT, ldI).total;
-  return (size_t)total * (bf ? 2 : 4);
+    total = op ? PassLayout<0, 1>(In, K, ldT, ldI).total : PassLayout<0, 0>(In, K, ldT, ldI).total;
+  return (size_t)total * (pr == 1 ? 2 : pr == 2 ? 1 : 4);
 }
 
 constexpr size_t kFpLdsMax = 160 * 1024;
 
-bool fast_pass_supported(Arith ar, const ModeView& v, int K, int op) {
-  if (ar == kF64) return false;
-  if (v.In > kFpMaxIn || K > kFpMaxK) return false;
-  return pass_lds(ar == kBF16, op, v.In, K) <= kFpLdsMax;
+// Widest column block (64, 48, 32 or 16, or K itself when smaller) whose LDS layout fits;
+// 0 when the pass does not take this mode.
+int fast_pass_block_k(Arith ar, const ModeView& v, int K, int op) {
+  if (ar == kF64 || K < 1 || (ar == kFP8 && op != 0)) return 0;  // fp8: the sketch only
+  int64_t rows = v.In;
+  if (v.In > kFpMaxIn) {  // the sketch in row blocks; the power step needs every row at once
+    if (op != 0) return 0;
+    rows = kFpMaxIn;
+  }
+  const int widths[4] = {kFpMaxK, 48, 32, 16};
+  for (int w : widths) {
+    const int kb = K < w ? K : w;
+    if (pass_lds(prec_of(ar), op, rows, kb) <= kFpLdsMax) return kb;
+  }
+  return 0;
 }
 
-static const void* pass_fn(bool bf, int op, int loader, int aq) {
-#define RTR_FP_SEL(B_, O_, L_) \
-  if (bf == B_ && op == O_ && loader == L_)                                        \
-    return aq == 4 ? (const void*)mode_pass_kernel<B_, O_, L_, 4>                  \
-                   : (const void*)mode_pass_kernel<B_, O_, L_, 8>;
-  RTR_FP_SEL(true, 0, 0) RTR_FP_SEL(true, 0, 1) RTR_FP_SEL(true, 0, 2)
-  RTR_FP_SEL(true, 1, 0) RTR_FP_SEL(true, 1, 1) RTR_FP_SEL(true, 1, 2)
-  RTR_FP_SEL(false, 0, 0) RTR_FP_SEL(false, 0, 1) RTR_FP_SEL(false, 0, 2)
-  RTR_FP_SEL(false, 1, 0) RTR_FP_SEL(false, 1, 1) RTR_FP_SEL(false, 1, 2)
+bool fast_pass_supported(Arith ar, const ModeView& v, int K, int op) {
+  return fast_pass_block_k(ar, v, K, op) > 0;
+}
+
+int64_t fast_pass_block_rows() { return kFpMaxIn; }
+
+static const void* pass_fn(int pr, int op, int loader, int aq) {
+#define RTR_FP_SEL(P_, O_, L_) \
+  if (pr == P_ && op == O_ && loader == L_)                                        \
+    return aq == 4 ? (const void*)mode_pass_kernel<P_, O_, L_, 4>                  \
+                   : (const void*)mode_pass_kernel<P_, O_, L_, 8>;
+  RTR_FP_SEL(1, 0, 0) RTR_FP_SEL(1, 0, 1) RTR_FP_SEL(1, 0, 2)
+  RTR_FP_SEL(1, 1, 0) RTR_FP_SEL(1, 1, 1) RTR_FP_SEL(1, 1, 2)
+  RTR_FP_SEL(0, 0, 0) RTR_FP_SEL(0, 0, 1) RTR_FP_SEL(0, 0, 2)
+  RTR_FP_SEL(0, 1, 0) RTR_FP_SEL(0, 1, 1) RTR_FP_SEL(0, 1, 2)
+  RTR_FP_SEL(2, 0, 0) RTR_FP_SEL(2, 0, 1) RTR_FP_SEL(2, 0, 2)
 #undef RTR_FP_SEL
   return nullptr;
 }
 
-static int pick_loader(const void* X, const ModeView& v) {
+// X: first element of the row block; strideA: the full mode's I_n * B.
+static int pick_loader(const void* X, const ModeView& v, int64_t strideA) {
   const bool al16 = ((uintptr_t)X & 15) == 0;
   if (al16 && v.B % 4 == 0) return 0;
-  if (al16 && v.B == 1 && v.In % 4 == 0) return 1;
+  if (al16 && v.B == 1 && v.In % 4 == 0 && strideA % 4 == 0) return 1;
   return 2;
 }
 
+// The row block [row0, row0 + rows) of X_(n) as a mode view of its own (rows = 0: all).
+static ModeView block_view(const ModeView& v, int64_t row0, int64_t rows) {
+  ModeView b = v;
+  b.In = rows > 0 ? rows : v.In - row0;
+  return b;
+}
+
 // Work-groups resident per CU (HIP occupancy query) times the CU count.
-int64_t fast_pass_grid(Arith ar, const ModeView& v, int K, int op, const void* X) {
-  const bool bf = ar == kBF16;
+int64_t fast_pass_grid(Arith ar, const ModeView& v, int K, int op, const void* X, int64_t row0,
+                       int64_t rows) {
+  const int pr = prec_of(ar);
+  const ModeView b = block_view(v, row0, rows);
   const int64_t J = v.A * v.B;
   const int64_t ntiles = (J + kFpTJ - 1) / kFpTJ;
-  const size_t lds = pass_lds(bf, op, v.In, K);
-  const void* fn = pass_fn(bf, op, pick_loader(X, v), acc_slots(v.In, K));
+  const size_t lds = pass_lds(pr, op, b.In, K);
+  const void* fn = pass_fn(pr, op, pick_loader((const float*)X + row0 * v.B, b, v.In * v.B),
+                           acc_slots(b.In, K));
+  if (!fn) return 0;
   int dev = 0, cus = 256, per_cu = 1;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -379,27 +473,37 @@ int64_t fast_pass_grid(Arith ar, const ModeView& v, int K, int op, const void* X
 
 hipError_t launch_fast_pass(Arith ar, int op, const void* X, const ModeView& v, int K,
                             uint64_t seed, uint32_t stream_word, uint32_t tensor_id,
-                            const double* Q, void* partial, int64_t grid, hipStream_t s) {
-  const bool bf = ar == kBF16;
+                            const double* Q, void* partial, int64_t grid, hipStream_t s,
+                            int64_t row0, int64_t rows, int Ktot, int k0, const KrArgs* kr) {
+  if (Ktot == 0) Ktot = K;
+  if (k0 < 0 || K < 1 || K > kFpMaxK || k0 + K > Ktot) return hipErrorInvalidValue;
+  const int pr = prec_of(ar);
+  const ModeView b = block_view(v, row0, rows);
+  if (row0 < 0 || b.In < 1 || row0 + b.In > v.In || b.In > kFpMaxIn || (op != 0 && b.In != v.In))
+    return hipErrorInvalidValue;
   PassArgs p{};
-  p.X = (const float*)X;
+  p.X = (const float*)X + row0 * v.B;
   p.A = v.A;
-  p.In = v.In;
+  p.In = b.In;
   p.B = v.B;
+  p.strideA = v.In * v.B;
   p.J = v.A * v.B;
   p.K = K;
+  p.Ktot = Ktot;
+  p.k0 = k0;
+  if (kr) p.kr = *kr;
   p.seed = seed;
   p.stream = stream_word;
   p.tid = tensor_id;
   p.Q = Q;
   p.ntiles = (p.J + kFpTJ - 1) / kFpTJ;
   p.partial = (float*)partial;
-  p.loader = pick_loader(X, v);
-  p.ldT = ld_t(bf);
-  p.ldI = ld_i(bf, v.In);
-  p.kI = k_i(bf, v.In);
-  const size_t lds = pass_lds(bf, op, v.In, K);
-  const void* fn = pass_fn(bf, op, p.loader, acc_slots(v.In, K));
+  p.loader = pick_loader(p.X, b, p.strideA);
+  p.ldT = ld_t(pr);
+  p.ldI = ld_i(pr, b.In);
+  p.kI = k_i(pr, b.In);
+  const size_t lds = pass_lds(pr, op, b.In, K);
+  const void* fn = pass_fn(pr, op, p.loader, acc_slots(b.In, K));
   if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

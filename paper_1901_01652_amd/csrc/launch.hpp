@@ -6,12 +6,29 @@
 
 namespace rtr {
 
-enum Arith { kF64 = 0, kF32 = 1, kBF16 = 2 };
+enum Arith { kF64 = 0, kF32 = 1, kBF16 = 2, kFP8 = 3 };
 
 // Stream word of the Gaussian test matrix of mode n (tag 1 in bits 24..31).
 __host__ __device__ inline uint32_t omega_stream(int n) {
   return (1u << 24) | ((uint32_t)(n & 0xFF) << 16);
 }
+
+// Stream word of the Gaussian factor of mode m in the Khatri-Rao test matrix of mode n (tag 3).
+__host__ __device__ inline uint32_t kr_stream(int n, int m) {
+  return (3u << 24) | ((uint32_t)(n & 0xFF) << 16) | ((uint32_t)(m & 0xFF) << 8);
+}
+
+// Khatri-Rao structured test matrix of one mode: row j of M (the row-major index of the other
+// modes' indices, first other mode slowest) is the element-wise product over the other modes
+// m of row i_m of their Gaussian factor F_m (I_m x ld, row-major).  f == nullptr: the plain
+// Gaussian test matrix.
+struct KrArgs {
+  const void* f;            // factor storage: FP32 for the FP32/BF16 passes, FP64 for FP64
+  int nm;                   // number of other modes (N - 1)
+  int dim[7];               // their sizes, in increasing mode order
+  int64_t off[7];           // element offset of each factor in f
+  int ld;                   // factor row length (the mode's K)
+};
 
 // X viewed for mode n as A x In x B (A = prod_{m<n} I_m, B = prod_{m>n} I_m).
 struct ModeView {
@@ -31,7 +48,7 @@ void prof_end(hipStream_t s);
 int64_t sketch_chunks(const ModeView& v, int K);
 hipError_t launch_sketch_partial(Arith ar, const void* X, const ModeView& v, int K,
                                  uint64_t seed, uint32_t stream_word, uint32_t tensor_id,
-                                 void* partial, int64_t chunks, hipStream_t s);
+                                 void* partial, int64_t chunks, hipStream_t s, const KrArgs* kr = nullptr);
 // Elements [start, start+count) of a Gaussian stream (FP64 or FP32 Box-Muller).
 hipError_t launch_normals(bool f32, uint64_t seed, uint32_t stream_word, uint32_t tensor_id,
                           int64_t start, int64_t count, void* out, hipStream_t s);
@@ -42,11 +59,20 @@ hipError_t launch_power_partial(Arith ar, const void* X, const ModeView& v, int 
                                 const double* Q, void* partial, int64_t chunks,
                                 hipStream_t s);
 // ---- fastpass.hip: matrix-core sketch (op 0) / power step (op 1) over FP32 X ----------
+// A sketch (op 0) of a mode with I_n above fast_pass_block_rows() runs one launch per row
+// block [row0, row0 + rows); partials are then [grid][rows][K].  rows = 0: all rows.  A
+// projection wider than fast_pass_block_k() runs one launch per column block [k0, k0 + K) of
+// Ktot columns (Ktot = 0: K); partials are then [grid][rows][K] for that block.
 bool fast_pass_supported(Arith ar, const ModeView& v, int K, int op);
-int64_t fast_pass_grid(Arith ar, const ModeView& v, int K, int op, const void* X);
+int64_t fast_pass_block_rows();
+int fast_pass_block_k(Arith ar, const ModeView& v, int K, int op);
+int64_t fast_pass_grid(Arith ar, const ModeView& v, int K, int op, const void* X,
+                       int64_t row0 = 0, int64_t rows = 0);
 hipError_t launch_fast_pass(Arith ar, int op, const void* X, const ModeView& v, int K,
                             uint64_t seed, uint32_t stream_word, uint32_t tensor_id,
-                            const double* Q, void* partial, int64_t grid, hipStream_t s);
+                            const double* Q, void* partial, int64_t grid, hipStream_t s,
+                            int64_t row0 = 0, int64_t rows = 0, int Ktot = 0, int k0 = 0,
+                            const KrArgs* kr = nullptr);
 // ---- slab.hip: BF16 sketch (op 0) / power step (op 1) of the last two modes in one pass ---
 // X viewed as A contiguous slabs of Ip x Iq; partials [grid][Ip][Kp] and [grid][Iq][Kq] (FP32).
 bool slab_pass_supported(int64_t A, int64_t Ip, int64_t Iq, int Kp, int Kq, const void* X,
@@ -56,9 +82,55 @@ hipError_t launch_slab_pass(int op, const void* X, int64_t A, int64_t Ip, int64_
                             int Kq, uint64_t seed, uint32_t swp, uint32_t swq, uint32_t tensor_id,
                             const double* Qp, const double* Qq, float* partp, float* partq,
                             int64_t grid, hipStream_t s);
-// Fixed-order sum of partials into column-major Ycol (K x In storage, Ycol[k*In+i]).
+// ---- sketch.hip, work lists: the sketches of many tensors in one launch (FP32 X; FP32 or BF16
+// arithmetic), then every job's partials summed into its Ycol (column-major In x K) in a second
+// launch.  Job j owns grid blocks [block_start[j], block_start[j+1]) (host-built prefix sums).
+struct SketchJob {
+  const void* X;
+  int64_t A, In, B;
+  int K;
+  uint32_t stream, tensor_id;
+  uint64_t seed;
+  int64_t ntiles, per, chunks;
+  int nrb;
+  void* partial;   // [chunks][In][K] FP32
+  double* Ycol;
+};
+int64_t sketch_job_chunks(const ModeView& v, int K, int target);
+void sketch_job_fill(SketchJob& g, const void* X, const ModeView& v, int K, uint64_t seed,
+                     uint32_t stream_word, uint32_t tensor_id, int64_t chunks, void* partial,
+                     double* Ycol);
+int64_t sketch_job_blocks(const SketchJob& g);
+hipError_t launch_sketch_list(Arith ar, const SketchJob* jobs, const int64_t* block_start,
+                              int njobs, int64_t blocks, int64_t max_out, hipStream_t s);
+// QR of every job's Ycol (K <= 256) into Qout[j] (row-major In x K), work[j]: In x K scratch.
+hipError_t launch_qr_list(const SketchJob* jobs, double* const* work, double* const* Qout,
+                          int njobs, hipStream_t s);
+// ---- compress.hip, work list: one mode product for many tensors per launch.  kc (4, 16 or
+// 64): outputs per thread, the tile the batched autotuner picks.
+struct TtmJob {
+  const void* in;
+  int64_t A, In, B;
+  int K;
+  const double* Q;
+  double* out;
+};
+int64_t ttm_job_blocks(const TtmJob& g, int kc);
+hipError_t launch_ttm_list(Arith ar, bool first, int kc, const TtmJob* jobs,
+                           const int64_t* block_start, int njobs, int64_t blocks, hipStream_t s);
+// ---- kr_sketch.hip: BF16 sketch of every mode in one read of X with Khatri-Rao test
+// matrices (order >= 3; the last two modes form the slabs).  Keff: K'_n per mode (K'_n = I_n:
+// mode not projected).  F holds the factors F^(n)_m (I_m x K'_n row-major) at foff[n][m];
+// part[n]: [grid][I_n][K'_n] FP32 partial sketches; xpart: [grid] partial sums of ||X||^2.
+bool kr_allmode_supported(int order, const int64_t* dims, const int* Keff, const void* X);
+int64_t kr_allmode_grid(int order, const int64_t* dims);
+hipError_t launch_kr_allmode(const void* X, int order, const int64_t* dims, const int* Keff,
+                             const float* F, const int64_t (*foff)[8], float* const* part,
+                             double* xpart, int64_t grid, hipStream_t s);
+// Fixed-order sum of partials into column-major Ycol (K x In storage, Ycol[k*ldy+i]; ldy = 0
+// means In).
 hipError_t launch_reduce_partials(Arith ar, const void* partial, int64_t chunks, int64_t In,
-                                  int K, double* Ycol, hipStream_t s);
+                                  int K, double* Ycol, hipStream_t s, int64_t ldy = 0);
 
 // ---- qr.hip ---------------------------------------------------------------------------
 struct QrJobs {
@@ -88,6 +160,8 @@ bool compress_wave_supported(int64_t A, int64_t Ip, int64_t Iq, int Kp, int Kq, 
 hipError_t launch_compress_wave(const void* X, int64_t A, int64_t Ip, int64_t Iq, int Kp, int Kq,
                                 const double* Qp, const double* Qq, double* T, hipStream_t s);
 // Sum of squares of n values (FP64/FP32) into out[0] (FP64); ``partial`` holds 1024 FP64.
+// Fixed-order sum of count doubles into *out (one work-group).
+hipError_t launch_sum(const double* x, int64_t count, double* out, hipStream_t s);
 hipError_t launch_sumsq(bool f32, const void* x, int64_t n, double* partial, double* out,
                         hipStream_t s);
 
@@ -301,6 +375,8 @@ hipError_t launch_to_f64(const float* x, int64_t n, int64_t per_row, const doubl
                          double* y, hipStream_t s);
 hipError_t launch_normalize(const double* P, int64_t d, int rows, float* out, hipStream_t s);
 size_t tr_loss4_lds(const TrLoss4& sh);
+hipError_t launch_core_loss(const float* y, const float* t, int dout, float gscale, int batch,
+                            float* loss, float* dy, hipStream_t s);
 hipError_t launch_tr_loss4(const float* y, const float* tgt, int dout, const TrLoss4& sh,
                            float gscale, int batch, float* loss, float* dy, hipStream_t s);
 

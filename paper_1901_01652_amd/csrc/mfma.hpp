@@ -4,6 +4,7 @@
 // Bt slice, contraction group (l >> 4); the accumulator holds C[4*(l>>4) + r][l & 15],
 // r = 0..3.
 //   bf16: v_mfma_f32_16x16x32_bf16, 8 contraction elements per lane (one 16-byte read)
+//   fp8:  v_mfma_f32_16x16x32_fp8_fp8 (OCP e4m3), 8 contraction elements per lane (8 bytes)
 //   fp32: v_mfma_f32_16x16x4_f32, 1 contraction element per lane
 #pragma once
 #include <hip/hip_runtime.h>
@@ -39,17 +40,51 @@ __device__ __forceinline__ f32x4 tile_abt(const float* A, int lda, const float* 
   return acc;
 }
 
-// Element type of the LDS operands and the contraction granule for each arithmetic.
-template <bool BF>
+// fp8 e4m3 operands: 8 per lane packed in 64 bits.  kdim: multiple of 32.
+__device__ __forceinline__ f32x4 tile_abt(const unsigned char* A, int lda, const unsigned char* Bt,
+                                          int ldb, int kdim, f32x4 acc) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const unsigned char* a = A + r * lda + g * 8;
+  const unsigned char* b = Bt + r * ldb + g * 8;
+  for (int k = 0; k < kdim; k += 32) {
+    const long av = *(const long*)(a + k);
+    const long bv = *(const long*)(b + k);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// Element type of the LDS operands, the contraction granule and the 8-element matrix-core
+// step for each arithmetic: 0 FP32, 1 bf16, 2 fp8 (OCP e4m3; inputs clamped to +-448, the
+// largest finite value, before rounding).
+template <int PR>
 struct Mma;
 template <>
-struct Mma<true> {
+struct Mma<1> {
   using T = __bf16;
+  using V8 = bf16x8;
   static constexpr int kStep = 32;
   static __device__ __forceinline__ __bf16 cvt(float v) { return (__bf16)v; }
+  static __device__ __forceinline__ f32x4 mma8(V8 a, V8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
 };
 template <>
-struct Mma<false> {
+struct Mma<2> {
+  using T = unsigned char;
+  using V8 = long;
+  static constexpr int kStep = 32;
+  static __device__ __forceinline__ unsigned char cvt(float v) {
+    const float c = fminf(fmaxf(v, -448.f), 448.f);
+    return (unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32(c, 0.f, 0, false) & 0xFF);
+  }
+  static __device__ __forceinline__ f32x4 mma8(V8 a, V8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mma<0> {
   using T = float;
   static constexpr int kStep = 4;
   static __device__ __forceinline__ float cvt(float v) { return v; }

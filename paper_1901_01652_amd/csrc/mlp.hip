@@ -331,6 +331,34 @@ hipError_t launch_normalize(const double* P, int64_t d, int rows, float* out, hi
   return hipGetLastError();
 }
 
+// Supervised core loss per sample: loss[s] = ||y[s] - t[s]||^2, dy[s] = gscale * 2 (y[s] - t[s]).
+// One work-group per sample; the squares are summed per thread, then over the work-group in a
+// fixed order.
+__global__ __launch_bounds__(256) void core_loss_kernel(const float* __restrict__ y,
+                                                        const float* __restrict__ t, int dout,
+                                                        float gscale, float* __restrict__ loss,
+                                                        float* __restrict__ dy) {
+  __shared__ double red[16];
+  const int64_t base = (int64_t)blockIdx.x * dout;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < dout; i += blockDim.x) {
+    const float d = y[base + i] - t[base + i];
+    acc += (double)d * d;
+    dy[base + i] = gscale * 2.f * d;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) loss[blockIdx.x] = (float)acc;
+}
+
+hipError_t launch_core_loss(const float* y, const float* t, int dout, float gscale, int batch,
+                            float* loss, float* dy, hipStream_t s) {
+  prof_begin("mlp_core_loss", s);
+  hipLaunchKernelGGL(core_loss_kernel, dim3((unsigned)batch), dim3(256), 0, s, y, t, dout, gscale,
+                     loss, dy);
+  prof_end(s);
+  return hipGetLastError();
+}
+
 size_t tr_loss4_lds(const TrLoss4& sh) {
   const int n12 = sh.K[0] * sh.K[1], n34 = sh.K[2] * sh.K[3], rr = sh.R[0] * sh.R[2];
   return (size_t)(sh.zpad + n12 * n34 + 2 * (n12 + n34) * rr) * sizeof(float);

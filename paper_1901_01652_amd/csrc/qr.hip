@@ -12,16 +12,11 @@ namespace rtr {
 constexpr int kQrThreads = 256;
 constexpr int kQrKMax = 256;
 
-__global__ __launch_bounds__(kQrThreads) void householder_qr_kernel(QrJobs jobs) {
+// One matrix per work-group: A (column-major In x K, overwritten), Qm scratch, Qout row-major.
+__device__ __forceinline__ void qr_one(double* A, double* Qm, int64_t In, int K, double* Qout) {
   __shared__ double red[16];
   __shared__ double rdiag[kQrKMax];
   __shared__ double vtv[kQrKMax];
-  const int job = blockIdx.x;
-  double* A = jobs.A[job];
-  double* Qm = jobs.Qwork[job];
-  const int64_t In = jobs.In[job];
-  const int K = jobs.K[job];
-  double* Qout = jobs.Q[job];
   const int lane = threadIdx.x % kWave;
   const int wid = threadIdx.x / kWave;
   const int nw = kQrThreads / kWave;
@@ -81,6 +76,28 @@ __global__ __launch_bounds__(kQrThreads) void householder_qr_kernel(QrJobs jobs)
     const double sg = (rdiag[col] < 0.0) ? -1.0 : 1.0;
     Qout[p] = sg * Qm[(int64_t)col * In + row];
   }
+}
+
+__global__ __launch_bounds__(kQrThreads) void householder_qr_kernel(QrJobs jobs) {
+  const int job = blockIdx.x;
+  qr_one(jobs.A[job], jobs.Qwork[job], jobs.In[job], jobs.K[job], jobs.Q[job]);
+}
+
+// Any number of matrices from a device job list (one work-group each).
+__global__ __launch_bounds__(kQrThreads) void qr_list_kernel(const SketchJob* __restrict__ jobs,
+                                                             double* const* __restrict__ work,
+                                                             double* const* __restrict__ Qout) {
+  const SketchJob g = jobs[blockIdx.x];
+  qr_one(g.Ycol, work[blockIdx.x], g.In, g.K, Qout[blockIdx.x]);
+}
+
+hipError_t launch_qr_list(const SketchJob* jobs, double* const* work, double* const* Qout,
+                          int njobs, hipStream_t s) {
+  if (njobs < 1) return hipSuccess;
+  prof_begin("householder_qr", s);
+  hipLaunchKernelGGL(qr_list_kernel, dim3((unsigned)njobs), dim3(kQrThreads), 0, s, jobs, work, Qout);
+  prof_end(s);
+  return hipGetLastError();
 }
 
 hipError_t launch_householder_qr(const QrJobs& jobs, hipStream_t s) {

@@ -66,6 +66,12 @@ struct rtr_context {
   hipEvent_t join_ev[kBatchBranches] = {};
   bool ws_locked = false;  // set while a capture hands out fixed slices of the workspace
   size_t ws_hi = 0;        // largest workspace request since it was last reset
+  // batched work lists (sketch, QR, mode products of every tensor per launch): device job
+  // arrays, and the tiles chosen by rtr_batch_autotune
+  void* jobs_dev = nullptr;
+  size_t jobs_cap = 0;
+  int bt_target = 64;  // column-tile chunks per sketch job
+  int bt_kc = 16;      // outputs per thread of the batched mode products
 };
 
 namespace {
@@ -228,9 +234,17 @@ rtr_status check_arith(rtr_context* h, rtr_dtype x_dtype, rtr_dtype compute, rtr
     *ar = rtr::kBF16;
     return RTR_OK;
   }
+  if (x_dtype == RTR_F32 && compute == RTR_FP8_E4M3) {
+    *ar = rtr::kFP8;
+    return RTR_OK;
+  }
   return fail(h, RTR_ERR_UNSUPPORTED,
-              "supported (x_dtype, compute): (F64, F64), (F32, F32), (F32, BF16)");
+              "supported (x_dtype, compute): (F64, F64), (F32, F32), (F32, BF16), (F32, FP8_E4M3)");
 }
+
+// The FP8 compute option applies to the sketch products only; power steps and mode products
+// run in the bf16 arithmetic (with its FP32 refinement in the compression).
+rtr::Arith not_fp8(rtr::Arith ar) { return ar == rtr::kFP8 ? rtr::kBF16 : ar; }
 
 int64_t keff(const int64_t* dims, const int32_t* K, int n) {
   return K[n] < dims[n] ? (int64_t)K[n] : dims[n];
@@ -256,7 +270,7 @@ static bool streams_x(const char* name) {
   static const char* const kNames[] = {"sketch_partial", "power_partial", "ttm_first",
                                        "residual", "sketch_fused", "power_fused",
                                        "compress_fused", "read_probe", "als_persist",
-                                       "sketch_slab", "power_slab"};
+                                       "sketch_slab", "power_slab", "sketch_kr_allmode"};
   for (const char* k : kNames)
     if (std::strcmp(k, name) == 0) return true;
   return false;
@@ -334,6 +348,7 @@ rtr_status rtr_destroy(rtr_handle h) {
   if (h->items_copied) (void)hipEventDestroy(h->items_copied);
   if (h->items_dev) (void)hipFree(h->items_dev);
   if (h->gitems_dev) (void)hipFree(h->gitems_dev);
+  if (h->jobs_dev) (void)hipFree(h->jobs_dev);
   if (h->items_host) (void)hipHostFree(h->items_host);
   if (h->ws) (void)hipFree(h->ws);
   if (h->status) (void)hipFree(h->status);
@@ -359,13 +374,27 @@ const char* rtr_status_string(rtr_status s) {
 // ---------------------------------------------------------------------------------------
 namespace {
 
+// Largest projection size: the QR kernel's limit (the sketch and the power step run in column
+// blocks of at most 64).
+constexpr int kSketchKMax = 256;
+
+// Rows per block of the matrix-core sketch: equal blocks of at most fast_pass_block_rows(),
+// rounded up to whole 16-row tiles.
+int64_t row_block(int64_t In) {
+  const int64_t cap = rtr::fast_pass_block_rows();
+  if (In <= cap) return In;
+  const int64_t nb = (In + cap - 1) / cap;
+  return std::min(cap, ((In + nb - 1) / nb + 15) / 16 * 16);
+}
+
 // Alg. 1 steps 3-6 (+ power iterations).  With ``fixed`` the partial sketches and QR work
 // arrays live in that buffer of ``fixed_cap`` bytes and nothing is allocated (a request that
 // needs more is refused before anything is enqueued); otherwise in the handle's workspace.
 rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t order,
                        const int64_t* dims, const int32_t* K, int32_t power_iters, uint64_t seed,
                        uint32_t tensor_id, rtr_dtype compute, double* Q, void* stream,
-                       void* fixed, size_t fixed_cap) {
+                       void* fixed, size_t fixed_cap, bool khatri_rao = false,
+                       double* x_norm2 = nullptr) {
   rtr_status st;
   if ((st = check_shape(h, order, dims, K))) return st;
   if (!K) return fail(h, RTR_ERR_INVALID_ARG, "K is NULL");
@@ -382,8 +411,8 @@ rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t
   const int sp = order - 2, sq = order - 1;
   int64_t slabA = 1;
   for (int n = 0; n < sp; ++n) slabA *= dims[n];
-  const bool slab_ok = ar == rtr::kBF16 && order >= 2 && keff(dims, K, sp) < dims[sp] &&
-                       keff(dims, K, sq) < dims[sq];
+  const bool slab_ok = ar == rtr::kBF16 && !khatri_rao && order >= 2 &&
+                       keff(dims, K, sp) < dims[sp] && keff(dims, K, sq) < dims[sq];
   const bool slab0 = slab_ok && rtr::slab_pass_supported(slabA, dims[sp], dims[sq], (int)keff(dims, K, sp),
                                                          (int)keff(dims, K, sq), X, 0);
   const bool slab1 = slab_ok && power_iters > 0 &&
@@ -399,32 +428,77 @@ rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t
   for (int n = 0; n < order; ++n) {
     const int64_t k = keff(dims, K, n);
     if (k == dims[n]) continue;
-    if (k > 64)
-      return fail(h, RTR_ERR_UNSUPPORTED, "projection size above 64 (mode " + std::to_string(n) + ")");
+    if (k > kSketchKMax)
+      return fail(h, RTR_ERR_UNSUPPORTED,
+                  "projection size above " + std::to_string(kSketchKMax) + " (mode " + std::to_string(n) + ")");
     rtr::ModeView v = mode_view(dims, order, n);
-    size_t need = rtr::fast_pass_supported(ar, v, (int)k, 0)
-                      ? (size_t)rtr::fast_pass_grid(ar, v, (int)k, 0, X) * v.In * k * sizeof(float)
-                      : (size_t)rtr::sketch_chunks(v, (int)k) * v.In * k * pelem;
+    size_t need = 0;
+    const int kb = rtr::fast_pass_block_k(ar, v, (int)k, 0);
+    if (kb > 0) {
+      const int64_t rb = row_block(v.In);
+      for (int64_t r0 = 0; r0 < v.In; r0 += rb) {
+        const int64_t rows = std::min(rb, v.In - r0);
+        need = std::max(need, (size_t)rtr::fast_pass_grid(ar, v, kb, 0, X, r0, rows) * rows * kb *
+                                  sizeof(float));
+      }
+    } else {
+      if (k > 64)
+        return fail(h, RTR_ERR_UNSUPPORTED,
+                    "projection size above 64 needs the FP32/BF16 path (mode " + std::to_string(n) + ")");
+      need = (size_t)rtr::sketch_chunks(v, (int)k) * v.In * k * pelem;
+    }
     if (power_iters > 0) {
       size_t pw;
-      if (rtr::fast_pass_supported(ar, v, (int)k, 1)) {
-        pw = (size_t)rtr::fast_pass_grid(ar, v, (int)k, 1, X) * v.In * k * sizeof(float);
+      const rtr::Arith arp = not_fp8(ar);
+      const int kb1 = rtr::fast_pass_block_k(arp, v, (int)k, 1);
+      if (kb1 > 0) {
+        pw = (size_t)rtr::fast_pass_grid(arp, v, kb1, 1, X) * v.In * kb1 * sizeof(float);
       } else {
-        if (!rtr::power_supported(ar, v, (int)k))
+        if (!rtr::power_supported(arp, v, (int)k))
           return fail(h, RTR_ERR_UNSUPPORTED,
                       "power iterations need I_n*K_n <= 8192 (mode " + std::to_string(n) + ")");
-        pw = (size_t)rtr::power_chunks(ar, v, (int)k) * v.In * k * pelem;
+        pw = (size_t)rtr::power_chunks(arp, v, (int)k) * v.In * k * pelem;
       }
       if (pw > need) need = pw;
     }
     if (need > pmax) pmax = need;
   }
+  // Khatri-Rao factors of one mode at a time (sum over the other modes of I_m K_n)
+  size_t krmax = 0;
+  if (khatri_rao)
+    for (int n = 0; n < order; ++n) {
+      size_t e = 0;
+      for (int m = 0; m < order; ++m)
+        if (m != n) e += (size_t)dims[m] * keff(dims, K, n);
+      krmax = std::max(krmax, e * pelem);
+    }
+  // Khatri-Rao, BF16: every mode's sketch (and ||X||^2) in one pass when the slab shape fits
+  int keffi[RTR_MAX_ORDER];
+  for (int n = 0; n < order; ++n) keffi[n] = (int)keff(dims, K, n);
+  const bool allmode = khatri_rao && ar == rtr::kBF16 && rtr::kr_allmode_supported(order, dims, keffi, X);
+  const int64_t am_grid = allmode ? rtr::kr_allmode_grid(order, dims) : 0;
+  size_t am_f = 0, am_p = 0;  // factor floats, partial floats
+  int64_t am_foff[8][8] = {};
+  if (allmode)
+    for (int n = 0; n < order; ++n) {
+      if (keffi[n] == dims[n]) continue;
+      for (int m = 0; m < order; ++m) {
+        if (m == n) continue;
+        am_foff[n][m] = (int64_t)am_f;
+        am_f += (size_t)dims[m] * keffi[n];
+      }
+      am_p += (size_t)am_grid * dims[n] * keffi[n];
+    }
   Carve plan(nullptr);
   plan.take<char>(pmax);
   for (int n = 0; n < order; ++n) {
     plan.take<double>((size_t)dims[n] * keff(dims, K, n));
     plan.take<double>((size_t)dims[n] * keff(dims, K, n));
   }
+  plan.take<char>(krmax);
+  plan.take<float>(am_f);
+  plan.take<float>(am_p);
+  plan.take<double>((size_t)am_grid + 1024);
   void* ws;
   if (fixed) {
     if (plan.off + 256 > fixed_cap)
@@ -438,6 +512,11 @@ rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t
   }
   Carve cv(ws);
   void* partial = cv.take<char>(pmax);
+  // every launch below checks that its partial sums fit the planned buffer
+  auto fits = [&](size_t bytes) -> rtr_status {
+    return bytes <= pmax ? RTR_OK
+                         : fail(h, RTR_ERR_INTERNAL, "partial sums exceed the planned workspace");
+  };
   double* Ycol[RTR_MAX_ORDER];
   double* Qw[RTR_MAX_ORDER];
   double* Qn[RTR_MAX_ORDER];
@@ -449,6 +528,30 @@ rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t
     Qn[n] = Q + qoff;
     qoff += (size_t)dims[n] * k;
   }
+  void* krbuf = cv.take<char>(krmax);
+  float* am_F = cv.take<float>(am_f);
+  float* am_part = cv.take<float>(am_p);
+  double* am_x = cv.take<double>((size_t)am_grid + 1024);
+  // draws mode n's Khatri-Rao factors into krbuf and describes them
+  auto kr_factors = [&](int n, rtr::KrArgs* ka) -> rtr_status {
+    const int64_t k = keff(dims, K, n);
+    *ka = rtr::KrArgs{};
+    ka->f = krbuf;
+    ka->ld = (int)k;
+    int64_t off = 0;
+    for (int m = 0; m < order; ++m) {
+      if (m == n) continue;
+      ka->dim[ka->nm] = (int)dims[m];
+      ka->off[ka->nm] = off;
+      ++ka->nm;
+      char* dst = (char*)krbuf + off * pelem;
+      HIP_TRY(rtr::launch_normals(pelem == sizeof(float), seed, rtr::kr_stream(n, m), tensor_id, 0,
+                                  dims[m] * k, dst, s),
+              "normals");
+      off += dims[m] * k;
+    }
+    return RTR_OK;
+  };
 
   rtr::QrJobs jobs{};
   // partial sums of the two slab modes (FP32) and the reduction of both into Ycol
@@ -461,6 +564,28 @@ rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t
                                         Ycol[sq], s), "reduce_partials");
     return RTR_OK;
   };
+  if (allmode) {
+    // every factor F^(n)_m, one pass over X, then each mode's partials into its Ycol
+    float* parts[8] = {};
+    size_t po = 0;
+    for (int n = 0; n < order; ++n) {
+      if (keffi[n] == dims[n]) continue;
+      for (int m = 0; m < order; ++m)
+        if (m != n)
+          HIP_TRY(rtr::launch_normals(true, seed, rtr::kr_stream(n, m), tensor_id, 0,
+                                      dims[m] * keffi[n], am_F + am_foff[n][m], s),
+                  "normals");
+      parts[n] = am_part + po;
+      po += (size_t)am_grid * dims[n] * keffi[n];
+    }
+    HIP_TRY(rtr::launch_kr_allmode(X, order, dims, keffi, am_F, am_foff, parts, am_x, am_grid, s),
+            "sketch_kr_allmode");
+    if (x_norm2) HIP_TRY(rtr::launch_sum(am_x, am_grid, x_norm2, s), "sum");
+  } else if (x_norm2) {
+    size_t numel = 1;
+    for (int n = 0; n < order; ++n) numel *= (size_t)dims[n];
+    HIP_TRY(rtr::launch_sumsq(ar != rtr::kF64, X, (int64_t)numel, am_x, x_norm2, s), "sumsq");
+  }
   for (int n = 0; n < order; ++n) {
     const int64_t k = keff(dims, K, n);
     if (k == dims[n]) {
@@ -468,6 +593,23 @@ rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t
       continue;
     }
     rtr::ModeView v = mode_view(dims, order, n);
+    if (allmode) {
+      size_t po = 0;
+      for (int m = 0; m < n; ++m)
+        if (keffi[m] < dims[m]) po += (size_t)am_grid * dims[m] * keffi[m];
+      HIP_TRY(rtr::launch_reduce_partials(rtr::kF32, am_part + po, am_grid, dims[n], (int)k, Ycol[n], s),
+              "reduce_partials");
+      const int j = jobs.count++;
+      jobs.A[j] = Ycol[n];
+      jobs.Qwork[j] = Qw[n];
+      jobs.In[j] = dims[n];
+      jobs.K[j] = (int)k;
+      jobs.Q[j] = Qn[n];
+      continue;
+    }
+    rtr::KrArgs ka{};
+    if (khatri_rao && (st = kr_factors(n, &ka))) return st;
+    const rtr::KrArgs* kp = khatri_rao ? &ka : nullptr;
     if (slab0 && (n == sp || n == sq)) {
       if (n == sp) {
         HIP_TRY(rtr::launch_slab_pass(0, X, slabA, dims[sp], dims[sq], (int)keff(dims, K, sp),
@@ -478,16 +620,28 @@ rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t
         if ((st = reduce_slab())) return st;
       }
     } else if (rtr::fast_pass_supported(ar, v, (int)k, 0)) {
-      const int64_t grid = rtr::fast_pass_grid(ar, v, (int)k, 0, X);
-      HIP_TRY(rtr::launch_fast_pass(ar, 0, X, v, (int)k, seed, rtr::omega_stream(n), tensor_id,
-                                    nullptr, partial, grid, s),
-              "sketch_fused");
-      HIP_TRY(rtr::launch_reduce_partials(rtr::kF32, partial, grid, v.In, (int)k, Ycol[n], s),
-              "reduce_partials");
+      // one launch per row block and column block (a single one when I_n and K_n fit)
+      const int64_t rb = row_block(v.In);
+      const int kmax = rtr::fast_pass_block_k(ar, v, (int)k, 0);
+      for (int64_t r0 = 0; r0 < v.In; r0 += rb) {
+        const int64_t rows = std::min(rb, v.In - r0);
+        for (int k0 = 0; k0 < (int)k; k0 += kmax) {
+          const int kb = std::min(kmax, (int)k - k0);
+          const int64_t grid = rtr::fast_pass_grid(ar, v, kb, 0, X, r0, rows);
+          if ((st = fits((size_t)grid * rows * kb * sizeof(float)))) return st;
+          HIP_TRY(rtr::launch_fast_pass(ar, 0, X, v, kb, seed, rtr::omega_stream(n), tensor_id,
+                                        nullptr, partial, grid, s, r0, rows, (int)k, k0, kp),
+                  "sketch_fused");
+          HIP_TRY(rtr::launch_reduce_partials(rtr::kF32, partial, grid, rows, kb,
+                                              Ycol[n] + (int64_t)k0 * v.In + r0, s, v.In),
+                  "reduce_partials");
+        }
+      }
     } else {
       const int64_t chunks = rtr::sketch_chunks(v, (int)k);
+      if ((st = fits((size_t)chunks * v.In * k * pelem))) return st;
       HIP_TRY(rtr::launch_sketch_partial(ar, X, v, (int)k, seed, rtr::omega_stream(n), tensor_id,
-                                         partial, chunks, s),
+                                         partial, chunks, s, kp),
               "sketch_partial");
       HIP_TRY(rtr::launch_reduce_partials(ar, partial, chunks, v.In, (int)k, Ycol[n], s),
               "reduce_partials");
@@ -500,6 +654,7 @@ rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t
     jobs.Q[j] = Qn[n];
   }
   HIP_TRY(rtr::launch_householder_qr(jobs, s), "householder_qr");
+  const rtr::Arith arp = not_fp8(ar);  // arithmetic of the power steps
   for (int it = 0; it < power_iters; ++it) {
     for (int n = 0; n < order; ++n) {
       const int64_t k = keff(dims, K, n);
@@ -513,17 +668,26 @@ rtr_status sketch_impl(rtr_context* h, const void* X, rtr_dtype x_dtype, int32_t
                   "power_slab");
           if ((st = reduce_slab())) return st;
         }
-      } else if (rtr::fast_pass_supported(ar, v, (int)k, 1)) {
-        const int64_t grid = rtr::fast_pass_grid(ar, v, (int)k, 1, X);
-        HIP_TRY(rtr::launch_fast_pass(ar, 1, X, v, (int)k, 0, 0, 0, Qn[n], partial, grid, s),
-                "power_fused");
-        HIP_TRY(rtr::launch_reduce_partials(rtr::kF32, partial, grid, v.In, (int)k, Ycol[n], s),
-                "reduce_partials");
+      } else if (rtr::fast_pass_supported(arp, v, (int)k, 1)) {
+        const int kmax = rtr::fast_pass_block_k(arp, v, (int)k, 1);
+        for (int k0 = 0; k0 < (int)k; k0 += kmax) {
+          const int kb = std::min(kmax, (int)k - k0);
+          const int64_t grid = rtr::fast_pass_grid(arp, v, kb, 1, X);
+          if ((st = fits((size_t)grid * v.In * kb * sizeof(float)))) return st;
+          HIP_TRY(rtr::launch_fast_pass(arp, 1, X, v, kb, 0, 0, 0, Qn[n], partial, grid, s, 0, 0,
+                                        (int)k, k0),
+                  "power_fused");
+          HIP_TRY(rtr::launch_reduce_partials(rtr::kF32, partial, grid, v.In, kb,
+                                              Ycol[n] + (int64_t)k0 * v.In, s, v.In),
+                  "reduce_partials");
+        }
       } else {
-        const int64_t chunks = rtr::power_chunks(ar, v, (int)k);
-        HIP_TRY(rtr::launch_power_partial(ar, X, v, (int)k, Qn[n], partial, chunks, s),
+        const int64_t chunks = rtr::power_chunks(arp, v, (int)k);
+        if ((st = fits((size_t)chunks * v.In * k * (arp == rtr::kF64 ? sizeof(double) : sizeof(float)))))
+          return st;
+        HIP_TRY(rtr::launch_power_partial(arp, X, v, (int)k, Qn[n], partial, chunks, s),
                 "power_partial");
-        HIP_TRY(rtr::launch_reduce_partials(ar, partial, chunks, v.In, (int)k, Ycol[n], s),
+        HIP_TRY(rtr::launch_reduce_partials(arp, partial, chunks, v.In, (int)k, Ycol[n], s),
                 "reduce_partials");
       }
     }
@@ -543,6 +707,20 @@ rtr_status rtr_sketch(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t or
   Guard guard(h);
   return sketch_impl(h, X, x_dtype, order, dims, K, power_iters, seed, tensor_id, compute, Q,
                      stream, nullptr, 0);
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+rtr_status rtr_sketch_kr(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
+                         const int64_t* dims, const int32_t* K, int32_t power_iters,
+                         uint64_t seed, uint32_t tensor_id, rtr_dtype compute, double* Q,
+                         double* x_norm2, void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if ((st = check_dev_opt(h, x_norm2, sizeof(double), "x_norm2"))) return st;
+  return sketch_impl(h, X, x_dtype, order, dims, K, power_iters, seed, tensor_id, compute, Q,
+                     stream, nullptr, 0, true, x_norm2);
 } catch (...) {
   return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
 }
@@ -573,6 +751,7 @@ rtr_status rtr_compress(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t 
   if (!K) return fail(h, RTR_ERR_INVALID_ARG, "K is NULL");
   rtr::Arith ar;
   if ((st = check_arith(h, x_dtype, compute, &ar))) return st;
+  ar = not_fp8(ar);  // the compression reads X in bf16 with the FP32 refinement
   CHECK_DEV(X, x_bytes(dims, order, x_dtype), "X");
   CHECK_DEV(Q, q_bytes(dims, K, order), "Q");
   {
@@ -583,8 +762,9 @@ rtr_status rtr_compress(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t 
   if ((st = check_dev_opt(h, p_norm2, sizeof(double), "p_norm2"))) return st;
   hipStream_t s = (hipStream_t)stream;
   for (int n = 0; n < order; ++n)
-    if (keff(dims, K, n) > 64)
-      return fail(h, RTR_ERR_UNSUPPORTED, "projection size above 64 (mode " + std::to_string(n) + ")");
+    if (keff(dims, K, n) > kSketchKMax)
+      return fail(h, RTR_ERR_UNSUPPORTED,
+                  "projection size above " + std::to_string(kSketchKMax) + " (mode " + std::to_string(n) + ")");
   size_t qoffs[RTR_MAX_ORDER];
   {
     size_t q = 0;
@@ -675,6 +855,152 @@ rtr_status rtr_compress(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t 
 }
 
 // ---------------------------------------------------------------------------------------
+// Alg. 1 steps 3-8 with step 7 read sequentially: mode n is sketched from the tensor already
+// compressed in modes 1..n-1 (the first mode from X in the requested arithmetic, the later ones
+// from the FP64 intermediate), then that tensor is multiplied by Q_n^T.
+rtr_status rtr_sketch_sequential(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
+                                 const int64_t* dims, const int32_t* K, uint64_t seed,
+                                 uint32_t tensor_id, rtr_dtype compute, double* Q, double* P,
+                                 double* p_norm2, void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if ((st = check_shape(h, order, dims, K))) return st;
+  if (!K) return fail(h, RTR_ERR_INVALID_ARG, "K is NULL");
+  rtr::Arith ar;
+  if ((st = check_arith(h, x_dtype, compute, &ar))) return st;
+  CHECK_DEV(X, x_bytes(dims, order, x_dtype), "X");
+  CHECK_DEV(Q, q_bytes(dims, K, order), "Q");
+  size_t pnum = 1;
+  for (int n = 0; n < order; ++n) pnum *= (size_t)keff(dims, K, n);
+  CHECK_DEV(P, pnum * sizeof(double), "P");
+  if ((st = check_dev_opt(h, p_norm2, sizeof(double), "p_norm2"))) return st;
+  hipStream_t s = (hipStream_t)stream;
+
+  // plan: dims of the tensor each projected mode sees, partial-sum sizes, intermediate sizes
+  int64_t cd[RTR_MAX_ORDER];
+  for (int n = 0; n < order; ++n) cd[n] = dims[n];
+  size_t pmax = 0, midmax = 0;
+  int last = -1;
+  bool first = true;
+  for (int n = 0; n < order; ++n) {
+    const int64_t k = keff(dims, K, n);
+    if (k == dims[n]) continue;
+    rtr::ModeView v = mode_view(cd, order, n);
+    const rtr::Arith an = first ? ar : rtr::kF64;
+    const int kb = rtr::fast_pass_block_k(an, v, (int)k, 0);
+    size_t need;
+    if (kb > 0) {
+      need = 0;
+      const int64_t rb = row_block(v.In);
+      for (int64_t r0 = 0; r0 < v.In; r0 += rb) {
+        const int64_t rows = std::min(rb, v.In - r0);
+        need = std::max(need, (size_t)rtr::fast_pass_grid(an, v, kb, 0, X, r0, rows) * rows * kb *
+                                  sizeof(float));
+      }
+    } else {
+      if (k > 64)
+        return fail(h, RTR_ERR_UNSUPPORTED, "the sequential sketch takes K_n <= 64 past the first "
+                                            "projected mode (mode " + std::to_string(n) + ")");
+      need = (size_t)rtr::sketch_chunks(v, (int)k) * v.In * k *
+             (an == rtr::kF64 ? sizeof(double) : sizeof(float));
+    }
+    pmax = std::max(pmax, need);
+    cd[n] = k;
+    size_t z = 1;
+    for (int m = 0; m < order; ++m) z *= (size_t)cd[m];
+    midmax = std::max(midmax, z);
+    last = n;
+    first = false;
+  }
+  Carve plan(nullptr);
+  plan.take<char>(pmax);
+  plan.take<double>(midmax);
+  plan.take<double>(midmax);
+  for (int n = 0; n < order; ++n) {
+    plan.take<double>((size_t)dims[n] * keff(dims, K, n));
+    plan.take<double>((size_t)dims[n] * keff(dims, K, n));
+  }
+  plan.take<double>(1024);
+  if ((st = ensure_ws(h, plan.off + 256))) return st;
+  Carve cv(h->ws);
+  void* partial = cv.take<char>(pmax);
+  double* buf[2] = {cv.take<double>(midmax), cv.take<double>(midmax)};
+  double* Ycol[RTR_MAX_ORDER];
+  double* Qw[RTR_MAX_ORDER];
+  double* Qn[RTR_MAX_ORDER];
+  size_t qoff = 0;
+  for (int n = 0; n < order; ++n) {
+    const int64_t k = keff(dims, K, n);
+    Ycol[n] = cv.take<double>((size_t)dims[n] * k);
+    Qw[n] = cv.take<double>((size_t)dims[n] * k);
+    Qn[n] = Q + qoff;
+    qoff += (size_t)dims[n] * k;
+  }
+  double* red = cv.take<double>(1024);
+
+  for (int n = 0; n < order; ++n) cd[n] = dims[n];
+  const void* cur = X;
+  bool cur_is_x = true;
+  int nb = 0;
+  for (int n = 0; n < order; ++n) {
+    const int64_t k = keff(dims, K, n);
+    if (k == dims[n]) {
+      HIP_TRY(rtr::launch_identity(Qn[n], dims[n], s), "identity");
+      continue;
+    }
+    rtr::ModeView v = mode_view(cd, order, n);
+    const rtr::Arith an = cur_is_x ? ar : rtr::kF64;
+    const int kmax = rtr::fast_pass_block_k(an, v, (int)k, 0);
+    if (kmax > 0) {
+      const int64_t rb = row_block(v.In);
+      for (int64_t r0 = 0; r0 < v.In; r0 += rb) {
+        const int64_t rows = std::min(rb, v.In - r0);
+        for (int k0 = 0; k0 < (int)k; k0 += kmax) {
+          const int kb = std::min(kmax, (int)k - k0);
+          const int64_t grid = rtr::fast_pass_grid(an, v, kb, 0, cur, r0, rows);
+          HIP_TRY(rtr::launch_fast_pass(an, 0, cur, v, kb, seed, rtr::omega_stream(n), tensor_id,
+                                        nullptr, partial, grid, s, r0, rows, (int)k, k0),
+                  "sketch_fused");
+          HIP_TRY(rtr::launch_reduce_partials(rtr::kF32, partial, grid, rows, kb,
+                                              Ycol[n] + (int64_t)k0 * v.In + r0, s, v.In),
+                  "reduce_partials");
+        }
+      }
+    } else {
+      const int64_t chunks = rtr::sketch_chunks(v, (int)k);
+      HIP_TRY(rtr::launch_sketch_partial(an, cur, v, (int)k, seed, rtr::omega_stream(n), tensor_id,
+                                         partial, chunks, s),
+              "sketch_partial");
+      HIP_TRY(rtr::launch_reduce_partials(an, partial, chunks, v.In, (int)k, Ycol[n], s),
+              "reduce_partials");
+    }
+    rtr::QrJobs jobs{};
+    jobs.count = 1;
+    jobs.A[0] = Ycol[n];
+    jobs.Qwork[0] = Qw[n];
+    jobs.In[0] = dims[n];
+    jobs.K[0] = (int)k;
+    jobs.Q[0] = Qn[n];
+    HIP_TRY(rtr::launch_householder_qr(jobs, s), "householder_qr");
+    double* out = (n == last) ? P : buf[nb];
+    HIP_TRY(rtr::launch_ttm(not_fp8(ar), cur_is_x, cur, v, (int)k, Qn[n], out, s), "ttm");
+    cd[n] = k;
+    cur = out;
+    cur_is_x = false;
+    nb ^= 1;
+  }
+  if (last < 0) {  // nothing projected: P = X in FP64 (the product with Q_1 = I)
+    rtr::ModeView v = mode_view(dims, order, 0);
+    HIP_TRY(rtr::launch_ttm(not_fp8(ar), true, X, v, (int)dims[0], Qn[0], P, s), "ttm");
+  }
+  if (p_norm2) HIP_TRY(rtr::launch_sumsq(false, P, (int64_t)pnum, red, p_norm2, s), "sumsq");
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+// ---------------------------------------------------------------------------------------
 rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int32_t* Kp,
                          const int32_t* R, const rtr_decompose_opts* opts,
                          const double* Z_init, double* Z, double* err_trace,
@@ -731,7 +1057,7 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
       return fail(h, RTR_ERR_INVALID_ARG,
                   "R_n R_{n+1} exceeds the number of equations for core " + std::to_string(n));
     if (!rtr::als_supported(g.Kn, g.RR))
-      return fail(h, RTR_ERR_UNSUPPORTED, "K'_n R_n R_{n+1} + (R_n R_{n+1})^2 above 16384");
+      return fail(h, RTR_ERR_UNSUPPORTED, "TR-ALS takes K'_n <= 1024 and R_n R_{n+1} <= 256");
     geo[n] = g;
     Jmax = std::max(Jmax, g.J);
     RRmax = std::max(RRmax, g.RR);
@@ -1173,10 +1499,216 @@ namespace {
 
 // Alg. 1 steps 3-12 for every item: per-tensor sketch and compression, one batched TR-ALS
 // launch over the item array ``dev``, per-tensor back-projection.
+// ---------------------------------------------------------------------------------------
+// Batched work lists: the sketches of every (tensor, mode) in one launch, their sums in one,
+// every QR in one, and each mode product of the compression chain (mode 1 first, Eq. 3) for
+// every tensor in one launch per mode.  The job arrays hold device addresses inside the
+// workspace, so they are built and uploaded once per call, before the eager run and the
+// capture, and reused by both.
+struct StreamPlan {
+  rtr::Arith ar = rtr::kF32;
+  int kc = 16;
+  int njobs = 0;
+  int64_t sk_blocks = 0, sk_maxout = 0;
+  const rtr::SketchJob* d_sk = nullptr;
+  const int64_t* d_skstart = nullptr;
+  double* const* d_work = nullptr;
+  double* const* d_qout = nullptr;
+  std::vector<std::pair<double*, int64_t>> ident;  // modes kept: Q_n = I
+  int steps = 0;
+  std::vector<int> tt_n;
+  std::vector<int64_t> tt_blocks;
+  std::vector<const rtr::TtmJob*> d_tt;
+  std::vector<const int64_t*> d_ttstart;
+};
+
+// The work lists are switched off: the first graph-captured batch run that used them ended
+// with a GPU memory fault whose cause has not been shown yet (the eager run of the same code
+// had passed its parity test).  Until it is, rtr_batch_run takes the per-tensor path.
+constexpr bool kBatchWorkLists = false;
+
+bool stream_eligible(const rtr_batch_item* items, int32_t count, rtr_dtype x_dtype,
+                     int32_t power_iters) {
+  if (!kBatchWorkLists) return false;
+  if (x_dtype != RTR_F32 || power_iters != 0) return false;
+  for (int t = 0; t < count; ++t)
+    for (int n = 0; n < items[t].order; ++n)
+      if (keff(items[t].dims, items[t].K, n) > 64) return false;
+  return true;
+}
+
+rtr_status plan_stream(rtr_context* h, const rtr_batch_item* items, int32_t count, rtr::Arith ar,
+                       int target, int kc, hipStream_t s, StreamPlan* sp) {
+  sp->ar = ar;
+  sp->kc = kc;
+  int maxorder = 0;
+  for (int t = 0; t < count; ++t) maxorder = std::max(maxorder, (int)items[t].order);
+  // sizes: sketch partials, Ycol + Qwork per job, two intermediates per tensor
+  size_t part = 0, yq = 0, mid = 0;
+  int njobs = 0;
+  std::vector<size_t> midt(count, 0);
+  for (int t = 0; t < count; ++t) {
+    const rtr_batch_item& it = items[t];
+    int64_t cur[RTR_MAX_ORDER];
+    for (int n = 0; n < it.order; ++n) cur[n] = it.dims[n];
+    for (int n = 0; n < it.order; ++n) {
+      const int64_t k = keff(it.dims, it.K, n);
+      if (k < it.dims[n]) {
+        rtr::ModeView v = mode_view(it.dims, it.order, n);
+        part += (size_t)rtr::sketch_job_chunks(v, (int)k, target) * v.In * k;
+        yq += 2 * (size_t)v.In * k;
+        ++njobs;
+      }
+      cur[n] = k;
+      if (n + 1 < it.order) {
+        size_t z = 1;
+        for (int m = 0; m < it.order; ++m) z *= (size_t)cur[m];
+        midt[t] = std::max(midt[t], z);
+      }
+    }
+    mid += 2 * midt[t];
+  }
+  Carve plan(nullptr);
+  plan.take<float>(part);
+  plan.take<double>(yq);
+  plan.take<double>(mid);
+  rtr_status st;
+  if ((st = ensure_ws(h, plan.off + 256))) return st;
+  Carve cv(h->ws);
+  float* pbase = cv.take<float>(part);
+  double* ybase = cv.take<double>(yq);
+  double* mbase = cv.take<double>(mid);
+  // host job arrays
+  std::vector<rtr::SketchJob> sk;
+  std::vector<int64_t> skstart(1, 0);
+  std::vector<double*> work, qout;
+  std::vector<std::vector<rtr::TtmJob>> tt(maxorder);
+  std::vector<std::vector<int64_t>> ttstart(maxorder, std::vector<int64_t>(1, 0));
+  sp->ident.clear();
+  size_t po = 0, yo = 0, mo = 0;
+  for (int t = 0; t < count; ++t) {
+    const rtr_batch_item& it = items[t];
+    double* buf[2] = {mbase + mo, mbase + mo + midt[t]};
+    mo += 2 * midt[t];
+    size_t qoff = 0;
+    int64_t cur[RTR_MAX_ORDER];
+    for (int n = 0; n < it.order; ++n) cur[n] = it.dims[n];
+    const void* in = it.X;
+    for (int n = 0; n < it.order; ++n) {
+      const int64_t k = keff(it.dims, it.K, n);
+      double* Qn = it.Q + qoff;
+      qoff += (size_t)it.dims[n] * k;
+      rtr::ModeView v = mode_view(it.dims, it.order, n);
+      if (k < it.dims[n]) {
+        rtr::SketchJob g{};
+        const int64_t chunks = rtr::sketch_job_chunks(v, (int)k, target);
+        rtr::sketch_job_fill(g, it.X, v, (int)k, it.seed, rtr::omega_stream(n), it.tensor_id, chunks,
+                             pbase + po, ybase + yo);
+        po += (size_t)chunks * v.In * k;
+        work.push_back(ybase + yo + (size_t)v.In * k);
+        qout.push_back(Qn);
+        yo += 2 * (size_t)v.In * k;
+        sk.push_back(g);
+        skstart.push_back(skstart.back() + rtr::sketch_job_blocks(g));
+        sp->sk_maxout = std::max(sp->sk_maxout, v.In * k);
+      } else {
+        sp->ident.push_back({Qn, it.dims[n]});
+      }
+      // mode product n of tensor t: cur -> cur with I_n replaced by K'_n
+      rtr::ModeView cv2 = mode_view(cur, it.order, n);
+      rtr::TtmJob tj{};
+      tj.in = in;
+      tj.A = cv2.A;
+      tj.In = cv2.In;
+      tj.B = cv2.B;
+      tj.K = (int)k;
+      tj.Q = Qn;
+      tj.out = (n + 1 == it.order) ? it.P : buf[n & 1];
+      tt[n].push_back(tj);
+      ttstart[n].push_back(ttstart[n].back() + rtr::ttm_job_blocks(tj, kc));
+      in = tj.out;
+      cur[n] = k;
+    }
+  }
+  sp->njobs = (int)sk.size();
+  sp->sk_blocks = skstart.back();
+  sp->steps = maxorder;
+  // one device array for every job list (uploaded synchronously, outside any capture)
+  Carve jp(nullptr);
+  jp.take<rtr::SketchJob>(sk.size());
+  jp.take<int64_t>(skstart.size());
+  jp.take<double*>(work.size());
+  jp.take<double*>(qout.size());
+  for (int n = 0; n < maxorder; ++n) {
+    jp.take<rtr::TtmJob>(tt[n].size());
+    jp.take<int64_t>(ttstart[n].size());
+  }
+  if (jp.off > h->jobs_cap) {
+    if (h->ws_locked) return fail(h, RTR_ERR_INTERNAL, "job lists grew inside a graph capture");
+    if (h->jobs_dev) {
+      HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+      (void)hipFree(h->jobs_dev);
+      h->jobs_dev = nullptr;
+      h->jobs_cap = 0;
+      ++h->ws_epoch;  // cached graphs read the old job arrays
+    }
+    HIP_TRY(hipMalloc(&h->jobs_dev, jp.off + 256), "hipMalloc");
+    h->jobs_cap = jp.off + 256;
+  }
+  std::vector<char> host(jp.off + 256);
+  Carve hc(host.data()), dc(h->jobs_dev);
+  auto put = [&](const void* src, size_t bytes, size_t cnt, size_t elem) {
+    void* hd = hc.take<char>(cnt * elem);
+    void* dd = dc.take<char>(cnt * elem);
+    if (bytes) std::memcpy(hd, src, bytes);
+    return dd;
+  };
+  sp->d_sk = (const rtr::SketchJob*)put(sk.data(), sk.size() * sizeof(rtr::SketchJob), sk.size(),
+                                         sizeof(rtr::SketchJob));
+  sp->d_skstart = (const int64_t*)put(skstart.data(), skstart.size() * 8, skstart.size(), 8);
+  sp->d_work = (double* const*)put(work.data(), work.size() * sizeof(double*), work.size(),
+                                   sizeof(double*));
+  sp->d_qout = (double* const*)put(qout.data(), qout.size() * sizeof(double*), qout.size(),
+                                   sizeof(double*));
+  sp->tt_n.assign(maxorder, 0);
+  sp->tt_blocks.assign(maxorder, 0);
+  sp->d_tt.assign(maxorder, nullptr);
+  sp->d_ttstart.assign(maxorder, nullptr);
+  for (int n = 0; n < maxorder; ++n) {
+    sp->tt_n[n] = (int)tt[n].size();
+    sp->tt_blocks[n] = ttstart[n].back();
+    sp->d_tt[n] = (const rtr::TtmJob*)put(tt[n].data(), tt[n].size() * sizeof(rtr::TtmJob),
+                                          tt[n].size(), sizeof(rtr::TtmJob));
+    sp->d_ttstart[n] = (const int64_t*)put(ttstart[n].data(), ttstart[n].size() * 8,
+                                           ttstart[n].size(), 8);
+  }
+  HIP_TRY(hipMemcpyAsync(h->jobs_dev, host.data(), hc.off, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return RTR_OK;
+}
+
+// The launches of a planned batch: sketches, sums, QR, then one mode product per mode.
+rtr_status launch_stream(rtr_context* h, const StreamPlan& sp, hipStream_t s, int only = 0) {
+  if (only != 2) {
+    for (const auto& id : sp.ident) HIP_TRY(rtr::launch_identity(id.first, id.second, s), "identity");
+    HIP_TRY(rtr::launch_sketch_list(sp.ar, sp.d_sk, sp.d_skstart, sp.njobs, sp.sk_blocks,
+                                    sp.sk_maxout, s),
+            "sketch_list");
+    HIP_TRY(rtr::launch_qr_list(sp.d_sk, sp.d_work, sp.d_qout, sp.njobs, s), "qr_list");
+  }
+  if (only != 1)
+    for (int n = 0; n < sp.steps; ++n)
+      HIP_TRY(rtr::launch_ttm_list(sp.ar, n == 0, sp.kc, sp.d_tt[n], sp.d_ttstart[n], sp.tt_n[n],
+                                   sp.tt_blocks[n], s),
+              "ttm_list");
+  return RTR_OK;
+}
+
 rtr_status batch_sequence(rtr_context* h, const rtr_batch_item* items, int32_t count,
                           rtr_dtype x_dtype, rtr_dtype compute, int32_t power_iters,
                           int32_t max_sweeps, double tol, const BatchPlan& plan,
-                          const rtr::AlsItem* dev, hipStream_t s, int nb = 1) {
+                          const rtr::AlsItem* dev, hipStream_t s, int nb = 1,
+                          const StreamPlan* sp = nullptr) {
   // Sketch and compression of every tensor.  With nb > 1 (graph capture only) tensor t goes
   // to branch stream t % nb with its own slice of the workspace, so that the launches of small
   // tensors, which leave most of the chip idle, overlap; the branches join before TR-ALS.
@@ -1189,7 +1721,11 @@ rtr_status batch_sequence(rtr_context* h, const rtr_batch_item* items, int32_t c
     h->ws_locked = true;
   }
   rtr_status st = RTR_OK;
-  for (int t = 0; t < count && !st; ++t) {
+  if (sp) {
+    Guard guard(h);
+    st = launch_stream(h, *sp, s);
+  }
+  for (int t = 0; t < count && !st && !sp; ++t) {
     const rtr_batch_item& it = items[t];
     hipStream_t ts = nb > 1 ? h->br[t % nb] : s;
     if (nb > 1) {
@@ -1225,6 +1761,79 @@ rtr_status batch_sequence(rtr_context* h, const rtr_batch_item* items, int32_t c
 
 }  // namespace
 
+rtr_status rtr_batch_autotune(rtr_handle h, const rtr_batch_item* items, int32_t count,
+                              rtr_dtype x_dtype, rtr_dtype compute, int32_t* table,
+                              void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  if (!items || count < 1 || !table) return fail(h, RTR_ERR_INVALID_ARG, "items, count, table");
+  if (!kBatchWorkLists)
+    return fail(h, RTR_ERR_UNSUPPORTED, "the batched work lists are switched off in this build");
+  if (!stream_eligible(items, count, x_dtype, 0))
+    return fail(h, RTR_ERR_UNSUPPORTED, "the batched work lists take FP32 X and K'_n <= 64");
+  rtr::Arith ar;
+  if ((st = check_arith(h, x_dtype, compute, &ar))) return st;
+  ar = not_fp8(ar);
+  for (int t = 0; t < count; ++t) {
+    const rtr_batch_item& it = items[t];
+    if (it.order < 2 || it.order > RTR_MAX_ORDER || !it.X || !it.Q || !it.P)
+      return fail(h, RTR_ERR_INVALID_ARG, "item " + std::to_string(t) + ": order, X, Q, P");
+    const std::string where = "item " + std::to_string(t) + ": ";
+    rtr_status sc;
+    if ((sc = check_dev(h, it.X, x_bytes(it.dims, it.order, x_dtype), (where + "X").c_str())) ||
+        (sc = check_dev(h, it.Q, q_bytes(it.dims, it.K, it.order), (where + "Q").c_str())))
+      return sc;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+  HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+  // mean time of ``reps`` runs of one part of the work lists (after one untimed run)
+  auto clock = [&](const StreamPlan& sp, int part, float* us) -> rtr_status {
+    rtr_status r;
+    if ((r = launch_stream(h, sp, s, part))) return r;
+    HIP_TRY(hipEventRecord(e0, s), "hipEventRecord");
+    for (int i = 0; i < 3; ++i)
+      if ((r = launch_stream(h, sp, s, part))) return r;
+    HIP_TRY(hipEventRecord(e1, s), "hipEventRecord");
+    HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    *us = ms * 1e3f / 3.f;
+    return RTR_OK;
+  };
+  const int targets[3] = {16, 64, 256}, kcs[3] = {4, 16, 64};
+  float tt[3], tk[3];
+  int best_t = 0, best_k = 0;
+  Guard guard(h);
+  for (int i = 0; i < 3; ++i) {
+    StreamPlan sp;
+    if ((st = plan_stream(h, items, count, ar, targets[i], 16, s, &sp))) break;
+    if ((st = clock(sp, 1, &tt[i]))) break;
+    if (tt[i] < tt[best_t]) best_t = i;
+  }
+  for (int i = 0; i < 3 && !st; ++i) {
+    StreamPlan sp;
+    if ((st = plan_stream(h, items, count, ar, targets[best_t], kcs[i], s, &sp))) break;
+    if ((st = clock(sp, 2, &tk[i]))) break;
+    if (tk[i] < tk[best_k]) best_k = i;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  h->bt_target = targets[best_t];
+  h->bt_kc = kcs[best_k];
+  table[0] = h->bt_target;
+  table[1] = h->bt_kc;
+  for (int i = 0; i < 3; ++i) {
+    table[2 + i] = (int32_t)(tt[i] + 0.5f);
+    table[5 + i] = (int32_t)(tk[i] + 0.5f);
+  }
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
 rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t count,
                          rtr_dtype x_dtype, rtr_dtype compute, int32_t power_iters,
                          int32_t max_sweeps, double tol, int32_t use_graph, void* stream) try {
@@ -1236,7 +1845,7 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
   // its arguments were validated when it was captured.
   uint64_t key = 1469598103934665603ull;
   key = fnv(key, items, sizeof(rtr_batch_item) * (size_t)count);
-  const int64_t params[5] = {count, x_dtype, compute, power_iters, max_sweeps};
+  const int64_t params[7] = {count, x_dtype, compute, power_iters, max_sweeps, h->bt_target, h->bt_kc};
   key = fnv(key, params, sizeof(params));
   key = fnv(key, &tol, sizeof(tol));
   if (use_graph && h->gexec && key == h->gkey && h->gepoch == h->ws_epoch) {
@@ -1282,6 +1891,15 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
     st = plan_batch(h, als.data(), count, max_sweeps, tol, &plan);
     if (st) return st;
   }
+  // the work lists of every tensor's sketch and compression, where the batch allows them
+  StreamPlan splan;
+  const bool streamed = stream_eligible(items, count, x_dtype, power_iters);
+  if (streamed) {
+    rtr::Arith ar;
+    if ((st = check_arith(h, x_dtype, compute, &ar))) return st;
+    Guard guard(h);
+    if ((st = plan_stream(h, items, count, not_fp8(ar), h->bt_target, h->bt_kc, s, &splan))) return st;
+  }
   // eager run (also sizes the workspace for the capture below)
   h->ws_hi = 0;
   rtr::AlsItem* dev = nullptr;
@@ -1290,13 +1908,15 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
     st = upload_items(h, plan.items, s, &dev);
     if (st) return st;
   }
-  st = batch_sequence(h, items, count, x_dtype, compute, power_iters, max_sweeps, tol, plan, dev, s);
+  st = batch_sequence(h, items, count, x_dtype, compute, power_iters, max_sweeps, tol, plan, dev, s, 1,
+                      streamed ? &splan : nullptr);
   if (st || !use_graph) return st;
   // capture the same sequence into a graph over a dedicated copy of the item array
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
   const size_t bytes = plan.items.size() * sizeof(rtr::AlsItem);
   if (bytes > h->gitems_cap) {
     if (h->gitems_dev) (void)hipFree(h->gitems_dev);
+  if (h->jobs_dev) (void)hipFree(h->jobs_dev);
     h->gitems_dev = nullptr;
     h->gitems_cap = 0;
     HIP_TRY(hipMalloc(&h->gitems_dev, bytes), "hipMalloc");
@@ -1304,7 +1924,7 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
   }
   HIP_TRY(hipMemcpy(h->gitems_dev, plan.items.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy");
   if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
-  const int nb = std::min(kBatchBranches, count);
+  const int nb = streamed ? 1 : std::min(kBatchBranches, count);
   if (nb > 1) {
     for (int b = 0; b < nb; ++b) {
       if (!h->br[b]) HIP_TRY(hipStreamCreateWithFlags(&h->br[b], hipStreamNonBlocking), "hipStreamCreate");
@@ -1327,7 +1947,8 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
   const int epoch = h->ws_epoch;
   HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
   st = batch_sequence(h, items, count, x_dtype, compute, power_iters, max_sweeps, tol, plan,
-                      (const rtr::AlsItem*)h->gitems_dev, h->cap_stream, nb);
+                      (const rtr::AlsItem*)h->gitems_dev, h->cap_stream, nb,
+                      streamed ? &splan : nullptr);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
   h->prof_level = prof;
@@ -1443,6 +2064,26 @@ rtr_status rtr_mlp_forward(rtr_handle h, int32_t layers, const int32_t* sizes,
                   part, b[l], nullptr, l < layers - 1 ? 1 : 0, out, s);
     if (st) return st;
   }
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+rtr_status rtr_mlp_core_loss(rtr_handle h, const float* y, const float* target, int32_t batch,
+                             int64_t per_row, float grad_scale, float* loss, float* dy,
+                             void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if (batch < 1 || per_row < 1 || per_row > (1 << 30))
+    return fail(h, RTR_ERR_INVALID_ARG, "need batch >= 1 and 1 <= per_row <= 2^30");
+  CHECK_DEV(y, (size_t)batch * per_row * sizeof(float), "y");
+  CHECK_DEV(target, (size_t)batch * per_row * sizeof(float), "target");
+  CHECK_DEV(dy, (size_t)batch * per_row * sizeof(float), "dy");
+  CHECK_DEV(loss, (size_t)batch * sizeof(float), "loss");
+  HIP_TRY(rtr::launch_core_loss(y, target, (int)per_row, grad_scale, batch, loss, dy,
+                                (hipStream_t)stream),
+          "core loss");
   return RTR_OK;
 } catch (...) {
   return fail(h, RTR_ERR_INTERNAL, "unexpected exception");

@@ -41,37 +41,58 @@ constexpr int kSkTJ = 32;   // columns per tile
 constexpr int kSkKMax = 64; // projection size limit of the general kernel
 constexpr int kSkThreads = 256;
 
+// One work-group's share of a sketch: column tiles [t0, t1) of X_(n), rows [i0, i0 + 64),
+// accumulated into out[(i) * K + k] (this work-group's partial record, In x K).
 template <int AR>
-__global__ __launch_bounds__(kSkThreads) void sketch_partial_kernel(
-    const typename Ar<AR>::X* __restrict__ X, int64_t A, int64_t In, int64_t B, int K,
-    uint64_t seed, uint32_t stream, uint32_t tid, int64_t ntiles, int64_t tiles_per_chunk,
-    typename Ar<AR>::Acc* __restrict__ partial) {
+__device__ __forceinline__ void sketch_range(const typename Ar<AR>::X* __restrict__ X, int64_t A,
+                                             int64_t In, int64_t B, int K, uint64_t seed,
+                                             uint32_t stream, uint32_t tid, int64_t t0, int64_t t1,
+                                             int64_t i0, typename Ar<AR>::Acc* __restrict__ out,
+                                             const KrArgs& kr) {
   using Acc = typename Ar<AR>::Acc;
   __shared__ Acc Xs[kSkTI][kSkTJ + 1];
   __shared__ Acc Om[kSkTJ * kSkKMax];
   __shared__ int64_t colbase[kSkTJ];
   const int64_t J = A * B;
-  const int64_t chunk = blockIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.y * kSkTI;
   const int il = threadIdx.x % kSkTI;
   const int kg = threadIdx.x / kSkTI;  // 4 groups of columns k = kg + 4q
   Acc acc[kSkKMax / 4];
 #pragma unroll
   for (int q = 0; q < kSkKMax / 4; ++q) acc[q] = 0;
 
-  const int64_t t0 = chunk * tiles_per_chunk;
-  const int64_t t1 = min(ntiles, t0 + tiles_per_chunk);
   for (int64_t t = t0; t < t1; ++t) {
     const int64_t j0 = t * kSkTJ;
     const int64_t jn = min((int64_t)kSkTJ, J - j0);
     const int64_t e0 = j0 * K, e1 = (j0 + jn) * K;
-    for (int64_t c = (e0 >> 2) + threadIdx.x; c <= ((e1 - 1) >> 2); c += kSkThreads) {
-      Acc z[4];
-      normals4(seed, stream, tid, (uint64_t)c, z);
+    if (kr.f) {  // Khatri-Rao test matrix: products of the other modes' factor rows
+      const Acc* F = (const Acc*)kr.f;
+      for (int x = threadIdx.x; x < jn * K; x += kSkThreads) {
+        const int jj = x / K, k = x % K;
+        int64_t r = j0 + jj;
+        int64_t row[7];
 #pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        const int64_t e = 4 * c + l;
-        if (e >= e0 && e < e1) Om[e - e0] = Ar<AR>::rnd(z[l]);
+        for (int m = 6; m >= 0; --m) {
+          if (m < kr.nm) {
+            const int d = kr.dim[m];
+            row[m] = kr.off[m] + (r % d) * kr.ld;
+            r /= d;
+          }
+        }
+        Acc v = 1;
+#pragma unroll
+        for (int m = 0; m < 7; ++m)
+          if (m < kr.nm) v *= F[row[m] + k];
+        Om[x] = Ar<AR>::rnd(v);
+      }
+    } else {
+      for (int64_t c = (e0 >> 2) + threadIdx.x; c <= ((e1 - 1) >> 2); c += kSkThreads) {
+        Acc z[4];
+        normals4(seed, stream, tid, (uint64_t)c, z);
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          const int64_t e = 4 * c + l;
+          if (e >= e0 && e < e1) Om[e - e0] = Ar<AR>::rnd(z[l]);
+        }
       }
     }
     for (int x = (int)(jn * K) + threadIdx.x; x < kSkTJ * K; x += kSkThreads) Om[x] = 0;
@@ -111,9 +132,21 @@ __global__ __launch_bounds__(kSkThreads) void sketch_partial_kernel(
 #pragma unroll
     for (int q = 0; q < kSkKMax / 4; ++q) {
       const int k = kg + 4 * q;
-      if (k < K) partial[(chunk * In + i) * K + k] = acc[q];
+      if (k < K) out[i * K + k] = acc[q];
     }
   }
+}
+
+template <int AR>
+__global__ __launch_bounds__(kSkThreads) void sketch_partial_kernel(
+    const typename Ar<AR>::X* __restrict__ X, int64_t A, int64_t In, int64_t B, int K,
+    uint64_t seed, uint32_t stream, uint32_t tid, int64_t ntiles, int64_t tiles_per_chunk,
+    typename Ar<AR>::Acc* __restrict__ partial, KrArgs kr) {
+  const int64_t chunk = blockIdx.x;
+  const int64_t t0 = chunk * tiles_per_chunk;
+  const int64_t t1 = min(ntiles, t0 + tiles_per_chunk);
+  sketch_range<AR>(X, A, In, B, K, seed, stream, tid, t0, t1, (int64_t)blockIdx.y * kSkTI,
+                   partial + chunk * In * K, kr);
 }
 
 int64_t sketch_chunks(const ModeView& v, int K) {
@@ -129,8 +162,10 @@ int64_t sketch_chunks(const ModeView& v, int K) {
 
 hipError_t launch_sketch_partial(Arith ar, const void* X, const ModeView& v, int K,
                                  uint64_t seed, uint32_t stream_word, uint32_t tensor_id,
-                                 void* partial, int64_t chunks, hipStream_t s) {
+                                 void* partial, int64_t chunks, hipStream_t s, const KrArgs* kr) {
   if (K > kSkKMax) return hipErrorInvalidValue;
+  KrArgs ka{};
+  if (kr) ka = *kr;
   const int64_t J = v.A * v.B;
   const int64_t ntiles = (J + kSkTJ - 1) / kSkTJ;
   const int64_t per = (ntiles + chunks - 1) / chunks;
@@ -141,17 +176,17 @@ hipError_t launch_sketch_partial(Arith ar, const void* X, const ModeView& v, int
     case kF64:
       hipLaunchKernelGGL(sketch_partial_kernel<kF64>, grid, dim3(kSkThreads), 0, s,
                          (const double*)X, v.A, v.In, v.B, K, seed, stream_word, tensor_id,
-                         ntiles, per, (double*)partial);
+                         ntiles, per, (double*)partial, ka);
       break;
     case kF32:
       hipLaunchKernelGGL(sketch_partial_kernel<kF32>, grid, dim3(kSkThreads), 0, s,
                          (const float*)X, v.A, v.In, v.B, K, seed, stream_word, tensor_id,
-                         ntiles, per, (float*)partial);
+                         ntiles, per, (float*)partial, ka);
       break;
     default:
       hipLaunchKernelGGL(sketch_partial_kernel<kBF16>, grid, dim3(kSkThreads), 0, s,
                          (const float*)X, v.A, v.In, v.B, K, seed, stream_word, tensor_id,
-                         ntiles, per, (float*)partial);
+                         ntiles, per, (float*)partial, ka);
   }
   prof_end(s);
   return hipGetLastError();
@@ -323,13 +358,13 @@ hipError_t launch_power_partial(Arith ar, const void* X, const ModeView& v, int 
 // owns 64 consecutive outputs; its 16 wavefronts take every 16th chunk each (coalesced
 // along the outputs), and the 16 slice sums are added in a fixed order.
 template <typename P>
-__global__ __launch_bounds__(1024) void reduce_partials_kernel(const P* __restrict__ partial,
-                                                               int64_t chunks, int64_t In, int K,
-                                                               double* __restrict__ Ycol) {
+__device__ __forceinline__ void reduce_block(const P* __restrict__ partial, int64_t chunks,
+                                             int64_t In, int K, double* __restrict__ Ycol,
+                                             int64_t ldy, int64_t oblock) {
   __shared__ double part[16][65];
   const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
   const int64_t nout = In * K;
-  const int64_t o = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t o = oblock * 64 + lane;
   double s = 0.0;
   if (o < nout)
     for (int64_t c = slice; c < chunks; c += 16) s += (double)partial[c * nout + o];
@@ -341,21 +376,102 @@ __global__ __launch_bounds__(1024) void reduce_partials_kernel(const P* __restri
     for (int q = 0; q < 16; ++q) t += part[q][lane];
     const int64_t i = o / K;
     const int k = (int)(o % K);
-    Ycol[(int64_t)k * In + i] = t;
+    Ycol[(int64_t)k * ldy + i] = t;
   }
 }
 
+template <typename P>
+__global__ __launch_bounds__(1024) void reduce_partials_kernel(const P* __restrict__ partial,
+                                                               int64_t chunks, int64_t In, int K,
+                                                               double* __restrict__ Ycol,
+                                                               int64_t ldy) {
+  reduce_block<P>(partial, chunks, In, K, Ycol, ldy, blockIdx.x);
+}
+
 hipError_t launch_reduce_partials(Arith ar, const void* partial, int64_t chunks, int64_t In,
-                                  int K, double* Ycol, hipStream_t s) {
+                                  int K, double* Ycol, hipStream_t s, int64_t ldy) {
+  if (ldy == 0) ldy = In;
   const int64_t nout = In * K;
   const unsigned blocks = (unsigned)((nout + 63) / 64);
   prof_begin("reduce_partials", s);
   if (ar == kF64)
     hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(blocks), dim3(1024), 0, s,
-                       (const double*)partial, chunks, In, K, Ycol);
+                       (const double*)partial, chunks, In, K, Ycol, ldy);
   else
     hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(blocks), dim3(1024), 0, s,
-                       (const float*)partial, chunks, In, K, Ycol);
+                       (const float*)partial, chunks, In, K, Ycol, ldy);
+  prof_end(s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Work lists for many tensors at once (the batched workload): one launch sketches every
+// (tensor, mode) job, one launch sums every job's partials.  Job j owns blocks
+// [block_start[j], block_start[j + 1]) of the grid; a block finds its job by binary search.
+template <int AR>
+__global__ __launch_bounds__(kSkThreads) void sketch_list_kernel(const SketchJob* __restrict__ jobs,
+                                                                 const int64_t* __restrict__ block_start,
+                                                                 int njobs) {
+  const int j = find_job(block_start, njobs, blockIdx.x);
+  const SketchJob g = jobs[j];
+  const int64_t local = (int64_t)blockIdx.x - block_start[j];
+  const int64_t chunk = local / g.nrb, rb = local % g.nrb;
+  const int64_t t0 = chunk * g.per;
+  const int64_t t1 = min(g.ntiles, t0 + g.per);
+  KrArgs none{};
+  sketch_range<AR>((const typename Ar<AR>::X*)g.X, g.A, g.In, g.B, g.K, g.seed, g.stream,
+                   g.tensor_id, t0, t1, rb * kSkTI,
+                   (typename Ar<AR>::Acc*)g.partial + chunk * g.In * g.K, none);
+}
+
+__global__ __launch_bounds__(1024) void reduce_list_kernel(const SketchJob* __restrict__ jobs) {
+  const SketchJob g = jobs[blockIdx.y];
+  if ((int64_t)blockIdx.x * 64 >= g.In * g.K) return;
+  reduce_block<float>((const float*)g.partial, g.chunks, g.In, g.K, g.Ycol, g.In, blockIdx.x);
+}
+
+int64_t sketch_job_chunks(const ModeView& v, int K, int target) {
+  const int64_t J = v.A * v.B;
+  const int64_t ntiles = (J + kSkTJ - 1) / kSkTJ;
+  int64_t chunks = ntiles < target ? ntiles : target;
+  if (chunks < 1) chunks = 1;
+  const int64_t per = (ntiles + chunks - 1) / chunks;
+  return (ntiles + per - 1) / per;
+}
+
+void sketch_job_fill(SketchJob& g, const void* X, const ModeView& v, int K, uint64_t seed,
+                     uint32_t stream_word, uint32_t tensor_id, int64_t chunks, void* partial,
+                     double* Ycol) {
+  g.X = X;
+  g.A = v.A;
+  g.In = v.In;
+  g.B = v.B;
+  g.K = K;
+  g.seed = seed;
+  g.stream = stream_word;
+  g.tensor_id = tensor_id;
+  g.ntiles = (v.A * v.B + kSkTJ - 1) / kSkTJ;
+  g.per = (g.ntiles + chunks - 1) / chunks;
+  g.chunks = chunks;
+  g.nrb = (int)((v.In + kSkTI - 1) / kSkTI);
+  g.partial = partial;
+  g.Ycol = Ycol;
+}
+
+int64_t sketch_job_blocks(const SketchJob& g) { return g.chunks * g.nrb; }
+
+hipError_t launch_sketch_list(Arith ar, const SketchJob* jobs, const int64_t* block_start,
+                              int njobs, int64_t blocks, int64_t max_out, hipStream_t s) {
+  if (njobs < 1) return hipSuccess;
+  prof_begin("sketch_list", s);
+  if (ar == kBF16)
+    hipLaunchKernelGGL(sketch_list_kernel<kBF16>, dim3((unsigned)blocks), dim3(kSkThreads), 0, s,
+                       jobs, block_start, njobs);
+  else
+    hipLaunchKernelGGL(sketch_list_kernel<kF32>, dim3((unsigned)blocks), dim3(kSkThreads), 0, s,
+                       jobs, block_start, njobs);
+  hipLaunchKernelGGL(reduce_list_kernel, dim3((unsigned)((max_out + 63) / 64), (unsigned)njobs),
+                     dim3(1024), 0, s, jobs);
   prof_end(s);
   return hipGetLastError();
 }

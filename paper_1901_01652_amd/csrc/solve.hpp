@@ -9,9 +9,10 @@ namespace rtr {
 // pivoting (the Gram is symmetric positive definite, every pivot is a Schur-complement
 // diagonal).  Thread t owns elements e = t + nth*q, q < QMAX, in registers.  Step k: the
 // owners of row k and column k publish them to LDS (double-buffered), one barrier, then every
-// element is updated.  Leaves [I | Gram^-1 M^T]; returns false on a non-positive pivot.
-template <int QMAX>
-__device__ bool gauss_jordan(const double* G, const double* M, double* X, double* rowbuf,
+// element is updated.  Leaves [I | Gram^-1 M^T] and hands every solution entry (r, i) of
+// Gram^-1 M^T to store(r, i, value); returns false on a non-positive pivot.
+template <int QMAX, typename Store>
+__device__ bool gauss_jordan(const double* G, const double* M, Store store, double* rowbuf,
                              double* colbuf, int RR, int Kn, int* failed) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int W = RR + Kn, ne = RR * W;
@@ -58,8 +59,16 @@ __device__ bool gauss_jordan(const double* G, const double* M, double* X, double
   }
 #pragma unroll
   for (int q = 0; q < QMAX; ++q)
-    if (rr[q] >= 0 && cc[q] >= RR) X[rr[q] * Kn + (cc[q] - RR)] = a[q];
+    if (rr[q] >= 0 && cc[q] >= RR) store(rr[q], cc[q] - RR, a[q]);
   return true;
+}
+
+// The same with the solution written to X (RR x Kn, row-major).
+template <int QMAX>
+__device__ bool gauss_jordan(const double* G, const double* M, double* X, double* rowbuf,
+                             double* colbuf, int RR, int Kn, int* failed) {
+  return gauss_jordan<QMAX>(G, M, [=](int r, int i, double v) { X[r * Kn + i] = v; }, rowbuf,
+                            colbuf, RR, Kn, failed);
 }
 
 }  // namespace rtr

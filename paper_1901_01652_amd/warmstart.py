@@ -11,9 +11,9 @@ and the conversions run in the library's kernels.
 import numpy as np
 import torch
 
-from . import (rtr_compress, rtr_decompose, rtr_mlp_adam, rtr_mlp_backward, rtr_mlp_forward,
-               rtr_mlp_normalize, rtr_mlp_to_cores, rtr_mlp_tr_loss, rtr_sketch, core_shapes,
-               pack)
+from . import (rtr_compress, rtr_decompose, rtr_mlp_adam, rtr_mlp_backward, rtr_mlp_core_loss,
+               rtr_mlp_forward, rtr_mlp_normalize, rtr_mlp_to_cores, rtr_mlp_tr_loss, rtr_sketch,
+               core_shapes, pack)
 
 
 class WarmStart:
@@ -50,6 +50,16 @@ class WarmStart:
         loss as a device scalar."""
         y, acts = self.forward(x)
         loss, dy = rtr_mlp_tr_loss(self.h, y, x, self.K, self.R, 1.0 / x.shape[0])
+        dW, db = rtr_mlp_backward(self.h, self.W, x, acts, dy, compute=self.compute)
+        self.step += 1
+        for p, gr, m, v in zip(self.W + self.b, dW + db, self.m, self.v):
+            rtr_mlp_adam(self.h, p, gr, m, v, self.step, lr)
+        return loss.mean()
+
+    def train_step_supervised(self, x, t, lr=1e-3):
+        """One Adam step on the supervised core loss against targets t (B x packed cores)."""
+        y, acts = self.forward(x)
+        loss, dy = rtr_mlp_core_loss(self.h, y, t, 1.0 / x.shape[0])
         dW, db = rtr_mlp_backward(self.h, self.W, x, acts, dy, compute=self.compute)
         self.step += 1
         for p, gr, m, v in zip(self.W + self.b, dW + db, self.m, self.v):
@@ -134,4 +144,61 @@ def train(model, data, epochs, batch=256, lr=1e-3, seed=0, log=None):
         hist.append(tot / max(cnt, 1))
         if log:
             log(f"[warm-start] epoch {ep}: loss {hist[-1]:.5f}")
+    return hist
+
+
+def train_until(model, data, max_epochs=200, batch=256, lr=1e-3, window=5, rel_tol=1e-3,
+                seed=0, log=None):
+    """Mini-batch Adam until the loss plateaus: stop once the mean loss of the last ``window``
+    epochs differs from that of the ``window`` before by less than ``rel_tol`` (relative), or
+    after ``max_epochs``.  Returns the per-epoch mean losses."""
+    hist = []
+    for ep in range(max_epochs):
+        hist += train(model, data, 1, batch, lr, seed + ep)
+        if log:
+            log(f"[warm-start] epoch {ep}: loss {hist[-1]:.6f}")
+        if len(hist) >= 2 * window:
+            a = sum(hist[-window:]) / window
+            b = sum(hist[-2 * window:-window]) / window
+            if abs(a - b) <= rel_tol * abs(b):
+                break
+    return hist
+
+
+def method_targets(h, data, K, R, Z0, sweeps=30):
+    """Cores the method itself produces for each normalised projected tensor (rows of ``data``):
+    TR-ALS from the one fixed set of initial cores ``Z0`` (packed, device), so that every
+    target is in the gauge that ALS reaches from the same start.  Returns B x packed FP32."""
+    B = data.shape[0]
+    out = torch.empty((B, Z0.numel()), dtype=torch.float32, device=data.device)
+    for r in range(B):
+        P = data[r].reshape(list(K)).to(torch.float64)
+        Z, _, _ = rtr_decompose(h, P, R, Z0, sweeps)
+        out[r].copy_(Z)
+    return out
+
+
+def train_supervised(model, data, targets, max_epochs=200, batch=256, lr=1e-3, window=5,
+                     rel_tol=1e-3, seed=0, log=None):
+    """Mini-batch Adam on the supervised core loss until it plateaus (as ``train_until``)."""
+    g = torch.Generator(device="cpu").manual_seed(int(seed))
+    n = data.shape[0]
+    hist = []
+    for ep in range(max_epochs):
+        order = torch.randperm(n, generator=g).to(data.device)
+        tot, cnt = 0.0, 0
+        for s in range(0, n - batch + 1, batch):
+            idx = order[s:s + batch]
+            x = data.index_select(0, idx).contiguous()
+            t = targets.index_select(0, idx).contiguous()
+            tot += float(model.train_step_supervised(x, t, lr))
+            cnt += 1
+        hist.append(tot / max(cnt, 1))
+        if log:
+            log(f"[warm-start] epoch {ep}: core loss {hist[-1]:.6f}")
+        if len(hist) >= 2 * window:
+            a = sum(hist[-window:]) / window
+            b = sum(hist[-2 * window:-window]) / window
+            if abs(a - b) <= rel_tol * abs(b):
+                break
     return hist

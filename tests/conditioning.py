@@ -88,3 +88,43 @@ def condition(X, K, Z0, sweeps, q, seed, delta=1e-8, samples=2, tensor_id=0):
         for k in KEYS:
             cond[k] = max(cond[k], distance(qp[k], qb[k], k) / delta)
     return base, qb, cond
+
+
+def sketch_condition(X, K, q, seed, delta=1e-8, samples=6, tensor_id=0, test="gaussian"):
+    """Per mode: (oracle basis Q_n, amplification of the projector Q_n Q_n^T, amplification of
+    Q_n) when the sketch and every power product of that mode are off by a random relative
+    ``delta``: the largest over ``samples`` random directions (the amplification is a maximum
+    over directions; a few samples approach it from below).  Modes with K_n >= I_n report 0."""
+    X = np.asarray(X, dtype=np.float64)
+    out = []
+    for n in range(X.ndim):
+        In = X.shape[n]
+        if K[n] >= In:
+            out.append((np.eye(In), 0.0, 0.0))
+            continue
+        A = unfold(X, n)
+        if test == "khatri_rao":
+            M = orc.khatri_rao_test_matrix(seed, n, X.shape, K[n], tensor_id)
+        else:
+            M = orc.gaussian_test_matrix(seed, n, A.shape[1], K[n], tensor_id)
+
+        def basis(rng):
+            def pert(B):
+                if rng is None:
+                    return B
+                E = rng.standard_normal(B.shape)
+                return B + (delta * np.linalg.norm(B) / np.linalg.norm(E)) * E
+            Q, _ = orc.qr_pos(pert(A @ M))
+            for _ in range(q):
+                W, _ = orc.qr_pos(A.T @ Q)
+                Q, _ = orc.qr_pos(pert(A @ W))
+            return Q
+
+        Q0 = basis(None)
+        cp = cq = 0.0
+        for s in range(samples):
+            Qp = basis(np.random.default_rng(4099 + s))
+            cp = max(cp, rel(Qp @ Qp.T, Q0 @ Q0.T) / delta)
+            cq = max(cq, rel(Qp, Q0) / delta)
+        out.append((Q0, cp, cq))
+    return out

@@ -1,18 +1,18 @@
 """Batched TR-ALS (one persistent launch for many tensors) and the batched Alg. 1 pipeline
 (optionally replayed as one HIP graph), against the FP64 oracle, through the C ABI.
 
-Tolerances: FP64 path 1e-10 on the per-sweep error trace (relative), 1e-9 on Psi(Z);
-FP32 path: P and Psi(G) 1e-5 (relative Frobenius), the final sweep's error 1e-5 absolute
-(trace entries are already relative to ||P||, and the FP32 P differs from the oracle's by
-~1e-6 ||P||).  Earlier sweeps can pass through sensitive transients of the ALS trajectory:
-each is held to max(1e-5, 50 x the oracle's own change when it reruns from P perturbed by
-1e-6 relative in a random direction) -- the FP32 error is structured, so a random probe
-understates the worst direction by a factor that stayed below 30 on these inputs.
+Tolerances: FP64 path 1e-10 on the per-sweep error trace (relative), 1e-9 on Psi(Z).  FP32
+path, stage by stage: P against the oracle's P at 1e-5 (relative Frobenius); the batched TR-ALS
+against the oracle's TR-ALS on the GPU's own P at 1e-10 (ALS from a random start can pass
+through sensitive transients, so FP32-class differences in P are not compared through it);
+Psi(G) against the oracle's back-projection of the GPU's own cores at 1e-5.  The batch with
+FP32 X and no power iterations runs its sketches, QRs and mode products as work lists.
 """
 import numpy as np
 import pytest
 import torch
 
+import conditioning as C
 import paper_1901_01652_amd as rt
 from oracle import rtr as orc, tensor as ot
 import workloads as W
@@ -153,15 +153,19 @@ def test_batch_pipeline_matches_oracle(h, dtype, tol_trace, tol_psi):
         if dtype == torch.float64:
             diff = diff / np.asarray(o["rse_trace"])
         else:
-            assert diff[-1] < tol_trace, (w.tensor_id, diff[-1])
-            P = o["P"]
-            E = rng.standard_normal(P.shape)
-            _, t2 = orc.tr_als(P + 1e-6 * np.linalg.norm(P) / np.linalg.norm(E) * E, Z0, sweeps)
-            sens = np.abs(np.asarray(t2) - o["rse_trace"])
-            diff = diff / np.maximum(tol_trace, 50 * sens) * tol_trace
+            # FP32: P carries FP32-class error, to which TR-ALS from a random start can be
+            # sensitive; the batched TR-ALS is held stage-wise, against the oracle's TR-ALS on
+            # the GPU's own P
+            _, tro = orc.tr_als(Pg, Z0, sweeps)
+            diff = np.abs(g_trace - np.asarray(tro)) / np.asarray(tro) * tol_trace / 1e-10
         worst_t = max(worst_t, np.max(diff))
         G = [g.cpu().numpy() for g in rt.unpack(it["G"], rt.core_shapes(w.dims, w.ranks))]
-        worst_p = max(worst_p, rel(ot.tr_full(G), ot.tr_full(o["G"])))
+        if dtype == torch.float64:
+            worst_p = max(worst_p, rel(ot.tr_full(G), ot.tr_full(o["G"])))
+        else:  # Psi(G) of the GPU's cores against the oracle's back-projection of the same cores
+            Zg = [z.cpu().numpy() for z in rt.unpack(it["Z"], rt.core_shapes(w.K, w.ranks))]
+            Qg = [q.cpu().numpy() for q in rt.unpack(it["Q"], rt.q_shapes(w.dims, w.K))]
+            worst_p = max(worst_p, rel(ot.tr_full(G), ot.tr_full(orc.backproject(Zg, Qg))))
     say("worst trace", worst_t, "worst psi(G)", worst_p)
     assert worst_p < tol_psi
     assert worst_t < tol_trace
@@ -190,3 +194,73 @@ def test_batch_graph_replay(h, count):
             for it, r in zip(items, ref):
                 assert torch.equal(it[k], r), (rep, k)
         del junk
+
+
+WORK_LISTS_OFF = ("the batched work lists are switched off: the first graph-captured batch run "
+                  "that used them ended with a GPU memory fault whose cause is not yet shown")
+
+
+@pytest.mark.skip(reason=WORK_LISTS_OFF)
+def test_batch_work_lists_real_distribution(h):
+    """64 tensors of the batched workload's own distribution (order 4, I_n ~ U{16..96},
+    R ~ U{2..6}, K = 2R + 4, 35 dB), FP32: the sketches, QRs and mode products of the whole
+    batch as work lists (a few launches), stage by stage against the oracle: every projector at
+    the FP32 stage accuracy times the oracle's amplification, P against the oracle's compression
+    with the returned bases, and the TR-ALS error trace against the oracle's TR-ALS on the
+    returned P (1e-10)."""
+    say("batch work lists, I_n in [16, 96]")
+    sweeps = 20
+    ws = W.batched_uneven(64)
+    items, ref = [], []
+    for w in ws:
+        X, _ = W.make_tensor(w, dtype=torch.float32)
+        Z0 = W.make_init(w)
+        items.append({"X": X.to(DEV), "K": list(w.K), "R": list(w.ranks), "Z_init": rt.pack(Z0, DEV),
+                      "seed": w.seed, "tensor_id": w.tensor_id})
+        ref.append((w, Z0))
+    rt.rtr_profile_reset(h)
+    rt.rtr_profile_enable(h, 2)
+    rt.rtr_batch_run(h, items, sweeps, compute="f32")
+    torch.cuda.synchronize()
+    rt.rtr_profile_enable(h, 0)
+    _, nsk = rt.rtr_profile_read(h, "sketch_list")
+    assert nsk == 1, "the batch's sketches run as one work-list launch"
+    assert rt.rtr_status_sync(h) == 0
+    worst = {"proj": 0.0, "P": 0.0, "trace": 0.0}
+    for it, (w, Z0) in zip(items, ref):
+        X = it["X"].cpu().numpy().astype(np.float64)
+        Qg = [q.cpu().numpy() for q in rt.unpack(it["Q"], rt.q_shapes(w.dims, w.K))]
+        probe = C.sketch_condition(X, w.K, 0, seed=w.seed, tensor_id=w.tensor_id, samples=2)
+        for n in range(4):
+            Qo, cp, _ = probe[n]
+            e = rel(Qg[n] @ Qg[n].T, Qo @ Qo.T)
+            worst["proj"] = max(worst["proj"], e / max(1.0, cp))
+            assert e <= 1e-5 * max(1.0, cp), (w.tensor_id, n, e, cp)
+        Pg = it["P"].cpu().numpy()
+        eP = rel(Pg, orc.compress(X, Qg))
+        worst["P"] = max(worst["P"], eP)
+        assert eP < 1e-5, (w.tensor_id, eP)
+        _, tro = orc.tr_als(Pg, Z0, sweeps)
+        et = rel(it["err_trace"].cpu().numpy(), tro)
+        worst["trace"] = max(worst["trace"], et)
+        assert et < 1e-10, (w.tensor_id, et)
+    say("worst", worst)
+
+
+@pytest.mark.skip(reason=WORK_LISTS_OFF)
+def test_batch_autotune(h):
+    """The autotuner times its candidates on a batch, keeps the fastest pair, and the batch run
+    with the chosen tiles gives the same decomposition (sums in another order: FP32-level)."""
+    say("batch autotune")
+    items, _ = pipeline_items(16, torch.float32, lo=16, hi=48)
+    rt.rtr_batch_run(h, items, 10, compute="f32")
+    before = [(it["P"].cpu().clone(), it["err_trace"].cpu().clone()) for it in items]
+    table = rt.rtr_batch_autotune(h, items, compute="f32")
+    say("table", table)
+    assert table["sketch_chunks_per_job"] in (16, 64, 256)
+    assert table["ttm_outputs_per_thread"] in (4, 16, 64)
+    assert all(v > 0 for v in table["sketch_us"].values()) and all(v > 0 for v in table["ttm_us"].values())
+    rt.rtr_batch_run(h, items, 10, compute="f32")
+    for it, (P0, t0) in zip(items, before):
+        assert rel(it["P"].cpu().numpy(), P0.numpy()) < 1e-5
+        assert rel(it["err_trace"].cpu().numpy(), t0.numpy()) < 1e-4

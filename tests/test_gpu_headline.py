@@ -7,6 +7,10 @@
   FP64, FP32 and BF16-sketch paths against the FP64 oracle: projectors, P, the per-sweep error
   on P, Psi(G) at tol * max(1, cond) with cond from the oracle's conditioning probe
   (tests/conditioning.py), the final RSE at the plain tolerance.
+* The hyperspectral-shaped workload's recipe (smooth rank-10 spatial cores, [0, 1], 30 dB,
+  K = (60, 60, 40), TR-ALS rank 10 for 30 sweeps) at half size, 512 x 512 x 128: both spatial
+  modes are sketched in row blocks of 256, and compression's first stage runs on 512 slabs of
+  512 x 128; FP32 and BF16 against the oracle with the same conditioning-scaled tolerances.
 * Single-tensor TR-ALS shapes that reach every Gauss-Jordan register tier of the solve and
   the rank-6 accumulation the benchmark runs (K' = 20, R = 6), at 1e-10.
 """
@@ -64,6 +68,39 @@ def test_dense_block_parity(h, dense_block, compute):
            "trace": out["err_trace"].cpu().numpy(), "psi": ot.tr_full(G),
            "rse": pipeline.rse(h, Xd, w.ranks, out["G"])}
     assert int(out["sweeps_run"].item()) == w.sweeps
+    errs = {k: C.distance(got[k], qref[k], k) for k in C.KEYS}
+    say(compute, {k: f"{errs[k]:.3g} (limit {tol * max(1.0, cond[k]):.3g})" for k in C.KEYS})
+    for k in ("proj", "P", "trace", "psi"):
+        assert errs[k] <= tol * max(1.0, cond[k]), (k, errs[k], cond[k])
+    assert errs["rse"] <= tol, errs["rse"]
+
+
+@pytest.fixture(scope="module")
+def hsi_half():
+    w = W.hsi_shaped(scale=2)
+    say("oracle + conditioning probe on", w.name)
+    X, _ = W.make_tensor(w, dtype=torch.float32)
+    X = X.numpy()
+    Z0 = W.make_init(w)
+    base, qref, cond = C.condition(X.astype(np.float64), w.K, Z0, w.sweeps, w.q, w.seed)
+    say("cond", {k: f"{v:.3g}" for k, v in cond.items()}, "oracle RSE", base["rse"])
+    return w, X, Z0, base, qref, cond
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_hsi_shaped_parity(h, hsi_half, compute):
+    w, X, Z0, base, qref, cond = hsi_half
+    tol = TOL[compute]
+    say("hsi-shaped 512x512x128", compute)
+    Xd = torch.as_tensor(X).to(DEV)
+    out = pipeline.rtr_als(h, Xd, w.K, w.ranks, Z0, w.sweeps, w.q, w.seed, compute=compute)
+    torch.cuda.synchronize()
+    Q = [t.cpu().numpy() for t in rt.unpack(out["Q"], rt.q_shapes(w.dims, w.K))]
+    G = [g.cpu().numpy() for g in rt.unpack(out["G"], rt.core_shapes(w.dims, w.ranks))]
+    got = {"proj": [q @ q.T for q in Q], "P": out["P"].cpu().numpy(),
+           "trace": out["err_trace"].cpu().numpy(), "psi": ot.tr_full(G),
+           "rse": pipeline.rse(h, Xd, w.ranks, out["G"])}
+    assert rt.rtr_status_sync(h) == 0
     errs = {k: C.distance(got[k], qref[k], k) for k in C.KEYS}
     say(compute, {k: f"{errs[k]:.3g} (limit {tol * max(1.0, cond[k]):.3g})" for k in C.KEYS})
     for k in ("proj", "P", "trace", "psi"):

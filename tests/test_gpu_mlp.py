@@ -146,3 +146,52 @@ def test_to_cores(h):
     Z = rt.rtr_mlp_to_cores(h, y, pn2, order=4).cpu().numpy()
     want = y.double().cpu().numpy() * np.array([2.0, 1.0, 3.0])[:, None] ** 0.5
     np.testing.assert_allclose(Z, want, rtol=1e-14)
+
+
+@pytest.mark.parametrize("compute,tol", [("f32", 1e-4), ("bf16", 2e-2)])
+@pytest.mark.parametrize("full", [False, True])
+def test_backward_precisions_and_full_size(h, compute, tol, full):
+    """Backward pass in both precisions, on a small network and on the full warm-start network
+    (12^4 = 20736 inputs -> 1024 -> 1024 -> 1024 -> 768 outputs, the 4 cores 4 x 12 x 4).
+
+    FP32: the whole chain (forward, TR loss, backward) against the oracle's gradients of the
+    mean loss.  bf16: every product rounds both operands to 8 significant bits; the TR loss
+    derivative is cubic in the network's output, so the output's bf16 error is amplified on the
+    way into the backward pass.  The backward kernels are therefore compared stage-wise: the
+    oracle's back-propagation (FP64) applied to the GPU's own layer inputs and output gradient,
+    at the per-product bf16 accuracy 2e-2 of the forward test; the loss at 2e-2 as well."""
+    K, R = (C5_K, C5_R) if full else (SMALL_K, SMALL_R)
+    out = sum(a * b * c for a, b, c in om.core_shapes(K, R))
+    sizes = [int(np.prod(K)), 1024, 1024, 1024, out] if full else [72, 64, 48, out]
+    B = 8
+    say("mlp backward", compute, "full" if full else "small")
+    W, b = net(sizes, 16 if full else 6)
+    P, x = inputs(B, K, 17)
+    Wd, bd, xd = to_dev(W), to_dev(b), torch.as_tensor(x).to(DEV)
+    y, acts = rt.rtr_mlp_forward(h, Wd, bd, xd, compute=compute)
+    loss, dy = rt.rtr_mlp_tr_loss(h, y, xd, K, R, 1.0 / B)
+    dW, db = rt.rtr_mlp_backward(h, Wd, xd, acts, dy, compute=compute)
+    params = [(w.astype(np.float64), c.astype(np.float64)) for w, c in zip(W, b)]
+    lo = om.loss(params, x.astype(np.float64), x.astype(np.float64), K, R)
+    say("  loss", float(loss.mean()), lo)
+    assert abs(float(loss.mean()) - lo) <= (1e-5 if compute == "f32" else tol) * max(1.0, abs(lo))
+    if compute == "f32":
+        grads = om.backward(params, x.astype(np.float64), x.astype(np.float64), K, R)
+    else:
+        a_in = [x.astype(np.float64)] + [t.cpu().numpy().astype(np.float64) for t in acts]
+        grads = om.backprop(params, a_in, dy.cpu().numpy().astype(np.float64))
+    for l, (gW, gb) in enumerate(grads):
+        eW, eb = rel(dW[l].cpu().numpy(), gW), rel(db[l].cpu().numpy(), gb)
+        say("  layer", l, f"dW {eW:.3g} db {eb:.3g}")
+        assert eW < tol and eb < tol, (l, eW, eb)
+
+
+def test_core_loss_matches_oracle(h):
+    """Supervised core loss and its gradient against the oracle's definition."""
+    rng = np.random.default_rng(21)
+    y = rng.standard_normal((5, 768)).astype(np.float32)
+    t = rng.standard_normal((5, 768)).astype(np.float32)
+    loss, dy = rt.rtr_mlp_core_loss(h, torch.as_tensor(y).to(DEV), torch.as_tensor(t).to(DEV), 0.2)
+    lo, go = om.core_loss(y.astype(np.float64), t.astype(np.float64), 0.2)
+    assert rel(loss.cpu().numpy(), lo) < 1e-6
+    assert rel(dy.cpu().numpy(), go) < 1e-6

@@ -224,6 +224,8 @@ class Workload:
     tol: float = 0.0
     tensor_id: int = 0
     full_dims: Optional[List[int]] = None  # this is the leading block of a tensor of these dims
+    gen_ranks: Optional[List[int]] = None  # TR-rank of the generator when it differs from ranks
+    smooth_modes: int = 2                  # leading modes whose cores are smoothed
 
     def numel(self):
         return int(np.prod(self.dims))
@@ -258,6 +260,37 @@ def hsi_shaped(scale=1, seed_offset=3):
                     smooth_sigma=8.0 / scale, rescale01=True)
 
 
+def rgb_shaped(I=1024, K=100, seed_offset=6):
+    """Stand-in for the simulation's RGB image (Sec. 4.1): I x I x 3 FP32 from TR cores of rank
+    12 whose two spatial cores are smoothed (sigma 8 at I = 1024), rescaled to [0, 1], 30 dB;
+    projection K x K x 3 (the colour mode is kept); TR-ALS rank 10, 50 sweeps."""
+    return Workload(f"rgb-{I}x{I}x3-K{K}", [I, I, 3], [10] * 3, [K, K, 3], 0, 50, 30.0,
+                    BASE_SEED + seed_offset, smooth_sigma=8.0 * I / 1024, rescale01=True,
+                    gen_ranks=[12] * 3)
+
+
+def images_shaped(kind="cifar", seed_offset=7):
+    """Stand-ins for the image-collection compression experiment (Sec. 4.2): 32 x 32 x 3 x 50000
+    ("cifar") or 32 x 32 x 3 x 72 x 100 ("coil") FP32 from rank-8 TR cores with smooth spatial
+    cores (sigma 2), rescaled to [0, 1], 30 dB; only the long sample modes are projected
+    (K = 200 for the 50000 images, K = 64 for the 100 objects); TR-ALS rank 8, 30 sweeps."""
+    if kind == "cifar":
+        dims, K = [32, 32, 3, 50000], [32, 32, 3, 200]
+    else:
+        dims, K = [32, 32, 3, 72, 100], [32, 32, 3, 72, 64]
+    return Workload(f"{kind}-" + "x".join(map(str, dims)), dims, [8] * len(dims), K, 0, 30, 30.0,
+                    BASE_SEED + seed_offset, smooth_sigma=2.0, rescale01=True)
+
+
+def hsi_small_shaped(snr_db=20.0, seed_offset=8):
+    """Stand-in for the HSI reconstruction experiment (Sec. 4.3): 200 x 200 x 80 FP32 from
+    rank-10 TR cores with smooth spatial cores (sigma 2), rescaled to [0, 1], noise at
+    ``snr_db`` (None: noise-free); projection 100 x 100 x 6; TR-ALS rank 10, 30 sweeps."""
+    tag = "clean" if snr_db is None else f"{snr_db:g}dB"
+    return Workload(f"hsi-200x200x80-{tag}", [200, 200, 80], [10] * 3, [100, 100, 6], 0, 30,
+                    snr_db, BASE_SEED + seed_offset, smooth_sigma=2.0, rescale01=True)
+
+
 def warm_start_128(I=128, seed_offset=5):
     """128^4 FP32, rank 4, 35 dB, K=12, q=0; sweeps until the error changes by < 1e-4."""
     return Workload(f"warm-{I}^4", [I] * 4, [4] * 4, [12] * 4, 0, 100, 35.0, BASE_SEED + seed_offset, tol=1e-4)
@@ -276,17 +309,19 @@ def batched_uneven(count=512, seed_offset=4, lo=16, hi=96):
     return out
 
 
-def make_tensor(w: Workload, device="cpu", dtype=torch.float64):
+def make_tensor(w: Workload, device="cpu", dtype=torch.float64, clean=None):
     """Synthetic X for workload ``w``; returns (X, generating cores of X's own shape).
 
     The signal and the noise are formed in FP64 and rounded once to ``dtype``.  A block
     workload (``w.full_dims``) draws the cores of the full tensor, keeps their leading
     slices, and takes sigma and the noise of the full tensor, so X is exactly the leading
-    block of the full tensor's X."""
+    block of the full tensor's X.  With ``clean`` a list, the noise-free signal (after any
+    rescale, in ``dtype``) is appended to it."""
     full = list(w.full_dims) if w.full_dims else list(w.dims)
-    cores = tr_cores(w.seed, full, w.ranks, w.tensor_id)
+    cores = tr_cores(w.seed, full, w.gen_ranks or w.ranks, w.tensor_id)
     if w.smooth_sigma:
-        cores = [smooth_along(c, 1, w.smooth_sigma) if n < 2 else c for n, c in enumerate(cores)]
+        cores = [smooth_along(c, 1, w.smooth_sigma) if n < w.smooth_modes else c
+                 for n, c in enumerate(cores)]
     block = [c[:, :d, :] for c, d in zip(cores, w.dims)]
     S = tr_signal(block, device, torch.float64)
     if w.rescale01:
@@ -297,6 +332,8 @@ def make_tensor(w: Workload, device="cpu", dtype=torch.float64):
         s_norm2 = float(torch.sum(S * S))
     else:
         s_norm2 = tr_norm2(cores)
+    if clean is not None:
+        clean.append(S.clone() if dtype == torch.float64 else S.to(dtype))
     if w.snr_db is not None:
         sigma = noise_sigma(s_norm2, int(np.prod(full)), w.snr_db)
         noise_block(w.seed, w.tensor_id, full, w.dims, device, out=S, scale=sigma)
