@@ -92,9 +92,15 @@ def condition(X, K, Z0, sweeps, q, seed, delta=1e-8, samples=2, tensor_id=0):
 
 def sketch_condition(X, K, q, seed, delta=1e-8, samples=6, tensor_id=0, test="gaussian"):
     """Per mode: (oracle basis Q_n, amplification of the projector Q_n Q_n^T, amplification of
-    Q_n) when the sketch and every power product of that mode are off by a random relative
-    ``delta``: the largest over ``samples`` random directions (the amplification is a maximum
-    over directions; a few samples approach it from below).  Modes with K_n >= I_n report 0."""
+    Q_n) when the sketch and every power product of that mode are off by a relative ``delta``.
+
+    The amplification is a maximum over perturbation directions.  Random directions (the
+    largest over ``samples``) approach it from below; for the last product Y (K columns) the
+    first-order bounds close it from above: the projector moves by at most
+    sqrt(2) ||dY|| / sigma_min(Y), i.e. relative amplification sqrt(2) ||Y||_F /
+    (sigma_min(Y) sqrt(K)), and the R_ii >= 0 QR factor by at most (1 + sqrt(2)) ||dY|| /
+    sigma_min(Y).  Each reported amplification is the larger of the two.  Modes with
+    K_n >= I_n report 0."""
     X = np.asarray(X, dtype=np.float64)
     out = []
     for n in range(X.ndim):
@@ -108,9 +114,12 @@ def sketch_condition(X, K, q, seed, delta=1e-8, samples=6, tensor_id=0, test="ga
         else:
             M = orc.gaussian_test_matrix(seed, n, A.shape[1], K[n], tensor_id)
 
+        last = {}
+
         def basis(rng):
             def pert(B):
                 if rng is None:
+                    last["Y"] = B
                     return B
                 E = rng.standard_normal(B.shape)
                 return B + (delta * np.linalg.norm(B) / np.linalg.norm(E)) * E
@@ -121,7 +130,10 @@ def sketch_condition(X, K, q, seed, delta=1e-8, samples=6, tensor_id=0, test="ga
             return Q
 
         Q0 = basis(None)
-        cp = cq = 0.0
+        Y = last["Y"]
+        smin = np.linalg.svd(Y, compute_uv=False)[-1]
+        ratio = np.linalg.norm(Y) / (smin * np.sqrt(K[n]))
+        cp, cq = np.sqrt(2.0) * ratio, (1.0 + np.sqrt(2.0)) * ratio
         for s in range(samples):
             Qp = basis(np.random.default_rng(4099 + s))
             cp = max(cp, rel(Qp @ Qp.T, Q0 @ Q0.T) / delta)
