@@ -23,9 +23,9 @@ HBM_PEAK_GBPS = 8000.0
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # (calibrated on a 1 GiB copy), valid only for the kernel source they were taken on.
-TRAFFIC = {"power_fused": {"bytes_per_launch": 6476062020, "workload": "dense-200^4 bf16",
+TRAFFIC = {"power_fused": {"bytes_per_launch": 6408500460, "workload": "dense-200^4 bf16",
                            "source": "paper_1901_01652_amd/csrc/fastpass.hip",
-                           "sha256": "7bb27689a1237f20e5cd35672afbb4373e37a3eaaf27768787dc5966e42e20fc",
+                           "sha256": "12c47b0bd71b61619aef5d0f30dac1d3169da5db3a2b8fdd4c8a541016fc27d6",
                            "profile": "profiles/dense200_hbm_traffic_counters.md"}}
 
 
