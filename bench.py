@@ -22,7 +22,8 @@ import numpy as np
 HBM_PEAK_GBPS = 8000.0
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-# (calibrated on a 1 GiB copy), valid only for the kernel source they were taken on.
+# (scaled by what the counters read for kernels of known traffic), valid only for the kernel
+# source they were taken on.
 TRAFFIC = {"power_fused": {"bytes_per_launch": 6408500460, "workload": "dense-200^4 bf16",
                            "source": "paper_1901_01652_amd/csrc/fastpass.hip",
                            "sha256": "12c47b0bd71b61619aef5d0f30dac1d3169da5db3a2b8fdd4c8a541016fc27d6",
@@ -305,8 +306,9 @@ def bench_paper_shapes(rt, h, I=1024, Ks=(50, 75, 100, 125, 150, 175, 200)):
     * Sec. 4.3: 200 x 200 x 80 with K = 100 x 100 x 6 at four noise levels, the RSE against
       the noisy input and against the clean signal.
     Times are wall clock per call with the device drained (BF16 sketch path, FP64 TR-ALS).
-    TR-SVD ranks are capped at 32 (the back-projection's rank limit); "capped" reports whether
-    a cap was hit (the eps bound then no longer holds)."""
+    TR-SVD ranks are capped at 32 (the back-projection's rank limit), and in Sec. 4.2 at the
+    largest of 32, 16, 8, 4 whose steps keep every Gram within the eigen-solver's 512; "capped"
+    reports whether a cap was hit (the eps bound then no longer holds)."""
     import torch
     import workloads as W
     from paper_1901_01652_amd import pipeline
@@ -371,12 +373,21 @@ def bench_paper_shapes(rt, h, I=1024, Ks=(50, 75, 100, 125, 150, 175, 200)):
         run()
         ms, o = _clock(run)
         rse_als = pipeline.rse(h, X, w.ranks, o["G"])
-        caps = [32] * len(w.dims)
+        # the largest uniform rank cap whose TR-SVD steps fit the eigen-solver (at most 512)
+        caps = None
+        for c in (32, 16, 8, 4):
+            try:
+                pipeline.rtr_svd(h, X, w.K, [c] * len(w.dims), 0.15, 0, w.seed, compute="bf16")
+                caps = [c] * len(w.dims)
+                break
+            except rt.RtrError as e:
+                if e.code != rt.RTR_ERR_UNSUPPORTED:
+                    raise
         runs = lambda: pipeline.rtr_svd(h, X, w.K, caps, 0.15, 0, w.seed, compute="bf16")
-        runs()
         ms_s, os_ = _clock(runs)
+        capped = bool(rt.rtr_status_sync(h) & rt.RTR_STATUS_RANK_CAPPED)
         rse_svd = pipeline.rse(h, X, os_["ranks"], os_["G"])
-        coll.append({"workload": w.name, "K": w.K,
+        coll.append({"workload": w.name, "K": w.K, "rtr_svd_cap": caps[0], "capped": capped,
                      "rtr_als": {"ranks": w.ranks, "ms": round(ms, 2), "rse": round(rse_als, 5),
                                  "cr": round(w.numel() / params(w.dims, w.ranks), 1)},
                      "rtr_svd": {"ranks": os_["ranks"], "ms": round(ms_s, 2), "rse": round(rse_svd, 5),

@@ -24,6 +24,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "rtr.h")
 
 RTR_F64, RTR_F32, RTR_BF16, RTR_FP8_E4M3 = 0, 1, 2, 3
 RTR_METHOD_ALS, RTR_METHOD_SVD = 0, 1
+RTR_OK, RTR_ERR_INVALID_ARG, RTR_ERR_UNSUPPORTED = 0, 1, 2
 RTR_STATUS_CHOLESKY_FAILED = 0x1
 RTR_STATUS_RANK_CAPPED = 0x2
 RTR_STATUS_SYNC_TIMEOUT = 0x4

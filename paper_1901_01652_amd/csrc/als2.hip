@@ -594,15 +594,16 @@ hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s) {
 //   B  the records are summed in a fixed order, the elements split over the work-groups
 //   -- grid barrier --
 //   C  every work-group reads the summed M and Gram and solves the normal equations by
-//      Gauss-Jordan itself; the arithmetic is identical in each, so all LDS copies of core n
-//      receive the same values and no third barrier is needed.
-// The P tile of the next update is loaded into registers before the solve, so its latency
-// overlaps the solve.  A grid barrier is an agent-scope release/acquire on a monotonic
+//      Gauss-Jordan itself (4x4 pivot blocks, the eliminations on the FP64 matrix cores); the
+//      arithmetic is identical in each, so all LDS copies of core n receive the same values
+//      and no third barrier is needed.
+// The P tile of the next update is loaded into registers during the solve (issued after the
+// solve's own loads), so its latency overlaps the elimination.  A grid barrier is an agent-scope release/acquire on a monotonic
 // arrival counter (zero at launch); its wait is bounded: a barrier that does not complete
 // sets RTR_STATUS_SYNC_TIMEOUT and every work-group leaves the launch.
 constexpr int kPsThreads = 512;  // 8 wavefronts
 constexpr int kPsTiles = 4;      // 16x16 FP64 output tiles per wavefront (M and Gram)
-constexpr int kPsRowBuf = 256;   // pivot-row buffer of the solve (W + CW <= 256)
+constexpr int kPsSolveW = 128;   // bound of the solve's augmented width RR4 + K'_n
 
 __device__ __forceinline__ bool ps_grid_sync(unsigned* bar, unsigned nblk, unsigned& epoch,
                                              unsigned limit, unsigned* status, int* s_fail) {
@@ -710,107 +711,190 @@ __device__ __forceinline__ void ps_load_p(const AlsPersistArgs& g, const PsGeom&
   }
 }
 
-// Gauss-Jordan elimination on [Gram | M^T] (RR x W, W = RR + K'_n) without pivoting (the Gram
-// is symmetric positive definite: every pivot block is a Schur complement of it, itself
-// positive definite), two pivots per step, by the whole work-group.  Thread (r, cb) owns row
-// r, columns cb*CW .. cb*CW+CW-1 in registers, loaded straight from the summed record ``red``
-// (M at 0, K'_n x RR; Gram at gofs, RR x RR).  Step k (pivot rows and columns k, k+1, or k
-// alone for the last of an odd count): the owners of those rows and columns publish them
-// (double-buffered LDS), one barrier, then each thread forms the 2x2 pivot block's inverse, the
-// scaled pivot rows over its columns, and updates its entries.  The solution columns are
-// written into core n (Zn, LDS).  Returns false, leaving the core unchanged, if a pivot block
-// is not positive definite.
-template <int CW>
+// Inverse of a 4x4 pivot block by the 2x2 block formula (Schur complement of the leading 2x2
+// block; two divisions), row-major into ``out``.  Returns false unless the leading 2x2 block
+// and its Schur complement are positive definite (for a symmetric block: unless the block is).
+__device__ __forceinline__ bool ps_inv4(const double* p, int ld, double out[16]) {
+  const double a00 = p[0], a01 = p[1], a10 = p[ld], a11 = p[ld + 1];
+  const double b00 = p[2], b01 = p[3], b10 = p[ld + 2], b11 = p[ld + 3];
+  const double c00 = p[2 * ld], c01 = p[2 * ld + 1], c10 = p[3 * ld], c11 = p[3 * ld + 1];
+  const double d00 = p[2 * ld + 2], d01 = p[2 * ld + 3], d10 = p[3 * ld + 2], d11 = p[3 * ld + 3];
+  const double da = a00 * a11 - a01 * a10;
+  if (!(a00 > 0.0) || !(da > 0.0)) return false;
+  const double ia = 1.0 / da;
+  const double i00 = a11 * ia, i01 = -a01 * ia, i10 = -a10 * ia, i11 = a00 * ia;
+  // E = A^-1 B, F = C A^-1, S = D - C E
+  const double e00 = i00 * b00 + i01 * b10, e01 = i00 * b01 + i01 * b11;
+  const double e10 = i10 * b00 + i11 * b10, e11 = i10 * b01 + i11 * b11;
+  const double f00 = c00 * i00 + c01 * i10, f01 = c00 * i01 + c01 * i11;
+  const double f10 = c10 * i00 + c11 * i10, f11 = c10 * i01 + c11 * i11;
+  const double s00 = d00 - (c00 * e00 + c01 * e10), s01 = d01 - (c00 * e01 + c01 * e11);
+  const double s10 = d10 - (c10 * e00 + c11 * e10), s11 = d11 - (c10 * e01 + c11 * e11);
+  const double ds = s00 * s11 - s01 * s10;
+  if (!(s00 > 0.0) || !(ds > 0.0)) return false;
+  const double is = 1.0 / ds;
+  const double t00 = s11 * is, t01 = -s01 * is, t10 = -s10 * is, t11 = s00 * is;  // S^-1
+  // inverse = [A^-1 + E S^-1 F, -E S^-1; -S^-1 F, S^-1]
+  const double g00 = e00 * t00 + e01 * t10, g01 = e00 * t01 + e01 * t11;  // E S^-1
+  const double g10 = e10 * t00 + e11 * t10, g11 = e10 * t01 + e11 * t11;
+  out[0] = i00 + g00 * f00 + g01 * f10;
+  out[1] = i01 + g00 * f01 + g01 * f11;
+  out[2] = -g00;
+  out[3] = -g01;
+  out[4] = i10 + g10 * f00 + g11 * f10;
+  out[5] = i11 + g10 * f01 + g11 * f11;
+  out[6] = -g10;
+  out[7] = -g11;
+  out[8] = -(t00 * f00 + t01 * f10);
+  out[9] = -(t00 * f01 + t01 * f11);
+  out[10] = t00;
+  out[11] = t01;
+  out[12] = -(t10 * f00 + t11 * f10);
+  out[13] = -(t10 * f01 + t11 * f11);
+  out[14] = t10;
+  out[15] = t11;
+  return true;
+}
+
+// Gauss-Jordan elimination on [Gram | M^T] without pivoting (the Gram is symmetric positive
+// definite: every pivot block is a Schur complement of it, itself positive definite), four
+// pivots per step, on the FP64 matrix cores.  The RR4 x W4 augmented matrix (RR rounded up to
+// a multiple of 4, the extra unknowns decoupled by an identity block; W4 = RR4 + K'_n) lives in
+// 16x16 accumulator tiles: tile q = wid + 8u of the MT x NT grid, the lane holding rows
+// 4i + (lane / 16) and column lane % 16 of it.  Step k (pivots k..k+3): the owners publish the
+// pivot rows and columns (double-buffered LDS); barrier; wavefront 0 alone inverts the 4x4
+// pivot block P and overwrites the published pivot rows with R = P^-1 C[pivot rows, :];
+// barrier; then every tile takes one 16x16x4 product,
+//   C <- C - A R,   A = C[:, pivot columns] with the pivot rows zeroed,
+// after which the pivot rows are set to R.  Writing R in place, rather than forming it as
+// C_p - (P - I) R, keeps the pivot rows free of a cancellation whose error grows with the size
+// of P's entries; inverting in one wavefront keeps the other seven off the FP64 units while
+// the chain of dependent operations runs.  ``prefetch`` runs once the tiles' loads from ``red`` are issued (loads
+// it issues stay in flight during the elimination).  The solution columns are written into
+// core n (Zn, LDS).  Returns false, leaving the core unchanged, if a pivot block is not
+// positive definite.
+template <int TPW, class Prefetch>
 __device__ bool ps_solve(const double* red, int gofs, int RR, int Kn, int Rb, double* Zn,
-                         double* rowbuf, double* colbuf) {
-  const int W = RR + Kn;
-  const int nb = (W + CW - 1) / CW;
-  const int t = threadIdx.x;
-  const int r = t / nb, c0 = (t % nb) * CW;
-  const bool own = r < RR;
-  double a[CW];
+                         double* rowbuf, double* colbuf, Prefetch&& prefetch) {
+  const int RR4 = (RR + 3) & ~3, W4 = RR4 + Kn;
+  const int MT = (RR4 + 15) / 16, NT = (W4 + 15) / 16;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int r16 = lane & 15, g4 = lane >> 4;
+  f64x4 c[TPW];
 #pragma unroll
-  for (int u = 0; u < CW; ++u) {
-    const int c = c0 + u;
-    a[u] = 0.0;
-    if (own && c < W) a[u] = c < RR ? red[gofs + r * RR + c] : red[(c - RR) * RR + r];
-  }
-  int par = 0;
-  for (int k = 0; k < RR; k += 2, par ^= 1) {
-    const bool two = k + 1 < RR;
-    double* rb0 = rowbuf + par * 2 * kPsRowBuf;
-    double* rb1 = rb0 + kPsRowBuf;
-    double* cb0 = colbuf + par * 2 * 64;
-    double* cb1 = cb0 + 64;
-    if (own && (r == k || r == k + 1)) {
-      double* dst = r == k ? rb0 : rb1;
+  for (int u = 0; u < TPW; ++u) {
+    const int q = wid + 8 * u;
+    const int mt = q / NT, nt = q % NT;
+    const int col = nt * 16 + r16;
 #pragma unroll
-      for (int u = 0; u < CW; ++u) dst[c0 + u] = a[u];
+    for (int i = 0; i < 4; ++i) {
+      const int row = mt * 16 + 4 * i + g4;
+      double v = 0.0;
+      if (q < MT * NT) {
+        if (col < RR4)
+          v = (row < RR && col < RR) ? red[gofs + row * RR + col] : (row == col ? 1.0 : 0.0);
+        else if (col < W4 && row < RR)
+          v = red[(col - RR4) * RR + row];
+      }
+      c[u][i] = v;
     }
+  }
+  prefetch();
+  __shared__ int s_ok;
+  bool ok = true;
+  for (int k = 0, par = 0; k < RR4; k += 4, par ^= 1) {
+    double* rb = rowbuf + par * 4 * kPsSolveW;  // pivot rows [4][W4]
+    double* cb = colbuf + par * 64 * 4;         // pivot columns [RR4][4]
+    const int mp = k >> 4, ip = (k & 15) >> 2, np = k >> 4, cp = k & 15;
 #pragma unroll
-    for (int u = 0; u < CW; ++u) {
-      if (own && c0 + u == k) cb0[r] = a[u];
-      if (own && c0 + u == k + 1) cb1[r] = a[u];
+    for (int u = 0; u < TPW; ++u) {
+      const int q = wid + 8 * u;
+      if (q < MT * NT) {
+        const int mt = q / NT, nt = q % NT;
+        if (mt == mp) {
+          const double x = ip == 0 ? c[u][0] : ip == 1 ? c[u][1] : ip == 2 ? c[u][2] : c[u][3];
+          rb[g4 * kPsSolveW + nt * 16 + r16] = x;
+        }
+        if (nt == np && r16 >= cp && r16 < cp + 4) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) cb[(mt * 16 + 4 * i + g4) * 4 + (r16 - cp)] = c[u][i];
+        }
+      }
     }
     __syncthreads();
-    const int rs = own ? r : 0;
-    const double p00 = rb0[k], p01 = rb0[k + 1], p10 = rb1[k], p11 = rb1[k + 1];
-    const double x0 = cb0[rs], x1 = cb1[rs];
-    double r0[CW], r1[CW];
+    if (wid == 0) {
+      double pin[16] = {};
+      const bool good = ps_inv4(rb + k, kPsSolveW, pin);
+      double x[2][4];
 #pragma unroll
-    for (int u = 0; u < CW; ++u) {
-      r0[u] = rb0[c0 + u];
-      r1[u] = rb1[c0 + u];
-    }
-    if (two) {
-      const double det = p00 * p11 - p01 * p10;
-      if (!(p00 > 0.0) || !(det > 0.0)) return false;
-      const double id = 1.0 / det;
-      const double i00 = p11 * id, i01 = -p01 * id, i10 = -p10 * id, i11 = p00 * id;
-      const bool pk = r == k, pk1 = r == k + 1, piv = pk || pk1;
-      // a <- (pivot rows) scaled, or a - [x0 x1] (scaled pivot rows)
-      const double g0 = piv ? 0.0 : x0, g1 = piv ? 0.0 : x1;
-      const double s = piv ? 0.0 : 1.0;
-      const double h0 = pk ? 1.0 : 0.0, h1 = pk1 ? 1.0 : 0.0;
+      for (int h = 0; h < 2; ++h) {
+        const int col = lane + 64 * h;
 #pragma unroll
-      for (int u = 0; u < CW; ++u) {
-        const double q0 = fma(i00, r0[u], i01 * r1[u]);
-        const double q1 = fma(i10, r0[u], i11 * r1[u]);
-        const double rest = fma(-g1, q1, fma(-g0, q0, a[u] * s));
-        a[u] = fma(h0, q0, fma(h1, q1, rest));
+        for (int m = 0; m < 4; ++m) x[h][m] = col < NT * 16 ? rb[m * kPsSolveW + col] : 0.0;
       }
-    } else {
-      if (!(p00 > 0.0)) return false;
-      const double inv = 1.0 / p00;
-      const bool pk = r == k;
-      const double gm = pk ? 0.0 : x0 * inv;
-      const double sm = pk ? inv : 1.0;
 #pragma unroll
-      for (int u = 0; u < CW; ++u) a[u] = fma(-gm, r0[u], a[u] * sm);
+      for (int h = 0; h < 2; ++h) {
+        const int col = lane + 64 * h;
+        if (col < NT * 16) {
+#pragma unroll
+          for (int g = 0; g < 4; ++g)
+            rb[g * kPsSolveW + col] = pin[4 * g] * x[h][0] + pin[4 * g + 1] * x[h][1] +
+                                      pin[4 * g + 2] * x[h][2] + pin[4 * g + 3] * x[h][3];
+        }
+      }
+      if (lane == 0) s_ok = good ? 1 : 0;
+    }
+    __syncthreads();
+    ok = s_ok != 0;
+    if (!ok) break;  // the same outcome in every lane
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+      const int q = wid + 8 * u;
+      if (q < MT * NT) {
+        const int mt = q / NT, nt = q % NT;
+        const int col = nt * 16 + r16, row = mt * 16 + r16;
+        const double b = rb[g4 * kPsSolveW + col];
+        const double a = (row >= k && row < k + 4) ? 0.0 : cb[row * 4 + g4];
+        c[u] = mma_f64(-a, b, c[u]);
+        if (mt == mp) {  // the pivot rows become R (this lane's B operand)
+          if (ip == 0) c[u][0] = b;
+          if (ip == 1) c[u][1] = b;
+          if (ip == 2) c[u][2] = b;
+          if (ip == 3) c[u][3] = b;
+        }
+      }
     }
   }
-  __syncthreads();  // every read of the last step is done before the core changes
-  if (own) {
-    const int ai = r / Rb, b = r % Rb;
+  __syncthreads();
+  if (!ok) return false;
 #pragma unroll
-    for (int u = 0; u < CW; ++u) {
-      const int c = c0 + u;
-      if (c >= RR && c < W) Zn[(ai * Kn + (c - RR)) * Rb + b] = a[u];
+  for (int u = 0; u < TPW; ++u) {
+    const int q = wid + 8 * u;
+    if (q < MT * NT) {
+      const int mt = q / NT, nt = q % NT;
+      const int col = nt * 16 + r16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = mt * 16 + 4 * i + g4;
+        if (row < RR && col >= RR4 && col < W4)
+          Zn[((row / Rb) * Kn + (col - RR4)) * Rb + (row % Rb)] = c[u][i];
+      }
     }
   }
   return true;
 }
 
-// Columns per thread of ps_solve: the smallest CW with RR * ceil(W / CW) <= kPsThreads.
-static __host__ __device__ inline int ps_cw(int RR, int W) {
-  for (int cw = 4; cw <= 16; cw *= 2)
-    if (RR * ((W + cw - 1) / cw) <= kPsThreads) return cw;
-  return 0;
+// Tiles per wavefront of ps_solve (1, 2 or 4; 0 if the augmented matrix exceeds 32 tiles).
+static __host__ __device__ inline int ps_tpw(int RR, int Kn) {
+  const int RR4 = (RR + 3) & ~3, W4 = RR4 + Kn;
+  const int tiles = ((RR4 + 15) / 16) * ((W4 + 15) / 16);
+  if (W4 > kPsSolveW) return 0;
+  return tiles <= 8 ? 1 : tiles <= 16 ? 2 : tiles <= 32 ? 4 : 0;
 }
 
-// RM: rank bound of the subchain registers; CW: columns per thread of the solve; TJ: tile
+// RM: rank bound of the subchain registers; TPW: tiles per wavefront of the solve; TJ: tile
 // width; KT: bound of K'_n (sizes the register tile of P).
-template <int RM, int CW, int TJ, int KT>
+template <int RM, int TPW, int TJ, int KT>
 __global__ __launch_bounds__(kPsThreads) void als_persist_kernel(AlsPersistArgs g) {
   extern __shared__ __align__(16) double sm[];
   __shared__ double wred[16];
@@ -1031,10 +1115,10 @@ __global__ __launch_bounds__(kPsThreads) void als_persist_kernel(AlsPersistArgs 
         // the next update's first P tile, in flight during the solve
         const int nn = n + 1 < N ? n + 1 : 0;
         const PsGeom qn = ps_geom(g, nn, TJ);
-        ps_load_p<TJ, KPER>(g, qn, blockIdx.x, pv);
         double* rowbuf = U + g.ubuf;
-        double* colbuf = rowbuf + 4 * kPsRowBuf;
-        if (!ps_solve<CW>(g.red, rec_g, RR, Kn, Rb, Zs + q.zoffN, rowbuf, colbuf) &&
+        double* colbuf = rowbuf + 2 * 4 * kPsSolveW;
+        auto prefetch = [&]() { ps_load_p<TJ, KPER>(g, qn, blockIdx.x, pv); };
+        if (!ps_solve<TPW>(g.red, rec_g, RR, Kn, Rb, Zs + q.zoffN, rowbuf, colbuf, prefetch) &&
             blockIdx.x == 0 && tid == 0)
           atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
         __syncthreads();
@@ -1059,25 +1143,25 @@ int64_t ps_ubuf(int TJ, int maxK, int maxRR) {
 }
 
 int64_t ps_words(int TJ, int maxK, int maxRR, int64_t ztotal) {
-  const int64_t c = std::max<int64_t>(4 * kPsRowBuf + 4 * 64, kPsThreads);
+  const int64_t c = std::max<int64_t>(2 * 4 * kPsSolveW + 2 * 64 * 4, kPsThreads);
   return zwords(ztotal) + ps_ubuf(TJ, maxK, maxRR) + c;
 }
 
-template <int RM, int CW, int KT>
+template <int RM, int TPW, int KT>
 const void* ps_fn3(int TJ) {
-  return TJ == 128 ? (const void*)als_persist_kernel<RM, CW, 128, KT>
-                   : (const void*)als_persist_kernel<RM, CW, 64, KT>;
+  return TJ == 128 ? (const void*)als_persist_kernel<RM, TPW, 128, KT>
+                   : (const void*)als_persist_kernel<RM, TPW, 64, KT>;
 }
 
-template <int RM, int CW>
+template <int RM, int TPW>
 const void* ps_fn2(int TJ, int maxK) {
-  return maxK <= 32 ? ps_fn3<RM, CW, 32>(TJ) : ps_fn3<RM, CW, 64>(TJ);
+  return maxK <= 32 ? ps_fn3<RM, TPW, 32>(TJ) : ps_fn3<RM, TPW, 64>(TJ);
 }
 
 template <int RM>
-const void* ps_fn(int TJ, int cw, int maxK) {
-  return cw == 4 ? ps_fn2<RM, 4>(TJ, maxK) : cw == 8 ? ps_fn2<RM, 8>(TJ, maxK)
-                                                     : ps_fn2<RM, 16>(TJ, maxK);
+const void* ps_fn(int TJ, int tpw, int maxK) {
+  return tpw == 1 ? ps_fn2<RM, 1>(TJ, maxK) : tpw == 2 ? ps_fn2<RM, 2>(TJ, maxK)
+                                                       : ps_fn2<RM, 4>(TJ, maxK);
 }
 }  // namespace
 
@@ -1091,9 +1175,8 @@ bool als_persist_plan(AlsPersistArgs* g, size_t* lds) {
     maxK = std::max(maxK, Kn);
     rmax = std::max(rmax, g->R[n]);
     maxRR = std::max(maxRR, RR);
-    if (RR > 64 || RR + Kn + 16 > kPsRowBuf) return false;
-    maxNe = std::max(maxNe, ps_cw(RR, RR + Kn));
-    if (!ps_cw(RR, RR + Kn)) return false;
+    if (RR > 64 || !ps_tpw(RR, Kn)) return false;
+    maxNe = std::max(maxNe, ps_tpw(RR, Kn));
     rec = std::max(rec, (int64_t)Kn * RR + (int64_t)RR * RR + 1);
   }
   if (rmax > 8 || maxK > 64 || g->ztotal > kZldsMax || g->total >= (1LL << 31)) return false;
@@ -1126,7 +1209,7 @@ bool als_persist_plan(AlsPersistArgs* g, size_t* lds) {
 
 hipError_t launch_als_persist(const AlsPersistArgs& ga, size_t lds, hipStream_t s) {
   AlsPersistArgs g = ga;
-  // maxNe holds the largest columns-per-thread tier of the solve over the updates
+  // maxNe holds the largest tiles-per-wavefront tier of the solve over the updates
   const void* fn = g.rmax <= 4 ? ps_fn<4>(g.TJ, g.maxNe, g.maxK)
                  : g.rmax <= 6 ? ps_fn<6>(g.TJ, g.maxNe, g.maxK)
                                : ps_fn<8>(g.TJ, g.maxNe, g.maxK);
