@@ -2,8 +2,9 @@
 // (Golub & Van Loan, Alg. 5.2.1), then Q = H_1 ... H_K [I_K; 0] and the sign convention
 // R_ii >= 0 (a column of Q is negated where the Householder diagonal is negative).
 //
-// One work-group per matrix.  The matrix stays in global memory (it is tiny and
-// L2-resident); each wavefront owns a subset of columns while a reflector is applied.
+// One work-group per matrix.  A matrix whose factors fit in LDS (2 In K doubles up to 150 KB)
+// is factored there; a larger one stays in global memory (L2-resident), each wavefront owning a
+// subset of columns while a reflector is applied.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -11,6 +12,15 @@ namespace rtr {
 
 constexpr int kQrThreads = 256;
 constexpr int kQrKMax = 256;
+constexpr int kQrLdsThreads = 512;
+constexpr size_t kQrLdsMax = 150 * 1024;
+
+static __host__ __device__ inline size_t qr_lds_bytes(int64_t In, int K) {
+  return (size_t)(2 * In * K + 3 * K) * sizeof(double);
+}
+static __host__ __device__ inline bool qr_fits_lds(int64_t In, int K) {
+  return qr_lds_bytes(In, K) <= kQrLdsMax;
+}
 
 // One matrix per work-group: A (column-major In x K, overwritten), Qm scratch, Qout row-major.
 __device__ __forceinline__ void qr_one(double* A, double* Qm, int64_t In, int K, double* Qout) {
@@ -80,7 +90,85 @@ __device__ __forceinline__ void qr_one(double* A, double* Qm, int64_t In, int K,
 
 __global__ __launch_bounds__(kQrThreads) void householder_qr_kernel(QrJobs jobs) {
   const int job = blockIdx.x;
+  if (qr_fits_lds(jobs.In[job], jobs.K[job])) return;  // taken by householder_qr_lds_kernel
   qr_one(jobs.A[job], jobs.Qwork[job], jobs.In[job], jobs.K[job], jobs.Q[job]);
+}
+
+// The same factorization with the matrix and the product Q held in LDS (In x K each, column-
+// major).  Wavefront w owns the columns j = w mod 8 throughout.  Step c: every wavefront forms
+// the reflector of column c itself (the norm of column c from row c on, alpha, beta, v^T v:
+// identical arithmetic in each), then applies it to the columns it owns (dot product, scale,
+// update), one barrier per step since column c comes from its owner.  Q = H_0 .. H_{K-1} [I; 0]
+// is accumulated backwards on the owners' columns of Q and needs no barrier at all: the
+// reflectors are read only and every column of Q stays with one wavefront.
+__global__ __launch_bounds__(kQrLdsThreads) void householder_qr_lds_kernel(QrJobs jobs) {
+  const int job = blockIdx.x;
+  const int64_t In64 = jobs.In[job];
+  const int K = jobs.K[job];
+  if (!qr_fits_lds(In64, K)) return;  // taken by householder_qr_kernel
+  const int In = (int)In64;
+  extern __shared__ __align__(16) double qsm[];
+  double* A = qsm;                       // In x K, column-major
+  double* Q = A + (size_t)In * K;        // In x K, column-major
+  double* vdiag = Q + (size_t)In * K;    // v_c at row c (A keeps alpha there)
+  double* rdiag = vdiag + K;             // R_cc before the sign fix
+  double* vtv = rdiag + K;               // v^T v
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  constexpr int kW = kQrLdsThreads / kWave;
+  const double* Ag = jobs.A[job];
+  for (int p = tid; p < In * K; p += kQrLdsThreads) A[p] = Ag[p];
+  for (int p = tid; p < In * K; p += kQrLdsThreads) Q[p] = (p % In == p / In) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int c = 0; c < K; ++c) {
+    const double* a = A + (size_t)c * In;
+    double s2 = 0.0;
+    for (int i = c + lane; i < In; i += kWave) s2 = fma(a[i], a[i], s2);
+    s2 = wave_sum(s2);
+    const double alpha = a[c];
+    const double nrm = sqrt(s2);
+    const double beta = (alpha >= 0.0) ? -nrm : nrm;
+    const double vv = 2.0 * nrm * (nrm + fabs(alpha));
+    const double vc = alpha - beta;
+    if (tid == 0) {
+      vdiag[c] = vc;
+      rdiag[c] = beta;
+      vtv[c] = vv;
+    }
+    if (vv > 0.0) {
+      for (int j = c + 1 + ((wid - (c + 1)) % kW + kW) % kW; j < K; j += kW) {
+        double* b = A + (size_t)j * In;
+        double d = 0.0;
+        for (int i = c + 1 + lane; i < In; i += kWave) d = fma(a[i], b[i], d);
+        d = wave_sum(d);
+        const double f = 2.0 * fma(vc, b[c], d) / vv;
+        if (lane == 0) b[c] -= f * vc;
+        for (int i = c + 1 + lane; i < In; i += kWave) b[i] = fma(-f, a[i], b[i]);
+      }
+    }
+    __syncthreads();
+  }
+  // Q = H_0 H_1 .. H_{K-1} [I; 0]: H_c touches rows and columns c.. of the partial product
+  for (int c = K - 1; c >= 0; --c) {
+    const double vv = vtv[c];
+    if (!(vv > 0.0)) continue;
+    const double* a = A + (size_t)c * In;
+    const double vc = vdiag[c];
+    for (int j = c + ((wid - c) % kW + kW) % kW; j < K; j += kW) {
+      double* q = Q + (size_t)j * In;
+      double d = 0.0;
+      for (int i = c + 1 + lane; i < In; i += kWave) d = fma(a[i], q[i], d);
+      d = wave_sum(d);
+      const double f = 2.0 * fma(vc, q[c], d) / vv;
+      if (lane == 0) q[c] -= f * vc;
+      for (int i = c + 1 + lane; i < In; i += kWave) q[i] = fma(-f, a[i], q[i]);
+    }
+  }
+  __syncthreads();
+  double* Qo = jobs.Q[job];
+  for (int p = tid; p < In * K; p += kQrLdsThreads) {
+    const int row = p / K, col = p % K;
+    Qo[p] = (rdiag[col] < 0.0 ? -1.0 : 1.0) * Q[(size_t)col * In + row];
+  }
 }
 
 // Any number of matrices from a device job list (one work-group each).
@@ -104,8 +192,24 @@ hipError_t launch_householder_qr(const QrJobs& jobs, hipStream_t s) {
   if (jobs.count <= 0) return hipSuccess;
   for (int j = 0; j < jobs.count; ++j)
     if (jobs.K[j] > kQrKMax) return hipErrorInvalidValue;
+  size_t lds = 0;
+  bool any_global = false;
+  for (int j = 0; j < jobs.count; ++j) {
+    if (qr_fits_lds(jobs.In[j], jobs.K[j]))
+      lds = std::max(lds, qr_lds_bytes(jobs.In[j], jobs.K[j]));
+    else
+      any_global = true;
+  }
   prof_begin("householder_qr", s);
-  hipLaunchKernelGGL(householder_qr_kernel, dim3(jobs.count), dim3(kQrThreads), 0, s, jobs);
+  if (lds > 0) {
+    hipError_t e = hipFuncSetAttribute((const void*)householder_qr_lds_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(householder_qr_lds_kernel, dim3(jobs.count), dim3(kQrLdsThreads), lds, s,
+                       jobs);
+  }
+  if (any_global)
+    hipLaunchKernelGGL(householder_qr_kernel, dim3(jobs.count), dim3(kQrThreads), 0, s, jobs);
   prof_end(s);
   return hipGetLastError();
 }
