@@ -524,6 +524,36 @@ def bench_warm_start(rt, h, ntrain=2048, max_epochs=80, ntest=32):
                      "ms": arm("warm", "ms")}}
 
 
+def bench_sparse(rt, h, dims=(20000, 15000, 10000), nnz=2_000_000, K=(20, 20, 20),
+                 R=(4, 4, 4), sweeps=20, reps=3):
+    """rTR-ALS of a sparse tensor given by its nonzeros (Sec. 5 names sparse tensors as future
+    work): power-law coordinates valued by a rank-4 TR model + 30 dB noise, FP64.  Times per
+    call (device drained), the sketch's Gaussian draws per second, and the RSE by the
+    Pythagorean identity."""
+    import torch
+    import workloads as W
+    from paper_1901_01652_amd import pipeline
+    idx, val, _ = W.sparse_tr(31, dims, list(R), nnz)
+    I = torch.as_tensor(idx).to("cuda:0")
+    V = torch.as_tensor(val).to("cuda:0")
+    Z0 = rt.pack(W.init_cores(31, K, R), "cuda:0")
+    xn2 = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    pipeline.rtr_als_coo(h, I, V, dims, K, R, Z0, sweeps, seed=31)   # warm-up
+    ms_sk, Q = _clock(lambda: rt.rtr_sketch_coo(h, I, V, dims, K, seed=31, x_norm2=xn2), reps)
+    ms_cp, P = _clock(lambda: rt.rtr_compress_coo(h, I, V, dims, K, Q), reps)
+    ms_all, o = _clock(lambda: pipeline.rtr_als_coo(h, I, V, dims, K, R, Z0, sweeps, seed=31), reps)
+    x2, p2 = o["x_norm2"].item(), o["p_norm2"].item()
+    e = float(o["err_trace"][sweeps - 1])
+    rse = float(np.sqrt((x2 - p2 + e * e * p2) / x2))
+    normals = nnz * sum(K)
+    return {"workload": f"sparse {'x'.join(map(str, dims))}, {nnz} nonzeros (power-law coordinates, "
+                        "rank-4 TR values, 30 dB), FP64; K=20, rank 4, 20 sweeps",
+            "sketch_ms": round(ms_sk, 3), "compress_ms": round(ms_cp, 3),
+            "end_to_end_ms": round(ms_all, 3), "rse": round(rse, 6),
+            "sketch_normals_per_s": round(normals / (ms_sk * 1e-3), 1),
+            "compress_gflops": round(2.0 * nnz * float(np.prod(K)) / (ms_cp * 1e-3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -544,6 +574,8 @@ def main():
                     help="skip the Khatri-Rao projection variant on the dense tensor")
     ap.add_argument("--no-paper-shapes", action="store_true",
                     help="skip the stand-ins for the paper's experiments (Sec. 4)")
+    ap.add_argument("--no-sparse", action="store_true",
+                    help="skip the sparse (coordinate-list) workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -680,6 +712,12 @@ def main():
     paper = None
     if not args.no_paper_shapes:
         paper = bench_paper_shapes(rt, h)
+    sparse = None
+    if not args.no_sparse:
+        log("[bench] sparse tensor, coordinate list")
+        sparse = bench_sparse(rt, h)
+        log(f"[bench] sparse: sketch {sparse['sketch_ms']} ms, compress {sparse['compress_ms']} ms, "
+            f"end to end {sparse['end_to_end_ms']} ms, RSE {sparse['rse']}")
     batched = None
     if not args.no_batched:
         del out
@@ -714,7 +752,7 @@ def main():
         "roofline": roof, "stages": stages, "read_peak": read_peak, "kernels": kern,
         "fp32_path": fp32, "cpu_baseline": cpu,
         "tr_svd": svd, "khatri_rao": kr, "hsi_shaped": hsi, "paper_shapes": paper, "batched": batched,
-        "warm_start": warm,
+        "warm_start": warm, "sparse": sparse,
     }
     h.close()
     print(json.dumps(line), flush=True)

@@ -102,6 +102,8 @@ typedef enum { RTR_METHOD_ALS = 0, RTR_METHOD_SVD = 1 } rtr_method;
 #define RTR_STATUS_SYNC_TIMEOUT 0x4u    /* a device-wide barrier of the single-launch TR-ALS
                                            did not complete within its bound; the launch
                                            ended early and its outputs are not valid */
+#define RTR_STATUS_INDEX_RANGE 0x8u     /* a coordinate-list entry lay outside the tensor and
+                                           was skipped */
 
 typedef struct rtr_context* rtr_handle;
 
@@ -207,6 +209,46 @@ rtr_status rtr_sketch_noalloc(rtr_handle h, const void* X, rtr_dtype x_dtype, in
 rtr_status rtr_compress(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
                         const int64_t* dims, const int32_t* K, const double* Q,
                         rtr_dtype compute, double* P, double* p_norm2, void* stream);
+
+/*
+ * Alg. 1 steps 3-6 for a sparse tensor given by its nonzeros (coordinate list); the paper
+ * names sparse tensors as future work (Sec. 5).  X is the sum over entries z of
+ * values[z] e_{indices[z, 0]} (x) .. (x) e_{indices[z, N-1]} (repeated coordinates add).
+ * Y_n = X_(n) M_n with the same Gaussian M_n as rtr_sketch (so a sparse tensor and its dense
+ * form give the same Q_n), formed from the nonzeros in FP64: each nonzero adds values[z]
+ * times row j_n of M_n to row i_n of Y_n, j_n its column of X_(n), M_n's row drawn where it is
+ * used.  The additions are FP64 atomics, so results are reproducible to rounding, not bitwise.
+ * Then the FP64 QR with R_ii >= 0 as rtr_sketch; no power iterations.
+ *   indices      device, int64, nnz x N row-major coordinates (0-based); an entry outside the
+ *                tensor is skipped and sets RTR_STATUS_INDEX_RANGE
+ *   values       device, nnz values, RTR_F64 or RTR_F32 (values_dtype)
+ *   nnz          number of entries (0 allowed)
+ *   order, dims, K, seed, tensor_id, Q   as for rtr_sketch
+ *   x_norm2      device, 1 FP64 (may be NULL): sum of values^2 (||X||_F^2 when the
+ *                coordinates are distinct)
+ * Limits: K'_n <= 256 (RTR_ERR_UNSUPPORTED otherwise).
+ */
+rtr_status rtr_sketch_coo(rtr_handle h, const int64_t* indices, const void* values,
+                          rtr_dtype values_dtype, int64_t nnz, int32_t order, const int64_t* dims,
+                          const int32_t* K, uint64_t seed, uint32_t tensor_id, double* Q,
+                          double* x_norm2, void* stream);
+
+/*
+ * Alg. 1 step 7 (Eq. 3) for a tensor given by its nonzeros, in FP64:
+ * P = sum_z values[z] Q_1[i_1, :] (x) .. (x) Q_N[i_N, :].  Viewing P as an F x B matrix
+ * (leading modes as rows), it is a product A B^T over the nonzeros, formed on the FP64 matrix
+ * cores in slices of the nonzeros whose partial P are summed in a fixed order (bitwise
+ * reproducible).
+ *   indices, values, values_dtype, nnz, order, dims, K   as for rtr_sketch_coo
+ *   Q          device, FP64, packed Q_n (I_n x K'_n)
+ *   P          device, FP64, row-major K'_1 x .. x K'_N
+ *   p_norm2    device, 1 FP64 (may be NULL): ||P||_F^2
+ * Limits: order >= 2, prod K'_n <= 2^28 (RTR_ERR_UNSUPPORTED otherwise).
+ */
+rtr_status rtr_compress_coo(rtr_handle h, const int64_t* indices, const void* values,
+                            rtr_dtype values_dtype, int64_t nnz, int32_t order, const int64_t* dims,
+                            const int32_t* K, const double* Q, double* P, double* p_norm2,
+                            void* stream);
 
 typedef struct {
   rtr_method method;  /* RTR_METHOD_ALS or RTR_METHOD_SVD */

@@ -16,6 +16,7 @@ tensor   definitions of Sec. 2: unfoldings, mode-n product, the TR format Psi (E
 rtr      Alg. 1 step by step: sketch, economy QR, power iterations, compression (Eq. 3),
          TR-ALS, TR-SVD, back-projection, RSE.
 mlp      FP64 forward/backward of the warm-start network and its TR-reconstruction loss.
+sparse   steps 4-7 for a tensor given by its nonzeros (densified, or looped over the entries).
 
 Every function states the passage it follows.  Parity status of each function is listed in
 its docstring; functions without an independent pin say "parity unpinned".

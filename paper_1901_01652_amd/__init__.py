@@ -28,6 +28,7 @@ RTR_OK, RTR_ERR_INVALID_ARG, RTR_ERR_UNSUPPORTED = 0, 1, 2
 RTR_STATUS_CHOLESKY_FAILED = 0x1
 RTR_STATUS_RANK_CAPPED = 0x2
 RTR_STATUS_SYNC_TIMEOUT = 0x4
+RTR_STATUS_INDEX_RANGE = 0x8
 MAX_ORDER = 8
 
 _DTYPES = {"f64": RTR_F64, "f32": RTR_F32, "bf16": RTR_BF16, "fp8": RTR_FP8_E4M3}
@@ -76,6 +77,8 @@ def _load():
                           vp],
         "rtr_sketch_sequential": [vp, vp, ctypes.c_int, i32, P64, P32, u64, u32, ctypes.c_int, vp,
                                   vp, vp, vp],
+        "rtr_sketch_coo": [vp, vp, vp, ctypes.c_int, i64, i32, P64, P32, u64, u32, vp, vp, vp],
+        "rtr_compress_coo": [vp, vp, vp, ctypes.c_int, i64, i32, P64, P32, vp, vp, vp, vp],
         "rtr_compress": [vp, vp, ctypes.c_int, i32, P64, P32, vp, ctypes.c_int, vp, vp, vp],
         "rtr_decompose": [vp, vp, i32, P32, P32, ctypes.POINTER(_Opts), vp, vp, vp, vp, vp],
         "rtr_decompose_svd": [vp, vp, i32, P32, P32, dp, vp, vp, vp, vp],
@@ -256,6 +259,36 @@ def rtr_sketch_sequential(h, X, K, seed=0, tensor_id=0, compute=None, Q=None, P=
                                       _ptr(p_norm2) if p_norm2 is not None else None,
                                       _stream(stream, X.device)))
     return Q, P
+
+
+def _coo(indices, values):
+    assert indices.dtype == torch.int64 and indices.dim() == 2 and indices.is_contiguous()
+    assert values.dim() == 1 and values.is_contiguous() and values.shape[0] == indices.shape[0]
+    return _xdtype(values), int(indices.shape[0])
+
+
+def rtr_sketch_coo(h, indices, values, dims, K, seed=0, tensor_id=0, Q=None, x_norm2=None,
+                   stream=None):
+    """Alg. 1 steps 3-6 for a tensor given by its nonzeros (``indices`` nnz x N int64,
+    ``values`` nnz FP64/FP32, both on the device): packed FP64 Q_n."""
+    vd, nnz = _coo(indices, values)
+    if Q is None:
+        Q = torch.empty(q_size(dims, K), dtype=torch.float64, device=values.device)
+    h.check(lib.rtr_sketch_coo(h.ptr, _ptr(indices), _ptr(values), vd, nnz, len(dims), _i64(dims),
+                               _i32(K), int(seed), int(tensor_id), _ptr(Q), _ptr(x_norm2),
+                               _stream(stream, values.device)))
+    return Q
+
+
+def rtr_compress_coo(h, indices, values, dims, K, Q, P=None, p_norm2=None, stream=None):
+    """Alg. 1 step 7 / Eq. (3) for a tensor given by its nonzeros: P (K'_1 x .. x K'_N, FP64)."""
+    vd, nnz = _coo(indices, values)
+    if P is None:
+        P = torch.empty(keff(dims, K), dtype=torch.float64, device=values.device)
+    h.check(lib.rtr_compress_coo(h.ptr, _ptr(indices), _ptr(values), vd, nnz, len(dims),
+                                 _i64(dims), _i32(K), _ptr(Q), _ptr(P), _ptr(p_norm2),
+                                 _stream(stream, values.device)))
+    return P
 
 
 def rtr_sketch_noalloc(h, X, K, Q, power_iters=0, seed=0, tensor_id=0, compute=None, stream=None):

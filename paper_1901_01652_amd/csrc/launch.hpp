@@ -165,6 +165,35 @@ hipError_t launch_sum(const double* x, int64_t count, double* out, hipStream_t s
 hipError_t launch_sumsq(bool f32, const void* x, int64_t n, double* partial, double* out,
                         hipStream_t s);
 
+// ---- coo.hip --------------------------------------------------------------------------
+// A tensor given by its nonzeros: idx is nnz x N (row-major), val FP64 or FP32.
+struct CooArgs {
+  const int64_t* idx;
+  const void* val;
+  int f32;
+  int64_t nnz;
+  int N;
+  int64_t dims[8];
+  int K[8];          // sketch: projection size per mode, 0 for a kept mode
+  double* Y[8];      // sketch: column-major I_n x K_n accumulators (zeroed by the caller)
+  uint64_t seed;
+  uint32_t tid;
+  unsigned* status;
+};
+// The compression as one product: P (F x B) = A B^T over the nonzeros.
+struct CooGemm {
+  const double* Q[8];  // Q_n, I_n x Kp[n] row-major
+  int Kp[8];
+  int split;           // modes 0..split-1 index the rows of P's F x B view
+  int64_t F, B;
+  int64_t slices, chunk;
+  double* part;        // slices x F x B
+};
+hipError_t launch_coo_sketch(const CooArgs& a, hipStream_t s);
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
+int64_t coo_slices(int64_t nnz, int64_t F, int64_t B, int64_t max_part);
+hipError_t launch_coo_compress(const CooArgs& a, CooGemm g, double* P, hipStream_t s);
+
 // ---- als.hip --------------------------------------------------------------------------
 struct Chain {
   int L;

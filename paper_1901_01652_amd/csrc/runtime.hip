@@ -741,6 +741,161 @@ rtr_status rtr_sketch_noalloc(rtr_handle h, const void* X, rtr_dtype x_dtype, in
 }
 
 // ---------------------------------------------------------------------------------------
+namespace {
+// Shared validation of a coordinate list: value type, count, device extents.
+rtr_status check_coo(rtr_context* h, const int64_t* indices, const void* values,
+                     rtr_dtype values_dtype, int64_t nnz, int32_t order) {
+  if (values_dtype != RTR_F64 && values_dtype != RTR_F32)
+    return fail(h, RTR_ERR_INVALID_ARG, "values_dtype must be RTR_F64 or RTR_F32");
+  if (nnz < 0 || nnz > ((int64_t)1 << 40))
+    return fail(h, RTR_ERR_INVALID_ARG, "nnz must be in [0, 2^40]");
+  if (nnz > 0) {
+    CHECK_DEV(indices, (size_t)nnz * order * sizeof(int64_t), "indices");
+    CHECK_DEV(values, (size_t)nnz * (values_dtype == RTR_F64 ? 8 : 4), "values");
+  }
+  return RTR_OK;
+}
+
+rtr::CooArgs coo_args(rtr_context* h, const int64_t* indices, const void* values,
+                      rtr_dtype values_dtype, int64_t nnz, int32_t order, const int64_t* dims) {
+  rtr::CooArgs a{};
+  a.idx = indices;
+  a.val = values;
+  a.f32 = values_dtype == RTR_F32 ? 1 : 0;
+  a.nnz = nnz;
+  a.N = order;
+  for (int n = 0; n < order; ++n) a.dims[n] = dims[n];
+  a.status = h->status;
+  return a;
+}
+}  // namespace
+
+rtr_status rtr_sketch_coo(rtr_handle h, const int64_t* indices, const void* values,
+                          rtr_dtype values_dtype, int64_t nnz, int32_t order, const int64_t* dims,
+                          const int32_t* K, uint64_t seed, uint32_t tensor_id, double* Q,
+                          double* x_norm2, void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if ((st = check_shape(h, order, dims, K))) return st;
+  if (!K) return fail(h, RTR_ERR_INVALID_ARG, "K is NULL");
+  if ((st = check_coo(h, indices, values, values_dtype, nnz, order))) return st;
+  CHECK_DEV(Q, q_bytes(dims, K, order), "Q");
+  if ((st = check_dev_opt(h, x_norm2, sizeof(double), "x_norm2"))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  for (int n = 0; n < order; ++n)
+    if (keff(dims, K, n) < dims[n] && keff(dims, K, n) > kSketchKMax)
+      return fail(h, RTR_ERR_UNSUPPORTED,
+                  "projection size above " + std::to_string(kSketchKMax) + " (mode " + std::to_string(n) + ")");
+  Carve plan(nullptr);
+  for (int n = 0; n < order; ++n) {
+    plan.take<double>((size_t)dims[n] * keff(dims, K, n));
+    plan.take<double>((size_t)dims[n] * keff(dims, K, n));
+  }
+  plan.take<double>(1024);
+  if ((st = ensure_ws(h, plan.off + 256))) return st;
+  Carve cv(h->ws);
+  rtr::CooArgs a = coo_args(h, indices, values, values_dtype, nnz, order, dims);
+  a.seed = seed;
+  a.tid = tensor_id;
+  rtr::QrJobs jobs{};
+  size_t qoff = 0;
+  for (int n = 0; n < order; ++n) {
+    const int64_t k = keff(dims, K, n);
+    double* Y = cv.take<double>((size_t)dims[n] * k);
+    double* Qw = cv.take<double>((size_t)dims[n] * k);
+    double* Qn = Q + qoff;
+    qoff += (size_t)dims[n] * k;
+    if (k == dims[n]) {
+      a.K[n] = 0;
+      HIP_TRY(rtr::launch_identity(Qn, dims[n], s), "identity");
+      continue;
+    }
+    a.K[n] = (int)k;
+    a.Y[n] = Y;
+    HIP_TRY(rtr::launch_fill(Y, dims[n] * k, 0.0, s), "fill");
+    const int j = jobs.count++;
+    jobs.A[j] = Y;
+    jobs.Qwork[j] = Qw;
+    jobs.In[j] = dims[n];
+    jobs.K[j] = (int)k;
+    jobs.Q[j] = Qn;
+  }
+  double* red = cv.take<double>(1024);
+  HIP_TRY(rtr::launch_coo_sketch(a, s), "sketch_coo");
+  HIP_TRY(rtr::launch_householder_qr(jobs, s), "householder_qr");
+  if (x_norm2) {
+    if (nnz > 0)
+      HIP_TRY(rtr::launch_sumsq(values_dtype == RTR_F32, values, nnz, red, x_norm2, s), "sumsq");
+    else
+      HIP_TRY(rtr::launch_fill(x_norm2, 1, 0.0, s), "fill");
+  }
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+rtr_status rtr_compress_coo(rtr_handle h, const int64_t* indices, const void* values,
+                            rtr_dtype values_dtype, int64_t nnz, int32_t order, const int64_t* dims,
+                            const int32_t* K, const double* Q, double* P, double* p_norm2,
+                            void* stream) try {
+  rtr_status st = check_handle(h);
+  if (st) return st;
+  Guard guard(h);
+  if ((st = check_shape(h, order, dims, K))) return st;
+  if (!K) return fail(h, RTR_ERR_INVALID_ARG, "K is NULL");
+  if (order < 2) return fail(h, RTR_ERR_INVALID_ARG, "the coordinate-list compression needs order >= 2");
+  if ((st = check_coo(h, indices, values, values_dtype, nnz, order))) return st;
+  CHECK_DEV(Q, q_bytes(dims, K, order), "Q");
+  int64_t total = 1;
+  for (int n = 0; n < order; ++n) total *= keff(dims, K, n);
+  if (total > ((int64_t)1 << 28))
+    return fail(h, RTR_ERR_UNSUPPORTED, "the projected tensor exceeds 2^28 entries");
+  CHECK_DEV(P, (size_t)total * sizeof(double), "P");
+  if ((st = check_dev_opt(h, p_norm2, sizeof(double), "p_norm2"))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // rows of P's F x B view: the leading modes that make F and B most even
+  int split = 1;
+  {
+    int64_t best = -1, f = 1;
+    for (int m = 1; m < order; ++m) {
+      f *= keff(dims, K, m - 1);
+      const int64_t b = total / f, worst = std::max(f, b);
+      if (best < 0 || worst < best) {
+        best = worst;
+        split = m;
+      }
+    }
+  }
+  rtr::CooGemm g{};
+  g.split = split;
+  g.F = 1;
+  size_t qoff = 0;
+  for (int n = 0; n < order; ++n) {
+    g.Q[n] = Q + qoff;
+    g.Kp[n] = (int)keff(dims, K, n);
+    qoff += (size_t)dims[n] * g.Kp[n];
+    if (n < split) g.F *= g.Kp[n];
+  }
+  g.B = total / g.F;
+  constexpr int64_t kPartMax = (int64_t)1 << 25;  // doubles of slice partials (256 MB)
+  g.slices = rtr::coo_slices(nnz, g.F, g.B, std::max(kPartMax, total));
+  Carve plan(nullptr);
+  plan.take<double>((size_t)g.slices * total);
+  plan.take<double>(1024);
+  if ((st = ensure_ws(h, plan.off + 256))) return st;
+  Carve cv(h->ws);
+  g.part = cv.take<double>((size_t)g.slices * total);
+  double* red = cv.take<double>(1024);
+  rtr::CooArgs a = coo_args(h, indices, values, values_dtype, nnz, order, dims);
+  HIP_TRY(rtr::launch_coo_compress(a, g, P, s), "compress_coo");
+  if (p_norm2) HIP_TRY(rtr::launch_sumsq(false, P, total, red, p_norm2, s), "sumsq");
+  return RTR_OK;
+} catch (...) {
+  return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+// ---------------------------------------------------------------------------------------
 rtr_status rtr_compress(rtr_handle h, const void* X, rtr_dtype x_dtype, int32_t order,
                         const int64_t* dims, const int32_t* K, const double* Q,
                         rtr_dtype compute, double* P, double* p_norm2, void* stream) try {

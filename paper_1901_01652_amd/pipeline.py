@@ -29,6 +29,26 @@ def rtr_als(h, X, K, R, Z_init, sweeps, power_iters=0, seed=0, tensor_id=0, comp
     return {"Q": Q, "P": P, "p_norm2": pn2, "Z": Z, "err_trace": trace, "sweeps_run": nsw, "G": G}
 
 
+def rtr_als_coo(h, indices, values, dims, K, R, Z_init, sweeps, seed=0, tensor_id=0, tol=0.0,
+                stream=None):
+    """rTR-ALS of a tensor given by its nonzeros (``indices`` nnz x N int64, ``values``, on
+    the device): sketch -> QR -> compress -> TR-ALS -> back-project, all in FP64.  Returns a
+    dict of device tensors with ||X||^2 (``x_norm2``) and ||P||^2 (``p_norm2``), from which
+    the RSE follows by the Pythagorean identity."""
+    from . import rtr_sketch_coo, rtr_compress_coo
+    dev = values.device
+    if not torch.is_tensor(Z_init):
+        Z_init = pack(Z_init, dev)
+    xn2 = torch.zeros(1, dtype=torch.float64, device=dev)
+    pn2 = torch.zeros(1, dtype=torch.float64, device=dev)
+    Q = rtr_sketch_coo(h, indices, values, dims, K, seed, tensor_id, x_norm2=xn2, stream=stream)
+    P = rtr_compress_coo(h, indices, values, dims, K, Q, p_norm2=pn2, stream=stream)
+    Z, trace, nsw = rtr_decompose(h, P, R, Z_init, sweeps, tol, stream=stream)
+    G = rtr_backproject(h, list(dims), K, R, Z, Q, stream=stream)
+    return {"Q": Q, "P": P, "x_norm2": xn2, "p_norm2": pn2, "Z": Z, "err_trace": trace,
+            "sweeps_run": nsw, "G": G}
+
+
 def rse(h, X, R, G, stream=None):
     """Sec. 4 RSE = ||X - Psi(G)|| / ||X|| from the explicit residual kernel."""
     out = rtr_residual(h, X, R, G, stream=stream)

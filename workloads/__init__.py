@@ -345,3 +345,43 @@ def make_init(w: Workload):
     """Random N(0,1) TR-ALS initial cores for ``w`` (shapes R x min(K, I) x R)."""
     Keff = [min(k, d) for k, d in zip(w.K, w.dims)]
     return init_cores(w.seed, Keff, w.ranks, w.tensor_id)
+
+
+def sparse_tr(seed, dims, ranks, nnz, snr_db=30.0, alpha=0.8, tensor_id=0):
+    """A sparse tensor: ``nnz`` distinct coordinates whose index along each mode follows a
+    power law (P(i) ~ (rank of i)^-alpha over a seeded permutation of the mode, the skewed
+    degree distribution of sparse count-like tensors), valued by a rank-``ranks`` TR model at
+    those coordinates plus Gaussian noise at ``snr_db`` (None: none).  Returns (indices
+    int64 nnz x N, values FP64, cores); entries are in the order they were first drawn."""
+    rng = _rng(seed, tensor_id, 23)
+    N = len(dims)
+    size = int(np.prod([int(d) for d in dims], dtype=np.float64))
+    nnz = int(min(nnz, size))
+    pmfs, perms = [], []
+    for d in dims:
+        w = np.arange(1, int(d) + 1, dtype=np.float64) ** (-alpha)
+        pmfs.append(w / w.sum())
+        perms.append(rng.permutation(int(d)))
+    chunks, have = [], np.zeros(0, dtype=np.int64)
+    count = 0
+    while count < nnz:
+        draw = np.stack([perms[m][rng.choice(int(dims[m]), size=2 * nnz, p=pmfs[m])]
+                         for m in range(N)], axis=1).astype(np.int64)
+        keys = np.ravel_multi_index(tuple(draw.T), tuple(int(d) for d in dims))
+        _, first = np.unique(keys, return_index=True)
+        first = np.sort(first)                        # first occurrences, in drawn order
+        first = first[~np.isin(keys[first], have)]    # not taken in an earlier round
+        first = first[:nnz - count]
+        chunks.append(draw[first])
+        have = np.concatenate([have, keys[first]])
+        count += len(first)
+    idx = np.concatenate(chunks).reshape(nnz, N)
+    cores = tr_cores(seed, dims, ranks, tensor_id, tag=29)
+    T = cores[0][:, idx[:, 0], :].transpose(1, 0, 2)           # nnz x R_1 x R_2
+    for n in range(1, N):
+        T = np.matmul(T, cores[n][:, idx[:, n], :].transpose(1, 0, 2))
+    vals = np.trace(T, axis1=1, axis2=2)
+    if snr_db is not None and nnz > 0:
+        sigma = np.linalg.norm(vals) / np.sqrt(nnz) * 10.0 ** (-snr_db / 20.0)
+        vals = vals + sigma * rng.standard_normal(nnz)
+    return idx, vals, cores
