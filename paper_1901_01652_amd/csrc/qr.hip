@@ -3,8 +3,9 @@
 // R_ii >= 0 (a column of Q is negated where the Householder diagonal is negative).
 //
 // One work-group per matrix.  A matrix whose factors fit in LDS (2 In K doubles up to 150 KB)
-// is factored there; a larger one stays in global memory (L2-resident), each wavefront owning a
-// subset of columns while a reflector is applied.
+// is factored there; a taller one with K <= 64 by TSQR (blocks of rows factored in LDS, then
+// their stacked R factors, recursively); anything else stays in global memory (L2-resident),
+// each wavefront owning a subset of columns while a reflector is applied.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -20,6 +21,34 @@ static __host__ __device__ inline size_t qr_lds_bytes(int64_t In, int K) {
 }
 static __host__ __device__ inline bool qr_fits_lds(int64_t In, int K) {
   return qr_lds_bytes(In, K) <= kQrLdsMax;
+}
+// Rows of one TSQR block: the most the LDS factorization takes.
+static __host__ __device__ inline int64_t tsqr_block_max(int K) {
+  return (int64_t)(kQrLdsMax / sizeof(double) - 3 * K) / (2 * K);
+}
+constexpr int kTsqrKMax = 64;
+// Whether TSQR can factor a rows x K matrix with ``wcap`` doubles of scratch and the matrix's
+// own ``acap`` doubles: at every level the blocks have at least K rows, the stacked factors
+// (mK x K) fit the level's scratch, the next level's Q fits the front of the level's matrix
+// and its scratch is the rest; the last level fits the LDS factorization.
+static __host__ __device__ inline bool tsqr_ok(int64_t rows, int K, int64_t wcap, int64_t acap) {
+  if (K > kTsqrKMax) return false;
+  for (int level = 0; level < 32; ++level) {
+    if (qr_fits_lds(rows, K)) return true;
+    const int64_t m = (rows + tsqr_block_max(K) - 1) / tsqr_block_max(K);
+    if (rows / m < K) return false;
+    const int64_t mk = m * K;
+    if (mk * K > wcap || mk * K > acap) return false;
+    const int64_t w2 = acap - mk * K;
+    acap = wcap;
+    wcap = w2;
+    rows = mk;
+  }
+  return false;
+}
+// A matrix beyond the LDS factorization that TSQR takes (with the caller's two In x K buffers).
+static __host__ __device__ inline bool qr_tall(int64_t In, int K) {
+  return !qr_fits_lds(In, K) && tsqr_ok(In, K, In * K, In * K);
 }
 
 // One matrix per work-group: A (column-major In x K, overwritten), Qm scratch, Qout row-major.
@@ -90,7 +119,8 @@ __device__ __forceinline__ void qr_one(double* A, double* Qm, int64_t In, int K,
 
 __global__ __launch_bounds__(kQrThreads) void householder_qr_kernel(QrJobs jobs) {
   const int job = blockIdx.x;
-  if (qr_fits_lds(jobs.In[job], jobs.K[job])) return;  // taken by householder_qr_lds_kernel
+  // taken by householder_qr_lds_kernel or the TSQR launches
+  if (qr_fits_lds(jobs.In[job], jobs.K[job]) || qr_tall(jobs.In[job], jobs.K[job])) return;
   qr_one(jobs.A[job], jobs.Qwork[job], jobs.In[job], jobs.K[job], jobs.Q[job]);
 }
 
@@ -101,13 +131,11 @@ __global__ __launch_bounds__(kQrThreads) void householder_qr_kernel(QrJobs jobs)
 // update), one barrier per step since column c comes from its owner.  Q = H_0 .. H_{K-1} [I; 0]
 // is accumulated backwards on the owners' columns of Q and needs no barrier at all: the
 // reflectors are read only and every column of Q stays with one wavefront.
-__global__ __launch_bounds__(kQrLdsThreads) void householder_qr_lds_kernel(QrJobs jobs) {
-  const int job = blockIdx.x;
-  const int64_t In64 = jobs.In[job];
-  const int K = jobs.K[job];
-  if (!qr_fits_lds(In64, K)) return;  // taken by householder_qr_kernel
-  const int In = (int)In64;
-  extern __shared__ __align__(16) double qsm[];
+// Ag: In x K column-major with leading dimension lda; Qo: In x K row-major; Ro (optional): the
+// K x K factor R, with the same sign convention as Q (R_ii >= 0), column-major, leading
+// dimension ldr.
+__device__ void qr_lds_core(const double* Ag, int64_t lda, int In, int K, double* qsm,
+                            double* Qo, double* Ro, int64_t ldr) {
   double* A = qsm;                       // In x K, column-major
   double* Q = A + (size_t)In * K;        // In x K, column-major
   double* vdiag = Q + (size_t)In * K;    // v_c at row c (A keeps alpha there)
@@ -115,8 +143,7 @@ __global__ __launch_bounds__(kQrLdsThreads) void householder_qr_lds_kernel(QrJob
   double* vtv = rdiag + K;               // v^T v
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   constexpr int kW = kQrLdsThreads / kWave;
-  const double* Ag = jobs.A[job];
-  for (int p = tid; p < In * K; p += kQrLdsThreads) A[p] = Ag[p];
+  for (int p = tid; p < In * K; p += kQrLdsThreads) A[p] = Ag[(int64_t)(p / In) * lda + p % In];
   for (int p = tid; p < In * K; p += kQrLdsThreads) Q[p] = (p % In == p / In) ? 1.0 : 0.0;
   __syncthreads();
   for (int c = 0; c < K; ++c) {
@@ -164,10 +191,61 @@ __global__ __launch_bounds__(kQrLdsThreads) void householder_qr_lds_kernel(QrJob
     }
   }
   __syncthreads();
-  double* Qo = jobs.Q[job];
   for (int p = tid; p < In * K; p += kQrLdsThreads) {
     const int row = p / K, col = p % K;
     Qo[p] = (rdiag[col] < 0.0 ? -1.0 : 1.0) * Q[(size_t)col * In + row];
+  }
+  if (Ro)
+    for (int p = tid; p < K * K; p += kQrLdsThreads) {
+      const int r = p % K, c = p / K;
+      const double v = r < c ? A[(size_t)c * In + r] : (r == c ? rdiag[c] : 0.0);
+      Ro[(int64_t)c * ldr + r] = (rdiag[r] < 0.0 ? -1.0 : 1.0) * v;
+    }
+}
+
+__global__ __launch_bounds__(kQrLdsThreads) void householder_qr_lds_kernel(QrJobs jobs) {
+  const int job = blockIdx.x;
+  if (!qr_fits_lds(jobs.In[job], jobs.K[job]) || qr_tall(jobs.In[job], jobs.K[job])) return;
+  extern __shared__ __align__(16) double qsm[];
+  qr_lds_core(jobs.A[job], jobs.In[job], (int)jobs.In[job], jobs.K[job], qsm, jobs.Q[job],
+              nullptr, 0);
+}
+
+// Tall-skinny QR (TSQR): the rows in m blocks of at least 2K each, block b factored in LDS
+// (Q_b into the rows of Q, R_b into rows bK..bK+K-1 of the stacked S); then S (mK x K) is
+// factored the same way, recursively, and Q_b <- Q_b Q_S[bK..bK+K-1, :].  With R_ii >= 0 at
+// the top the result is the unique such factor of the whole matrix.
+__device__ __forceinline__ int64_t tsqr_row0(int64_t rows, int m, int b) {
+  return rows * b / m;
+}
+
+__global__ __launch_bounds__(kQrLdsThreads) void qr_block_kernel(const double* A, int64_t rows,
+                                                                 int K, int m, double* Q,
+                                                                 double* S) {
+  extern __shared__ __align__(16) double qsm[];
+  const int b = blockIdx.x;
+  const int64_t r0 = tsqr_row0(rows, m, b), r1 = tsqr_row0(rows, m, b + 1);
+  qr_lds_core(A + r0, rows, (int)(r1 - r0), K, qsm, Q + r0 * K, S + (int64_t)b * K,
+              (int64_t)m * K);
+}
+
+__global__ __launch_bounds__(64) void qr_combine_kernel(double* Q, int64_t rows, int K, int m,
+                                                        const double* QS) {
+  const int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (r >= rows) return;
+  int b = (int)(r * m / rows);
+  while (b + 1 < m && tsqr_row0(rows, m, b + 1) <= r) ++b;
+  while (b > 0 && tsqr_row0(rows, m, b) > r) --b;
+  double q[kTsqrKMax];
+#pragma unroll
+  for (int c = 0; c < kTsqrKMax; ++c) q[c] = c < K ? Q[r * K + c] : 0.0;
+  const double* T = QS + (int64_t)b * K * K;  // rows bK.. of Q_S, row-major
+  for (int c2 = 0; c2 < K; ++c2) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < kTsqrKMax; ++c)
+      if (c < K) acc = fma(q[c], T[(int64_t)c * K + c2], acc);
+    Q[r * K + c2] = acc;
   }
 }
 
@@ -188,6 +266,38 @@ hipError_t launch_qr_list(const SketchJob* jobs, double* const* work, double* co
   return hipGetLastError();
 }
 
+// A (rows x K, column-major, acap doubles) is consumed; Q (rows x K, row-major) receives the
+// factor; W (wcap doubles) is scratch.  The stacked factors of each level go to W, the next
+// level's Q to the front of A (free once the block factorizations have read it), its scratch to
+// the rest of A; tsqr_ok checked that every level fits.
+static hipError_t tsqr(double* A, int64_t rows, int K, double* Q, double* W, int64_t wcap,
+                       int64_t acap, hipStream_t s) {
+  if (qr_fits_lds(rows, K)) {
+    QrJobs one{};
+    one.count = 1;
+    one.A[0] = A;
+    one.Qwork[0] = W;
+    one.In[0] = rows;
+    one.K[0] = K;
+    one.Q[0] = Q;
+    hipLaunchKernelGGL(householder_qr_lds_kernel, dim3(1), dim3(kQrLdsThreads),
+                       qr_lds_bytes(rows, K), s, one);
+    return hipGetLastError();
+  }
+  if (!tsqr_ok(rows, K, wcap, acap)) return hipErrorInvalidValue;
+  const int m = (int)((rows + tsqr_block_max(K) - 1) / tsqr_block_max(K));
+  const int64_t blk = (rows + m - 1) / m;  // the largest block
+  hipLaunchKernelGGL(qr_block_kernel, dim3(m), dim3(kQrLdsThreads), qr_lds_bytes(blk, K), s, A,
+                     rows, K, m, Q, W);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t mk = (int64_t)m * K;
+  if ((e = tsqr(W, mk, K, A, A + mk * K, acap - mk * K, wcap, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(qr_combine_kernel, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, s, Q, rows,
+                     K, m, (const double*)A);
+  return hipGetLastError();
+}
+
 hipError_t launch_householder_qr(const QrJobs& jobs, hipStream_t s) {
   if (jobs.count <= 0) return hipSuccess;
   for (int j = 0; j < jobs.count; ++j)
@@ -197,17 +307,24 @@ hipError_t launch_householder_qr(const QrJobs& jobs, hipStream_t s) {
   for (int j = 0; j < jobs.count; ++j) {
     if (qr_fits_lds(jobs.In[j], jobs.K[j]))
       lds = std::max(lds, qr_lds_bytes(jobs.In[j], jobs.K[j]));
-    else
+    else if (!qr_tall(jobs.In[j], jobs.K[j]))
       any_global = true;
   }
   prof_begin("householder_qr", s);
-  if (lds > 0) {
-    hipError_t e = hipFuncSetAttribute((const void*)householder_qr_lds_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  hipError_t e = hipFuncSetAttribute((const void*)householder_qr_lds_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kQrLdsMax);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)qr_block_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kQrLdsMax);
+  if (e != hipSuccess) return e;
+  if (lds > 0)
     hipLaunchKernelGGL(householder_qr_lds_kernel, dim3(jobs.count), dim3(kQrLdsThreads), lds, s,
                        jobs);
-  }
+  for (int j = 0; j < jobs.count; ++j)
+    if (qr_tall(jobs.In[j], jobs.K[j]) &&
+        (e = tsqr(jobs.A[j], jobs.In[j], jobs.K[j], jobs.Q[j], jobs.Qwork[j],
+                  jobs.In[j] * jobs.K[j], jobs.In[j] * jobs.K[j], s)) != hipSuccess)
+      return e;
   if (any_global)
     hipLaunchKernelGGL(householder_qr_kernel, dim3(jobs.count), dim3(kQrThreads), 0, s, jobs);
   prof_end(s);
