@@ -383,27 +383,7 @@ __global__ __launch_bounds__(kSolveThreads) void als_solve2_kernel(AlsSolveArgs 
     __syncthreads();
     if (*g.done || g.report_only) return;
   }
-  // fixed-order sum of the partials in batches of 32 loads issued together; the last batch
-  // reads clamped (valid) records and masks them by a multiply, so no record is fetched by
-  // a lone dependent load
-  for (int o = tid; o < nstore; o += nth) {
-    const double* src = g.part + o;
-    const int64_t st = nstore + 1;
-    const int last = g.nparts - 1;
-    double s = 0.0;
-    for (int c = 0; c < g.nparts; c += 32) {
-      double v[32];
-#pragma unroll
-      for (int e = 0; e < 32; ++e) {
-        const int cc = c + e <= last ? c + e : last;
-        v[e] = src[(int64_t)cc * st] * (c + e <= last ? 1.0 : 0.0);
-      }
-      __builtin_amdgcn_sched_barrier(0);  // all 32 loads ahead of the sums
-#pragma unroll
-      for (int e = 0; e < 32; ++e) s += v[e];
-    }
-    sm[o] = s;
-  }
+  for (int o = tid; o < nstore; o += nth) sm[o] = g.red[o];  // the summed records
   if (tid == 0) failed = 0;
   if (g.gram_in) {
     for (int x = tid; x < RR * RR; x += nth) G[x] = g.gram_in[x];
@@ -474,6 +454,74 @@ __global__ __launch_bounds__(kSolveThreads) void als_solve2_kernel(AlsSolveArgs 
       g.Zn[((int64_t)a * Kn + i) * g.Rb + b] = M[x];
     }
   }
+}
+
+// The accumulation's records summed element by element in a fixed order (one thread per
+// element, batches of 32 loads issued together; the last batch reads clamped valid records
+// and masks them by a multiply, so no record is fetched by a lone dependent load).
+__global__ __launch_bounds__(256) void als_reduce_kernel(const double* __restrict__ part,
+                                                         int nparts, int nstore,
+                                                         double* __restrict__ red) {
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o >= nstore) return;
+  const double* src = part + o;
+  const int64_t st = nstore + 1;
+  const int last = nparts - 1;
+  double s = 0.0;
+  for (int c = 0; c < nparts; c += 32) {
+    double v[32];
+#pragma unroll
+    for (int e = 0; e < 32; ++e) {
+      const int cc = c + e <= last ? c + e : last;
+      v[e] = src[(int64_t)cc * st] * (c + e <= last ? 1.0 : 0.0);
+    }
+    __builtin_amdgcn_sched_barrier(0);  // all 32 loads ahead of the sums
+#pragma unroll
+    for (int e = 0; e < 32; ++e) s += v[e];
+  }
+  red[o] = s;
+}
+
+// The update's solve by the blocked Gauss-Jordan of ps_solve (16 wavefronts), M and the Gram
+// read straight from the summed records (or the Gram from the accumulation launch).
+constexpr int kSolveW = 256;
+template <int TPW>
+__global__ __launch_bounds__(kSolveThreads) void als_solve_mfma_kernel(AlsSolveArgs g) {
+  if (*g.done) return;
+  extern __shared__ __align__(16) double sm[];
+  __shared__ double red16[16];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int RR = g.RR, Kn = g.Kn, nM = Kn * RR;
+  if (g.report_sweep >= 0) {
+    const int nstore = nM + (g.gram_direct ? RR * RR : 0);
+    double s = 0.0;
+    for (int c = tid; c < g.nparts; c += nth) s += g.part[(int64_t)c * (nstore + 1) + nstore];
+    s = block_sum(s, red16);
+    if (tid == 0) {
+      const double e = sqrt(s / g.pn2[0]);
+      const int sw = g.report_sweep;
+      g.trace[sw] = e;
+      *g.sweeps_run = sw + 1;
+      if (g.tol > 0.0 && sw >= 1 && fabs(e - g.trace[sw - 1]) < g.tol) *g.done = 1;
+    }
+    __syncthreads();
+    if (*g.done || g.report_only) return;
+  }
+  const double* Gp = g.gram_in ? g.gram_in : g.red + nM;
+  if (!ps_solve<kSolveThreads / 64, TPW, kSolveW>(g.red, Gp, RR, Kn, g.Rb, g.Zn, sm,
+                                                   sm + 2 * 4 * kSolveW, [] {}) &&
+      tid == 0)
+    atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
+}
+
+// Tiles per wavefront of als_solve_mfma_kernel (1, 2, 4 or 8), 0 if the shape is beyond it.
+static int solve_mfma_tpw(int RR, int Kn) {
+  const int RR4 = (RR + 3) & ~3, W4 = RR4 + Kn;
+  if (W4 > kSolveW) return 0;
+  const int tiles = ((RR4 + 15) / 16) * ((W4 + 15) / 16), nw = kSolveThreads / 64;
+  for (int t = 1; t <= 8; t *= 2)
+    if (tiles <= nw * t) return t;
+  return 0;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -559,6 +607,32 @@ hipError_t launch_als_accum(AlsArgs2 g, int rmax, hipStream_t s) {
 }
 
 hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s) {
+  hipError_t e;
+  if (!g.report_only) {  // the records summed once, by many work-groups
+    const int nstore = g.Kn * g.RR + (g.gram_direct ? g.RR * g.RR : 0);
+    prof_begin("als_reduce", s);
+    hipLaunchKernelGGL(als_reduce_kernel, dim3((unsigned)((nstore + 255) / 256)), dim3(256), 0, s,
+                       g.part, g.nparts, nstore, g.red);
+    prof_end(s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const int tpw = solve_mfma_tpw(g.RR, g.Kn);
+  if (tpw > 0 && (g.gram_in || g.gram_direct || g.report_only)) {
+    const void* fn = tpw == 1 ? (const void*)als_solve_mfma_kernel<1>
+                   : tpw == 2 ? (const void*)als_solve_mfma_kernel<2>
+                   : tpw == 4 ? (const void*)als_solve_mfma_kernel<4>
+                              : (const void*)als_solve_mfma_kernel<8>;
+    const size_t lds = (size_t)(2 * 4 * kSolveW + 2 * kSolveW * 4) * sizeof(double);
+    if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+        hipSuccess)
+      return e;
+    prof_begin("als_solve", s);
+    void* args[] = {&g};
+    e = hipLaunchKernel(fn, dim3(1), dim3(kSolveThreads), args, lds, s);
+    prof_end(s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+  }
   const size_t lds = solve_lds(g.Kn, g.RR, g.gram_direct, g.tdim, g.ztotal);
   // Gauss-Jordan path: augmented rows of at most 256 entries (the LDS row/column buffers),
   // elements spread over kSolveThreads threads
@@ -570,7 +644,7 @@ hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s) {
                  : ne <= 8 * T ? (const void*)als_solve2_kernel<8>
                  : ne <= 16 * T ? (const void*)als_solve2_kernel<16>
                                 : (const void*)als_solve2_kernel<0>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   prof_begin("als_solve", s);
   void* args[] = {&g};
@@ -758,23 +832,25 @@ __device__ __forceinline__ bool ps_inv4(const double* p, int ld, double out[16])
 
 // Gauss-Jordan elimination on [Gram | M^T] without pivoting (the Gram is symmetric positive
 // definite: every pivot block is a Schur complement of it, itself positive definite), four
-// pivots per step, on the FP64 matrix cores.  The RR4 x W4 augmented matrix (RR rounded up to
-// a multiple of 4, the extra unknowns decoupled by an identity block; W4 = RR4 + K'_n) lives in
-// 16x16 accumulator tiles: tile q = wid + 8u of the MT x NT grid, the lane holding rows
-// 4i + (lane / 16) and column lane % 16 of it.  Step k (pivots k..k+3): the owners publish the
-// pivot rows and columns (double-buffered LDS); barrier; wavefront 0 alone inverts the 4x4
-// pivot block P and overwrites the published pivot rows with R = P^-1 C[pivot rows, :];
-// barrier; then every tile takes one 16x16x4 product,
+// pivots per step, on the FP64 matrix cores, by a work-group of NW wavefronts.  Mp is M
+// (K'_n x RR row-major), Gp the Gram (RR x RR); SW bounds the augmented width and sizes the
+// LDS buffers (rowbuf 2 x 4 x SW, colbuf 2 x SW x 4 doubles).  The RR4 x W4 augmented matrix
+// (RR rounded up to a multiple of 4, the extra unknowns decoupled by an identity block;
+// W4 = RR4 + K'_n) lives in 16x16 accumulator tiles: tile q = wid + NW u of the MT x NT grid,
+// the lane holding rows 4i + (lane / 16) and column lane % 16 of it.  Step k (pivots
+// k..k+3): the owners publish the pivot rows and columns (double-buffered LDS); barrier;
+// wavefront 0 alone inverts the 4x4 pivot block P and overwrites the published pivot rows with
+// R = P^-1 C[pivot rows, :]; barrier; then every tile takes one 16x16x4 product,
 //   C <- C - A R,   A = C[:, pivot columns] with the pivot rows zeroed,
 // after which the pivot rows are set to R.  Writing R in place, rather than forming it as
 // C_p - (P - I) R, keeps the pivot rows free of a cancellation whose error grows with the size
-// of P's entries; inverting in one wavefront keeps the other seven off the FP64 units while
-// the chain of dependent operations runs.  ``prefetch`` runs once the tiles' loads from ``red`` are issued (loads
-// it issues stay in flight during the elimination).  The solution columns are written into
-// core n (Zn, LDS).  Returns false, leaving the core unchanged, if a pivot block is not
+// of P's entries; inverting in one wavefront keeps the others off the FP64 units while the
+// chain of dependent operations runs.  ``prefetch`` runs once the tiles' loads are issued
+// (loads it issues stay in flight during the elimination).  The solution columns are written
+// into core n (Zn).  Returns false, leaving the core unchanged, if a pivot block is not
 // positive definite.
-template <int TPW, class Prefetch>
-__device__ bool ps_solve(const double* red, int gofs, int RR, int Kn, int Rb, double* Zn,
+template <int NW, int TPW, int SW, class Prefetch>
+__device__ bool ps_solve(const double* Mp, const double* Gp, int RR, int Kn, int Rb, double* Zn,
                          double* rowbuf, double* colbuf, Prefetch&& prefetch) {
   const int RR4 = (RR + 3) & ~3, W4 = RR4 + Kn;
   const int MT = (RR4 + 15) / 16, NT = (W4 + 15) / 16;
@@ -783,7 +859,7 @@ __device__ bool ps_solve(const double* red, int gofs, int RR, int Kn, int Rb, do
   f64x4 c[TPW];
 #pragma unroll
   for (int u = 0; u < TPW; ++u) {
-    const int q = wid + 8 * u;
+    const int q = wid + NW * u;
     const int mt = q / NT, nt = q % NT;
     const int col = nt * 16 + r16;
 #pragma unroll
@@ -792,9 +868,9 @@ __device__ bool ps_solve(const double* red, int gofs, int RR, int Kn, int Rb, do
       double v = 0.0;
       if (q < MT * NT) {
         if (col < RR4)
-          v = (row < RR && col < RR) ? red[gofs + row * RR + col] : (row == col ? 1.0 : 0.0);
+          v = (row < RR && col < RR) ? Gp[row * RR + col] : (row == col ? 1.0 : 0.0);
         else if (col < W4 && row < RR)
-          v = red[(col - RR4) * RR + row];
+          v = Mp[(col - RR4) * RR + row];
       }
       c[u][i] = v;
     }
@@ -803,17 +879,17 @@ __device__ bool ps_solve(const double* red, int gofs, int RR, int Kn, int Rb, do
   __shared__ int s_ok;
   bool ok = true;
   for (int k = 0, par = 0; k < RR4; k += 4, par ^= 1) {
-    double* rb = rowbuf + par * 4 * kPsSolveW;  // pivot rows [4][W4]
-    double* cb = colbuf + par * 64 * 4;         // pivot columns [RR4][4]
+    double* rb = rowbuf + par * 4 * SW;  // pivot rows [4][W4]
+    double* cb = colbuf + par * SW * 4;         // pivot columns [RR4][4]
     const int mp = k >> 4, ip = (k & 15) >> 2, np = k >> 4, cp = k & 15;
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
-      const int q = wid + 8 * u;
+      const int q = wid + NW * u;
       if (q < MT * NT) {
         const int mt = q / NT, nt = q % NT;
         if (mt == mp) {
           const double x = ip == 0 ? c[u][0] : ip == 1 ? c[u][1] : ip == 2 ? c[u][2] : c[u][3];
-          rb[g4 * kPsSolveW + nt * 16 + r16] = x;
+          rb[g4 * SW + nt * 16 + r16] = x;
         }
         if (nt == np && r16 >= cp && r16 < cp + 4) {
 #pragma unroll
@@ -824,21 +900,21 @@ __device__ bool ps_solve(const double* red, int gofs, int RR, int Kn, int Rb, do
     __syncthreads();
     if (wid == 0) {
       double pin[16] = {};
-      const bool good = ps_inv4(rb + k, kPsSolveW, pin);
-      double x[2][4];
+      const bool good = ps_inv4(rb + k, SW, pin);
+      double x[SW / 64][4];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < SW / 64; ++h) {
         const int col = lane + 64 * h;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) x[h][m] = col < NT * 16 ? rb[m * kPsSolveW + col] : 0.0;
+        for (int m = 0; m < 4; ++m) x[h][m] = col < NT * 16 ? rb[m * SW + col] : 0.0;
       }
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < SW / 64; ++h) {
         const int col = lane + 64 * h;
         if (col < NT * 16) {
 #pragma unroll
           for (int g = 0; g < 4; ++g)
-            rb[g * kPsSolveW + col] = pin[4 * g] * x[h][0] + pin[4 * g + 1] * x[h][1] +
+            rb[g * SW + col] = pin[4 * g] * x[h][0] + pin[4 * g + 1] * x[h][1] +
                                       pin[4 * g + 2] * x[h][2] + pin[4 * g + 3] * x[h][3];
         }
       }
@@ -849,11 +925,11 @@ __device__ bool ps_solve(const double* red, int gofs, int RR, int Kn, int Rb, do
     if (!ok) break;  // the same outcome in every lane
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
-      const int q = wid + 8 * u;
+      const int q = wid + NW * u;
       if (q < MT * NT) {
         const int mt = q / NT, nt = q % NT;
         const int col = nt * 16 + r16, row = mt * 16 + r16;
-        const double b = rb[g4 * kPsSolveW + col];
+        const double b = rb[g4 * SW + col];
         const double a = (row >= k && row < k + 4) ? 0.0 : cb[row * 4 + g4];
         c[u] = mma_f64(-a, b, c[u]);
         if (mt == mp) {  // the pivot rows become R (this lane's B operand)
@@ -869,7 +945,7 @@ __device__ bool ps_solve(const double* red, int gofs, int RR, int Kn, int Rb, do
   if (!ok) return false;
 #pragma unroll
   for (int u = 0; u < TPW; ++u) {
-    const int q = wid + 8 * u;
+    const int q = wid + NW * u;
     if (q < MT * NT) {
       const int mt = q / NT, nt = q % NT;
       const int col = nt * 16 + r16;
@@ -1118,7 +1194,8 @@ __global__ __launch_bounds__(kPsThreads) void als_persist_kernel(AlsPersistArgs 
         double* rowbuf = U + g.ubuf;
         double* colbuf = rowbuf + 2 * 4 * kPsSolveW;
         auto prefetch = [&]() { ps_load_p<TJ, KPER>(g, qn, blockIdx.x, pv); };
-        if (!ps_solve<TPW>(g.red, rec_g, RR, Kn, Rb, Zs + q.zoffN, rowbuf, colbuf, prefetch) &&
+        if (!ps_solve<8, TPW, kPsSolveW>(g.red, g.red + rec_g, RR, Kn, Rb, Zs + q.zoffN, rowbuf,
+                                          colbuf, prefetch) &&
             blockIdx.x == 0 && tid == 0)
           atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
         __syncthreads();
@@ -1143,7 +1220,7 @@ int64_t ps_ubuf(int TJ, int maxK, int maxRR) {
 }
 
 int64_t ps_words(int TJ, int maxK, int maxRR, int64_t ztotal) {
-  const int64_t c = std::max<int64_t>(2 * 4 * kPsSolveW + 2 * 64 * 4, kPsThreads);
+  const int64_t c = std::max<int64_t>(2 * 4 * kPsSolveW + 2 * kPsSolveW * 4, kPsThreads);
   return zwords(ztotal) + ps_ubuf(TJ, maxK, maxRR) + c;
 }
 

@@ -261,6 +261,7 @@ struct AlsArgs2 {
 struct AlsSolveArgs {
   const double* gram_in;  // Gram formed by the accumulation launch (NULL: form it here)
   const double* part;
+  double* red;            // the records summed (M, then the Gram when accumulated directly)
   int nparts, Kn, RR, Rb, Ra;
   int gram_direct;
   int N, n;

@@ -1353,6 +1353,7 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
       const rtr::AlsGeom& g = geo[n];
       rtr::AlsSolveArgs a{};
       a.part = part;
+      a.red = MG;
       a.nparts = (int)grid;
       a.Kn = g.Kn;
       a.RR = g.RR;
