@@ -482,11 +482,12 @@ __global__ __launch_bounds__(256) void als_reduce_kernel(const double* __restric
   red[o] = s;
 }
 
-// The update's solve by the blocked Gauss-Jordan of ps_solve (16 wavefronts), M and the Gram
-// read straight from the summed records (or the Gram from the accumulation launch).
+// The update's solve by the blocked Gauss-Jordan of ps_solve (NW wavefronts, TPW tiles each; the
+// matrix cores, not the wavefront count, bound the elimination), M and the Gram read straight
+// from the summed records (or the Gram from the accumulation launch).
 constexpr int kSolveW = 256;
-template <int TPW>
-__global__ __launch_bounds__(kSolveThreads) void als_solve_mfma_kernel(AlsSolveArgs g) {
+template <int NW, int TPW>
+__global__ __launch_bounds__(NW * 64) void als_solve_mfma_kernel(AlsSolveArgs g) {
   if (*g.done) return;
   extern __shared__ __align__(16) double sm[];
   __shared__ double red16[16];
@@ -508,20 +509,26 @@ __global__ __launch_bounds__(kSolveThreads) void als_solve_mfma_kernel(AlsSolveA
     if (*g.done || g.report_only) return;
   }
   const double* Gp = g.gram_in ? g.gram_in : g.red + nM;
-  if (!ps_solve<kSolveThreads / 64, TPW, kSolveW>(g.red, Gp, RR, Kn, g.Rb, g.Zn, sm,
+  if (!ps_solve<NW, TPW, kSolveW>(g.red, Gp, RR, Kn, g.Rb, g.Zn, sm,
                                                    sm + 2 * 4 * kSolveW, [] {}) &&
       tid == 0)
     atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
 }
 
-// Tiles per wavefront of als_solve_mfma_kernel (1, 2, 4 or 8), 0 if the shape is beyond it.
-static int solve_mfma_tpw(int RR, int Kn) {
+// The variant of als_solve_mfma_kernel for a shape: 8 wavefronts (two per SIMD, so each holds
+// up to 12 tiles in registers) with 1, 2, 4, 8 or 12 tiles each; nullptr if the shape is beyond
+// them.
+static const void* solve_mfma_fn(int RR, int Kn, int* threads) {
   const int RR4 = (RR + 3) & ~3, W4 = RR4 + Kn;
-  if (W4 > kSolveW) return 0;
-  const int tiles = ((RR4 + 15) / 16) * ((W4 + 15) / 16), nw = kSolveThreads / 64;
-  for (int t = 1; t <= 8; t *= 2)
-    if (tiles <= nw * t) return t;
-  return 0;
+  if (W4 > kSolveW) return nullptr;
+  const int tiles = ((RR4 + 15) / 16) * ((W4 + 15) / 16);
+  *threads = 512;
+  if (tiles <= 8) return (const void*)als_solve_mfma_kernel<8, 1>;
+  if (tiles <= 16) return (const void*)als_solve_mfma_kernel<8, 2>;
+  if (tiles <= 32) return (const void*)als_solve_mfma_kernel<8, 4>;
+  if (tiles <= 64) return (const void*)als_solve_mfma_kernel<8, 8>;
+  if (tiles <= 96) return (const void*)als_solve_mfma_kernel<8, 12>;
+  return nullptr;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -616,19 +623,16 @@ hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s) {
     prof_end(s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  const int tpw = solve_mfma_tpw(g.RR, g.Kn);
-  if (tpw > 0 && (g.gram_in || g.gram_direct || g.report_only)) {
-    const void* fn = tpw == 1 ? (const void*)als_solve_mfma_kernel<1>
-                   : tpw == 2 ? (const void*)als_solve_mfma_kernel<2>
-                   : tpw == 4 ? (const void*)als_solve_mfma_kernel<4>
-                              : (const void*)als_solve_mfma_kernel<8>;
+  int threads = 0;
+  const void* mf = solve_mfma_fn(g.RR, g.Kn, &threads);
+  if (mf && (g.gram_in || g.gram_direct || g.report_only)) {
     const size_t lds = (size_t)(2 * 4 * kSolveW + 2 * kSolveW * 4) * sizeof(double);
-    if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+    if ((e = hipFuncSetAttribute(mf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
         hipSuccess)
       return e;
     prof_begin("als_solve", s);
     void* args[] = {&g};
-    e = hipLaunchKernel(fn, dim3(1), dim3(kSolveThreads), args, lds, s);
+    e = hipLaunchKernel(mf, dim3(1), dim3((unsigned)threads), args, lds, s);
     prof_end(s);
     if (e != hipSuccess) return e;
     return hipGetLastError();
@@ -854,7 +858,9 @@ __device__ bool ps_solve(const double* Mp, const double* Gp, int RR, int Kn, int
                          double* rowbuf, double* colbuf, Prefetch&& prefetch) {
   const int RR4 = (RR + 3) & ~3, W4 = RR4 + Kn;
   const int MT = (RR4 + 15) / 16, NT = (W4 + 15) / 16;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // the wavefront index in a scalar register: the tile indices and their LDS offsets derived
+  // from it then stay scalar instead of occupying vector registers per tile
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g4 = lane >> 4;
   f64x4 c[TPW];
 #pragma unroll
@@ -901,22 +907,16 @@ __device__ bool ps_solve(const double* Mp, const double* Gp, int RR, int Kn, int
     if (wid == 0) {
       double pin[16] = {};
       const bool good = ps_inv4(rb + k, SW, pin);
-      double x[SW / 64][4];
+      // each lane rewrites its own columns only, after reading them (the pivot block itself
+      // was read above), so the in-place update needs no further synchronisation
+      for (int col = lane; col < NT * 16; col += 64) {
+        double x[4];
 #pragma unroll
-      for (int h = 0; h < SW / 64; ++h) {
-        const int col = lane + 64 * h;
+        for (int m = 0; m < 4; ++m) x[m] = rb[m * SW + col];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) x[h][m] = col < NT * 16 ? rb[m * SW + col] : 0.0;
-      }
-#pragma unroll
-      for (int h = 0; h < SW / 64; ++h) {
-        const int col = lane + 64 * h;
-        if (col < NT * 16) {
-#pragma unroll
-          for (int g = 0; g < 4; ++g)
-            rb[g * SW + col] = pin[4 * g] * x[h][0] + pin[4 * g + 1] * x[h][1] +
-                                      pin[4 * g + 2] * x[h][2] + pin[4 * g + 3] * x[h][3];
-        }
+        for (int g = 0; g < 4; ++g)
+          rb[g * SW + col] = pin[4 * g] * x[0] + pin[4 * g + 1] * x[1] + pin[4 * g + 2] * x[2] +
+                             pin[4 * g + 3] * x[3];
       }
       if (lane == 0) s_ok = good ? 1 : 0;
     }
