@@ -37,6 +37,11 @@ __device__ __forceinline__ int swz_col(int row, int col) {
   return ((((col >> 3) ^ (row >> 4)) & 7) << 3) | (col & 7);
 }
 constexpr int kFpThreads = 512;   // 8 wavefronts
+
+__device__ __forceinline__ uint32_t bf16_u16(float v) {
+  const __bf16 b = (__bf16)v;
+  return (uint32_t)*(const unsigned short*)&b;
+}
 constexpr int kFpMaxIn = 256;
 constexpr int kFpMaxK = 64;
 
@@ -157,14 +162,37 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         const int i = (tid >> 4) + 32 * s;
+        const float4 v = buf[s];
         if (i < In) {
-          const float4 v = buf[s];
           T* d = Tij + i * ldT + 4 * c4;
           d[0] = Mma<PR>::cvt(v.x);
           d[1] = Mma<PR>::cvt(v.y);
           d[2] = Mma<PR>::cvt(v.z);
           d[3] = Mma<PR>::cvt(v.w);
-          if (OP == 1) {
+        }
+        if constexpr (OP == 1 && PR == 1) {
+          // T^T in bf16 pairs: rows i and i+1 of the tile sit in lanes l and l^16 (same
+          // columns); they swap half their values so that each writes two 32-bit words
+          // (columns 4c4, 4c4+1 from the even row's lane, 4c4+2, 4c4+3 from the odd one),
+          // half the stores of one 16-bit store per element and fewer of them per bank
+          const uint32_t p01 = (uint32_t)bf16_u16(v.x) | ((uint32_t)bf16_u16(v.y) << 16);
+          const uint32_t p23 = (uint32_t)bf16_u16(v.z) | ((uint32_t)bf16_u16(v.w) << 16);
+          const bool odd = (i & 1) != 0;
+          const uint32_t got = (uint32_t)__shfl_xor((int)(odd ? p01 : p23), 16);
+          const int ie = i & ~1;  // the pair's even row
+          if (ie < In) {
+            uint32_t* w0 = (uint32_t*)(Tji + (4 * c4 + (odd ? 2 : 0)) * ldI + ie);
+            uint32_t* w1 = (uint32_t*)(Tji + (4 * c4 + (odd ? 3 : 1)) * ldI + ie);
+            if (!odd) {
+              *w0 = (p01 & 0xFFFFu) | (got << 16);
+              *w1 = (p01 >> 16) | (got & 0xFFFF0000u);
+            } else {
+              *w0 = (got & 0xFFFFu) | (p23 << 16);
+              *w1 = (got >> 16) | (p23 & 0xFFFF0000u);
+            }
+          }
+        } else if constexpr (OP == 1) {
+          if (i < In) {
             Tji[(4 * c4 + 0) * ldI + i] = Mma<PR>::cvt(v.x);
             Tji[(4 * c4 + 1) * ldI + i] = Mma<PR>::cvt(v.y);
             Tji[(4 * c4 + 2) * ldI + i] = Mma<PR>::cvt(v.z);
