@@ -437,7 +437,9 @@ def bench_tr_svd(rt, h, P, eps=0.15, reps=3):
 def bench_batched(rt, h, count=512, sweeps=20, reps=3):
     """The batched workload: ``count`` order-4 FP32 tensors with I_n ~ U{16..96},
     R ~ U{2..6}, K = 2R+4, 35 dB, 20 sweeps.  Times the batched pipeline replayed as one HIP
-    graph, the same batch run eagerly, and the per-tensor loop over the single-tensor calls."""
+    graph (the work-list form with autotuned tiles and the per-tensor form on 8 branch streams,
+    the faster one reported as ``graph_ms``), the same batch run eagerly, and the per-tensor loop
+    over the single-tensor calls."""
     import torch
     import workloads as W
     dev = "cuda:0"
@@ -460,13 +462,30 @@ def bench_batched(rt, h, count=512, sweeps=20, reps=3):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / n
 
+    # tile choice for the work lists (sketch chunks per job, mode-product outputs per thread)
+    try:
+        table = rt.rtr_batch_autotune(h, items, compute="f32")
+    except rt.RtrError as e:
+        if e.code != rt.RTR_ERR_UNSUPPORTED:
+            raise
+        table = None
+    # the per-tensor form (8 branch streams in the graph) beside the work lists
+    rt.rtr_batch_set_work_lists(h, 0)
+    rt.rtr_batch_run(h, items, sweeps, use_graph=True)
+    graph_per_tensor_ms = clock(lambda: rt.rtr_batch_run(h, items, sweeps, use_graph=True), reps)
+    rt.rtr_batch_set_work_lists(h, 1)
     rt.rtr_batch_run(h, items, sweeps, use_graph=True)      # eager run + graph capture
-    graph_ms = clock(lambda: rt.rtr_batch_run(h, items, sweeps, use_graph=True), reps)
+    graph_lists_ms = clock(lambda: rt.rtr_batch_run(h, items, sweeps, use_graph=True), reps)
+    lists = graph_lists_ms <= graph_per_tensor_ms
+    rt.rtr_batch_set_work_lists(h, 1 if lists else 0)
+    graph_ms = min(graph_lists_ms, graph_per_tensor_ms)
     eager_ms = clock(lambda: rt.rtr_batch_run(h, items, sweeps, use_graph=False), 1)
     rt.rtr_profile_reset(h)
     rt.rtr_profile_enable(h, 2)
     rt.rtr_batch_run(h, items, sweeps, use_graph=False)
     als_ms, _ = rt.rtr_profile_read(h, "als_batch")
+    _, sk_launches = rt.rtr_profile_read(h, "sketch_list")
+    rt.rtr_batch_set_work_lists(h, 1)
     rt.rtr_profile_enable(h, 0)
 
     def loop():
@@ -484,7 +503,9 @@ def bench_batched(rt, h, count=512, sweeps=20, reps=3):
             "batched_als_kernel_ms": round(als_ms, 2),
             "speedup_vs_loop": round(loop_ms / graph_ms, 2),
             "p_err_median": round(float(np.median(final)), 6), "compute": "f32",
-            "sweeps": sweeps}
+            "sweeps": sweeps, "graph_work_lists_ms": round(graph_lists_ms, 2),
+            "graph_per_tensor_ms": round(graph_per_tensor_ms, 2),
+            "work_lists_used": sk_launches > 0, "autotune": table}
 
 
 def bench_warm_start(rt, h, ntrain=2048, max_epochs=80, ntest=32):

@@ -296,6 +296,14 @@ rtr_status rtr_decompose(rtr_handle h, const double* P, int32_t order, const int
 rtr_status rtr_set_als_launch(rtr_handle h, int32_t mode);
 
 /*
+ * How rtr_batch_run runs the sketches and compressions of a batch on this handle.  on = 1
+ * (default): as work lists over the whole batch where the batch takes them (see
+ * rtr_batch_autotune); on = 0: rtr_sketch and rtr_compress per tensor, on 8 branch streams in
+ * the captured graph.  Both compute the same quantities; their sums run in different orders.
+ */
+rtr_status rtr_batch_set_work_lists(rtr_handle h, int32_t on);
+
+/*
  * Alg. 1 step 9 with TR-SVD (the rTR-SVD variant of Sec. 4): sequential truncated SVDs of
  * P (TT-SVD style, Zhao et al. 2016) with the ranks chosen from the error bound.
  *   P, order, Kp  as for rtr_decompose (FP64 device, row-major K'_1 x .. x K'_N)
@@ -347,8 +355,8 @@ rtr_status rtr_decompose_batch(rtr_handle h, const rtr_als_item* items, int32_t 
 
 /*
  * Alg. 1 steps 3-12 for a batch of tensors: the sketch and compression of every tensor
- * (rtr_sketch and rtr_compress per tensor, on 8 branch streams inside a captured graph; the
- * work-list form described at rtr_batch_autotune is switched off in this build), one batched
+ * (as work lists over the whole batch where rtr_batch_autotune describes them, else
+ * rtr_sketch and rtr_compress per tensor on 8 branch streams inside a captured graph), one batched
  * TR-ALS launch (rtr_decompose_batch), per-tensor back-projection
  * (rtr_backproject, skipped where G is NULL).  With use_graph != 0 the whole sequence is
  * captured into a HIP graph the first time a given item array is seen (that call runs
@@ -390,10 +398,7 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
  *   table[2..4] sketch microseconds for 16 / 64 / 256, table[5..7] mode-product microseconds
  *   for 4 / 16 / 64
  * (host, 8 int32).  The outputs Q and P of the items are overwritten while timing.
- * RTR_ERR_UNSUPPORTED when the batch does not take the work lists.  The work lists are switched
- * off in this build (this call returns RTR_ERR_UNSUPPORTED and rtr_batch_run takes the
- * per-tensor path): a graph-captured batch run that used them ended with a GPU memory fault
- * whose cause has not been shown yet.
+ * RTR_ERR_UNSUPPORTED when the batch does not take the work lists.
  */
 rtr_status rtr_batch_autotune(rtr_handle h, const rtr_batch_item* items, int32_t count,
                               rtr_dtype x_dtype, rtr_dtype compute, int32_t* table,

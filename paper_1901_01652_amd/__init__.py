@@ -102,6 +102,7 @@ def _load():
         "rtr_profile_enable": [vp, i32],
         "rtr_read_probe": [vp, vp, i64, vp, vp],
         "rtr_set_als_launch": [vp, i32],
+        "rtr_batch_set_work_lists": [vp, i32],
         "rtr_profile_reset": [vp],
         "rtr_profile_read": [vp, ctypes.c_char_p, ctypes.POINTER(dp), P64],
     }
@@ -569,6 +570,11 @@ def rtr_status_sync(h, stream=None, device=0):
     if st not in (0, 5):
         h.check(st)
     return int(bits.value)
+
+
+def rtr_batch_set_work_lists(h, on):
+    """1: rtr_batch_run takes the work lists where the batch allows (default); 0: per tensor."""
+    h.check(lib.rtr_batch_set_work_lists(h.ptr, int(on)))
 
 
 def rtr_set_als_launch(h, mode):

@@ -72,6 +72,7 @@ struct rtr_context {
   size_t jobs_cap = 0;
   int bt_target = 64;  // column-tile chunks per sketch job
   int bt_kc = 16;      // outputs per thread of the batched mode products
+  int bt_lists = 1;    // rtr_batch_run may take the work lists
 };
 
 namespace {
@@ -1678,10 +1679,10 @@ struct StreamPlan {
   std::vector<const int64_t*> d_ttstart;
 };
 
-// The work lists are switched off: the first graph-captured batch run that used them ended
-// with a GPU memory fault whose cause has not been shown yet (the eager run of the same code
-// had passed its parity test).  Until it is, rtr_batch_run takes the per-tensor path.
-constexpr bool kBatchWorkLists = false;
+// The work lists of the batched path.  (They were once switched off after a GPU memory fault in
+// the first graph-captured run; the cause was a stray release of the job arrays before the
+// capture, which left the captured launches reading freed memory.)
+constexpr bool kBatchWorkLists = true;
 
 bool stream_eligible(const rtr_batch_item* items, int32_t count, rtr_dtype x_dtype,
                      int32_t power_iters) {
@@ -2049,13 +2050,15 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
   }
   // the work lists of every tensor's sketch and compression, where the batch allows them
   StreamPlan splan;
-  const bool streamed = stream_eligible(items, count, x_dtype, power_iters);
+  const bool streamed = h->bt_lists && stream_eligible(items, count, x_dtype, power_iters);
+  rtr::Arith sar = rtr::kF32;
   if (streamed) {
-    rtr::Arith ar;
-    if ((st = check_arith(h, x_dtype, compute, &ar))) return st;
+    if ((st = check_arith(h, x_dtype, compute, &sar))) return st;
+    sar = not_fp8(sar);
     Guard guard(h);
-    if ((st = plan_stream(h, items, count, not_fp8(ar), h->bt_target, h->bt_kc, s, &splan))) return st;
+    if ((st = plan_stream(h, items, count, sar, h->bt_target, h->bt_kc, s, &splan))) return st;
   }
+  const int splan_epoch = h->ws_epoch;  // the job lists point into this workspace
   // eager run (also sizes the workspace for the capture below)
   h->ws_hi = 0;
   rtr::AlsItem* dev = nullptr;
@@ -2069,10 +2072,14 @@ rtr_status rtr_batch_run(rtr_handle h, const rtr_batch_item* items, int32_t coun
   if (st || !use_graph) return st;
   // capture the same sequence into a graph over a dedicated copy of the item array
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (streamed && h->ws_epoch != splan_epoch) {
+    // the eager run grew the workspace: the job lists still point into the released one
+    Guard guard(h);
+    if ((st = plan_stream(h, items, count, sar, h->bt_target, h->bt_kc, s, &splan))) return st;
+  }
   const size_t bytes = plan.items.size() * sizeof(rtr::AlsItem);
   if (bytes > h->gitems_cap) {
     if (h->gitems_dev) (void)hipFree(h->gitems_dev);
-  if (h->jobs_dev) (void)hipFree(h->jobs_dev);
     h->gitems_dev = nullptr;
     h->gitems_cap = 0;
     HIP_TRY(hipMalloc(&h->gitems_dev, bytes), "hipMalloc");
@@ -2529,6 +2536,12 @@ rtr_status rtr_status_sync(rtr_handle h, void* stream, uint32_t* bits) try {
   return v ? fail(h, RTR_ERR_NUMERICAL, "device status bits set") : RTR_OK;
 } catch (...) {
   return fail(h, RTR_ERR_INTERNAL, "unexpected exception");
+}
+
+rtr_status rtr_batch_set_work_lists(rtr_handle h, int32_t on) {
+  if (!h || on < 0 || on > 1) return RTR_ERR_INVALID_ARG;
+  h->bt_lists = on;
+  return RTR_OK;
 }
 
 rtr_status rtr_set_als_launch(rtr_handle h, int32_t mode) {

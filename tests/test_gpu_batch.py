@@ -196,11 +196,6 @@ def test_batch_graph_replay(h, count):
         del junk
 
 
-WORK_LISTS_OFF = ("the batched work lists are switched off: the first graph-captured batch run "
-                  "that used them ended with a GPU memory fault whose cause is not yet shown")
-
-
-@pytest.mark.skip(reason=WORK_LISTS_OFF)
 def test_batch_work_lists_real_distribution(h):
     """64 tensors of the batched workload's own distribution (order 4, I_n ~ U{16..96},
     R ~ U{2..6}, K = 2R + 4, 35 dB), FP32: the sketches, QRs and mode products of the whole
@@ -247,12 +242,14 @@ def test_batch_work_lists_real_distribution(h):
     say("worst", worst)
 
 
-@pytest.mark.skip(reason=WORK_LISTS_OFF)
 def test_batch_autotune(h):
     """The autotuner times its candidates on a batch, keeps the fastest pair, and the batch run
-    with the chosen tiles gives the same decomposition (sums in another order: FP32-level)."""
+    with the chosen tiles gives the same P to FP32 accuracy (the partial sums are taken in
+    another order) and, on that P, exactly the oracle's TR-ALS (1e-10): the TR-ALS error trace
+    itself is not compared between the two runs, since ALS amplifies the FP32-level change of P
+    by the conditioning of these small random problems."""
     say("batch autotune")
-    items, _ = pipeline_items(16, torch.float32, lo=16, hi=48)
+    items, ref = pipeline_items(16, torch.float32, lo=16, hi=48)
     rt.rtr_batch_run(h, items, 10, compute="f32")
     before = [(it["P"].cpu().clone(), it["err_trace"].cpu().clone()) for it in items]
     table = rt.rtr_batch_autotune(h, items, compute="f32")
@@ -261,6 +258,8 @@ def test_batch_autotune(h):
     assert table["ttm_outputs_per_thread"] in (4, 16, 64)
     assert all(v > 0 for v in table["sketch_us"].values()) and all(v > 0 for v in table["ttm_us"].values())
     rt.rtr_batch_run(h, items, 10, compute="f32")
-    for it, (P0, t0) in zip(items, before):
-        assert rel(it["P"].cpu().numpy(), P0.numpy()) < 1e-5
-        assert rel(it["err_trace"].cpu().numpy(), t0.numpy()) < 1e-4
+    for it, (P0, t0), (_, w, Z0) in zip(items, before, ref):
+        Pg = it["P"].cpu().numpy()
+        assert rel(Pg, P0.numpy()) < 1e-5
+        _, tro = orc.tr_als(Pg, Z0, 10)
+        assert rel(it["err_trace"].cpu().numpy(), tro) < 1e-10
