@@ -95,14 +95,14 @@ __global__ __launch_bounds__(kAcThreads) void als_accum_kernel(AlsArgs2 g) {
     const int j0 = (int)(t * TJ);
     const int jn = (int)min((int64_t)TJ, g.J - j0);
     __syncthreads();
-    // P_<n>[:, tile] into Ls (rows padded to a multiple of 16 with zeros)
-    {
+    // P_<n>[:, tile] into Ls (rows padded to a multiple of 16 with zeros), 64 rows at a time
+    for (int i0 = 0; i0 < MT * 16; i0 += 64) {
       constexpr int kPer = (64 * TJ + kAcThreads - 1) / kAcThreads;
       double pv[kPer];
 #pragma unroll
       for (int e = 0; e < kPer; ++e) {
         const int x = tid + e * kAcThreads;
-        const int i = x / TJ, jj = x % TJ;
+        const int i = i0 + x / TJ, jj = x % TJ;
         pv[e] = 0.0;
         if (i < Kn && jj < jn) {
           int rem = j0 + jj, base = 0;
@@ -121,8 +121,8 @@ __global__ __launch_bounds__(kAcThreads) void als_accum_kernel(AlsArgs2 g) {
 #pragma unroll
       for (int e = 0; e < kPer; ++e) {
         const int x = tid + e * kAcThreads;
-        const int i = x / TJ, jj = x % TJ;
-        if (i < MT * 16) Ls[i * ldL + jj] = pv[e];
+        const int i = i0 + x / TJ, jj = x % TJ;
+        if (x < 64 * TJ && i < MT * 16) Ls[i * ldL + jj] = pv[e];
       }
     }
     // subchain rows: thread (jl, b) forms row b of S_j
@@ -557,8 +557,13 @@ bool als2_supported(int Kn, int RR, int64_t J, int64_t ztotal, int gram_direct, 
   const int tj = accum_tj(Kn, RR, ztotal);
   const int NT = pad16(RR) / 16, MT = pad16(Kn) / 16;
   const int tiles = MT * NT + (gram_direct ? NT * NT : 0);
-  return tj > 0 && Kn <= 64 && J < (1LL << 31) && tiles <= 16 * kAcTilesMax &&
-         solve_lds(Kn, RR, gram_direct, tdim, ztotal) <= 150 * 1024 &&
+  int thr = 0;
+  const bool mfma_solve = solve_mfma_fn(RR, Kn, &thr) != nullptr;
+  // the transfer-matrix Gram is formed by an extra work-group of the accumulation launch
+  const bool gram_fits =
+      gram_direct || (3 * (int64_t)tdim * tdim + 64 * (int64_t)tdim + ztotal) * 8 <= 150 * 1024;
+  return tj > 0 && Kn <= 256 && J < (1LL << 31) && tiles <= 16 * kAcTilesMax && gram_fits &&
+         (mfma_solve || solve_lds(Kn, RR, gram_direct, tdim, ztotal) <= 150 * 1024) &&
          (gram_direct || (ztotal <= 12 * 512 && maxK <= 64));
 }
 
