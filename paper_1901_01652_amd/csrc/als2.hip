@@ -509,19 +509,28 @@ __global__ __launch_bounds__(NW * 64) void als_solve_mfma_kernel(AlsSolveArgs g)
     if (*g.done || g.report_only) return;
   }
   const double* Gp = g.gram_in ? g.gram_in : g.red + nM;
-  if (!ps_solve<NW, TPW, kSolveW>(g.red, Gp, RR, Kn, g.Rb, g.Zn, sm,
-                                                   sm + 2 * 4 * kSolveW, [] {}) &&
-      tid == 0)
-    atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
+  for (int kc0 = 0; kc0 < Kn; kc0 += g.kwin) {  // right-hand sides in windows of kwin columns
+    const int kcols = Kn - kc0 < g.kwin ? Kn - kc0 : g.kwin;
+    if (!ps_solve<NW, TPW, kSolveW>(g.red, Gp, RR, Kn, kc0, kcols, g.Rb, g.Zn, sm,
+                                    sm + 2 * 4 * kSolveW, [] {})) {
+      if (tid == 0) atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
+      return;
+    }
+  }
 }
 
 // The variant of als_solve_mfma_kernel for a shape: 8 wavefronts (two per SIMD, so each holds
-// up to 12 tiles in registers) with 1, 2, 4, 8 or 12 tiles each; nullptr if the shape is beyond
-// them.
-static const void* solve_mfma_fn(int RR, int Kn, int* threads) {
-  const int RR4 = (RR + 3) & ~3, W4 = RR4 + Kn;
-  if (W4 > kSolveW) return nullptr;
-  const int tiles = ((RR4 + 15) / 16) * ((W4 + 15) / 16);
+// up to 12 tiles in registers) with 1, 2, 4, 8 or 12 tiles each, and the right-hand-side window
+// ``kwin`` (all of K'_n when the augmented matrix fits 96 tiles, else the widest window that
+// does); nullptr if not even one column fits.
+static const void* solve_mfma_fn(int RR, int Kn, int* threads, int* kwin) {
+  const int RR4 = (RR + 3) & ~3, MT = (RR4 + 15) / 16;
+  int win = Kn;
+  const int ntmax = 96 / MT;  // tile columns that fit beside MT tile rows
+  if (((RR4 + win + 15) / 16) > ntmax) win = ntmax * 16 - RR4;
+  if (win < 1 || RR4 + win > kSolveW) return nullptr;
+  *kwin = win;
+  const int tiles = MT * ((RR4 + win + 15) / 16);
   *threads = 512;
   if (tiles <= 8) return (const void*)als_solve_mfma_kernel<8, 1>;
   if (tiles <= 16) return (const void*)als_solve_mfma_kernel<8, 2>;
@@ -557,8 +566,8 @@ bool als2_supported(int Kn, int RR, int64_t J, int64_t ztotal, int gram_direct, 
   const int tj = accum_tj(Kn, RR, ztotal);
   const int NT = pad16(RR) / 16, MT = pad16(Kn) / 16;
   const int tiles = MT * NT + (gram_direct ? NT * NT : 0);
-  int thr = 0;
-  const bool mfma_solve = solve_mfma_fn(RR, Kn, &thr) != nullptr;
+  int thr = 0, kwin = 0;
+  const bool mfma_solve = solve_mfma_fn(RR, Kn, &thr, &kwin) != nullptr;
   // the transfer-matrix Gram is formed by an extra work-group of the accumulation launch
   const bool gram_fits =
       gram_direct || (3 * (int64_t)tdim * tdim + 64 * (int64_t)tdim + ztotal) * 8 <= 150 * 1024;
@@ -629,7 +638,7 @@ hipError_t launch_als_solve2(AlsSolveArgs g, hipStream_t s) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   int threads = 0;
-  const void* mf = solve_mfma_fn(g.RR, g.Kn, &threads);
+  const void* mf = solve_mfma_fn(g.RR, g.Kn, &threads, &g.kwin);
   if (mf && (g.gram_in || g.gram_direct || g.report_only)) {
     const size_t lds = (size_t)(2 * 4 * kSolveW + 2 * kSolveW * 4) * sizeof(double);
     if ((e = hipFuncSetAttribute(mf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
@@ -842,7 +851,9 @@ __device__ __forceinline__ bool ps_inv4(const double* p, int ld, double out[16])
 // Gauss-Jordan elimination on [Gram | M^T] without pivoting (the Gram is symmetric positive
 // definite: every pivot block is a Schur complement of it, itself positive definite), four
 // pivots per step, on the FP64 matrix cores, by a work-group of NW wavefronts.  Mp is M
-// (K'_n x RR row-major), Gp the Gram (RR x RR); SW bounds the augmented width and sizes the
+// (K'_n x RR row-major), Gp the Gram (RR x RR); the right-hand sides taken are the columns
+// kc0 .. kc0 + kcols - 1 of M^T (the solve may run in windows of them, each eliminating the
+// Gram anew); SW bounds the augmented width RR4 + kcols and sizes the
 // LDS buffers (rowbuf 2 x 4 x SW, colbuf 2 x SW x 4 doubles).  The RR4 x W4 augmented matrix
 // (RR rounded up to a multiple of 4, the extra unknowns decoupled by an identity block;
 // W4 = RR4 + K'_n) lives in 16x16 accumulator tiles: tile q = wid + NW u of the MT x NT grid,
@@ -859,9 +870,9 @@ __device__ __forceinline__ bool ps_inv4(const double* p, int ld, double out[16])
 // into core n (Zn).  Returns false, leaving the core unchanged, if a pivot block is not
 // positive definite.
 template <int NW, int TPW, int SW, class Prefetch>
-__device__ bool ps_solve(const double* Mp, const double* Gp, int RR, int Kn, int Rb, double* Zn,
-                         double* rowbuf, double* colbuf, Prefetch&& prefetch) {
-  const int RR4 = (RR + 3) & ~3, W4 = RR4 + Kn;
+__device__ bool ps_solve(const double* Mp, const double* Gp, int RR, int Kn, int kc0, int kcols,
+                         int Rb, double* Zn, double* rowbuf, double* colbuf, Prefetch&& prefetch) {
+  const int RR4 = (RR + 3) & ~3, W4 = RR4 + kcols;
   const int MT = (RR4 + 15) / 16, NT = (W4 + 15) / 16;
   // the wavefront index in a scalar register: the tile indices and their LDS offsets derived
   // from it then stay scalar instead of occupying vector registers per tile
@@ -881,7 +892,7 @@ __device__ bool ps_solve(const double* Mp, const double* Gp, int RR, int Kn, int
         if (col < RR4)
           v = (row < RR && col < RR) ? Gp[row * RR + col] : (row == col ? 1.0 : 0.0);
         else if (col < W4 && row < RR)
-          v = Mp[(col - RR4) * RR + row];
+          v = Mp[(kc0 + col - RR4) * RR + row];
       }
       c[u][i] = v;
     }
@@ -958,7 +969,7 @@ __device__ bool ps_solve(const double* Mp, const double* Gp, int RR, int Kn, int
       for (int i = 0; i < 4; ++i) {
         const int row = mt * 16 + 4 * i + g4;
         if (row < RR && col >= RR4 && col < W4)
-          Zn[((row / Rb) * Kn + (col - RR4)) * Rb + (row % Rb)] = c[u][i];
+          Zn[((row / Rb) * Kn + kc0 + (col - RR4)) * Rb + (row % Rb)] = c[u][i];
       }
     }
   }
@@ -1199,8 +1210,8 @@ __global__ __launch_bounds__(kPsThreads) void als_persist_kernel(AlsPersistArgs 
         double* rowbuf = U + g.ubuf;
         double* colbuf = rowbuf + 2 * 4 * kPsSolveW;
         auto prefetch = [&]() { ps_load_p<TJ, KPER>(g, qn, blockIdx.x, pv); };
-        if (!ps_solve<8, TPW, kPsSolveW>(g.red, g.red + rec_g, RR, Kn, Rb, Zs + q.zoffN, rowbuf,
-                                          colbuf, prefetch) &&
+        if (!ps_solve<8, TPW, kPsSolveW>(g.red, g.red + rec_g, RR, Kn, 0, Kn, Rb, Zs + q.zoffN,
+                                          rowbuf, colbuf, prefetch) &&
             blockIdx.x == 0 && tid == 0)
           atomicOr(g.status, (unsigned)RTR_STATUS_CHOLESKY_FAILED);
         __syncthreads();

@@ -262,6 +262,7 @@ struct AlsSolveArgs {
   const double* gram_in;  // Gram formed by the accumulation launch (NULL: form it here)
   const double* part;
   double* red;            // the records summed (M, then the Gram when accumulated directly)
+  int kwin;               // right-hand sides per window of the blocked solve (set at launch)
   int nparts, Kn, RR, Rb, Ra;
   int gram_direct;
   int N, n;
