@@ -111,13 +111,14 @@ def evaluate(h, model, template, ids, max_sweeps=100, tol=1e-4, compute="bf16"):
         X, Q, P, pn2 = projected(h, w, compute)
         del X
         rec = {"tensor_id": int(t)}
+        Zr = pack(make_init(w), P.device)  # the random start is given, not timed
         for arm in ("random", "warm"):
             ev0 = torch.cuda.Event(enable_timing=True)
             ev1 = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             ev0.record()
             if arm == "random":
-                Z0 = pack(make_init(w), P.device)
+                Z0 = Zr
             else:
                 Z0 = model.init_cores(P.unsqueeze(0), pn2).reshape(-1)
             Z, trace, nsw = rtr_decompose(h, P, w.ranks, Z0, max_sweeps, tol)
