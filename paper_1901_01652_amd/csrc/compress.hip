@@ -33,8 +33,6 @@ __device__ __forceinline__ void ttm_thread(const Tin* __restrict__ in, int64_t A
   Acc acc[KC];
 #pragma unroll
   for (int k = 0; k < KC; ++k) acc[k] = 0;
-  // unrolled so that several loads of the fiber are in flight per thread
-#pragma unroll 8
   for (int64_t i = 0; i < In; ++i) {
     const double* q = Q + i * K + k0;
     if constexpr (AR == kBF16) {
@@ -134,12 +132,10 @@ hipError_t launch_ttm(Arith ar, bool first, const void* in, const ModeView& v, i
   if (K < 1 || K > kTtmKLimit) return hipErrorInvalidValue;
   const int64_t fibers = v.A * v.B;
   prof_begin(first ? "ttm_first" : "ttm", s);
-  // the widest k-group (each group reads the fiber once) that still leaves at least 2^16
-  // threads to cover the GPU; split K further only when there are few fibers
-  auto threads = [&](int kc) { return fibers * ((K + kc - 1) / kc); };
-  if (threads(kTtmKMax) >= (1 << 16))
+  // enough threads to cover the GPU: split K when there are few fibers
+  if (fibers >= (1 << 17))
     launch_ttm_kc<kTtmKMax>(ar, first, in, v, K, Q, out, s);
-  else if (threads(16) >= (1 << 16))
+  else if (fibers >= (1 << 15))
     launch_ttm_kc<16>(ar, first, in, v, K, Q, out, s);
   else
     launch_ttm_kc<4>(ar, first, in, v, K, Q, out, s);
