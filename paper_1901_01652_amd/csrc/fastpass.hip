@@ -124,11 +124,14 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
       const int64_t j = j0 + 4 * c4;
       const bool ok = j < p.J;
       const int64_t cb = ok ? (j / p.B) * p.strideA + (j % p.B) : 0;
+      // one per-lane base; the step between the eight rows is uniform, so the eight
+      // addresses do not each hold a register pair across the tile loop
+      const float* xb = p.X + cb + (int64_t)(tid >> 4) * p.B;
+      const int64_t rs = 32 * p.B;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         const int i = (tid >> 4) + 32 * s;
-        buf[s] = (ok && i < In) ? *(const float4*)(p.X + cb + (int64_t)i * p.B)
-                                : make_float4(0.f, 0.f, 0.f, 0.f);
+        buf[s] = (ok && i < In) ? *(const float4*)(xb + s * rs) : make_float4(0.f, 0.f, 0.f, 0.f);
       }
     } else if constexpr (LD == 1) {
       const int q4 = In / 4;
@@ -163,36 +166,41 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
       for (int s = 0; s < 8; ++s) {
         const int i = (tid >> 4) + 32 * s;
         const float4 v = buf[s];
-        if (i < In) {
-          T* d = Tij + i * ldT + 4 * c4;
-          d[0] = Mma<PR>::cvt(v.x);
-          d[1] = Mma<PR>::cvt(v.y);
-          d[2] = Mma<PR>::cvt(v.z);
-          d[3] = Mma<PR>::cvt(v.w);
-        }
-        if constexpr (OP == 1 && PR == 1) {
-          // T^T in bf16 pairs: rows i and i+1 of the tile sit in lanes l and l^16 (same
-          // columns); they swap half their values so that each writes two 32-bit words
-          // (columns 4c4, 4c4+1 from the even row's lane, 4c4+2, 4c4+3 from the odd one),
-          // half the stores of one 16-bit store per element and fewer of them per bank
+        if constexpr (PR == 1) {
+          // the four values as two bf16 pairs, stored to the row-major tile as one 8-byte word
+          // (ldT is a multiple of 4 elements)
           const uint32_t p01 = (uint32_t)bf16_u16(v.x) | ((uint32_t)bf16_u16(v.y) << 16);
           const uint32_t p23 = (uint32_t)bf16_u16(v.z) | ((uint32_t)bf16_u16(v.w) << 16);
-          const bool odd = (i & 1) != 0;
-          const uint32_t got = (uint32_t)__shfl_xor((int)(odd ? p01 : p23), 16);
-          const int ie = i & ~1;  // the pair's even row
-          if (ie < In) {
-            uint32_t* w0 = (uint32_t*)(Tji + (4 * c4 + (odd ? 2 : 0)) * ldI + ie);
-            uint32_t* w1 = (uint32_t*)(Tji + (4 * c4 + (odd ? 3 : 1)) * ldI + ie);
-            if (!odd) {
-              *w0 = (p01 & 0xFFFFu) | (got << 16);
-              *w1 = (p01 >> 16) | (got & 0xFFFF0000u);
-            } else {
-              *w0 = (got & 0xFFFFu) | (p23 << 16);
-              *w1 = (got >> 16) | (p23 & 0xFFFF0000u);
+          if (i < In) *(uint2*)(Tij + i * ldT + 4 * c4) = make_uint2(p01, p23);
+          if constexpr (OP == 1) {
+            // T^T in bf16 pairs: rows i and i+1 of the tile sit in lanes l and l^16 (same
+            // columns); they swap half their values so that each writes two 32-bit words
+            // (columns 4c4, 4c4+1 from the even row's lane, 4c4+2, 4c4+3 from the odd one),
+            // half the stores of one 16-bit store per element and fewer of them per bank
+            const bool odd = (i & 1) != 0;
+            const uint32_t got = (uint32_t)__shfl_xor((int)(odd ? p01 : p23), 16);
+            const int ie = i & ~1;  // the pair's even row
+            if (ie < In) {
+              uint32_t* w0 = (uint32_t*)(Tji + (4 * c4 + (odd ? 2 : 0)) * ldI + ie);
+              uint32_t* w1 = (uint32_t*)(Tji + (4 * c4 + (odd ? 3 : 1)) * ldI + ie);
+              if (!odd) {
+                *w0 = (p01 & 0xFFFFu) | (got << 16);
+                *w1 = (p01 >> 16) | (got & 0xFFFF0000u);
+              } else {
+                *w0 = (got & 0xFFFFu) | (p23 << 16);
+                *w1 = (got >> 16) | (p23 & 0xFFFF0000u);
+              }
             }
           }
-        } else if constexpr (OP == 1) {
+        } else {
           if (i < In) {
+            T* d = Tij + i * ldT + 4 * c4;
+            d[0] = Mma<PR>::cvt(v.x);
+            d[1] = Mma<PR>::cvt(v.y);
+            d[2] = Mma<PR>::cvt(v.z);
+            d[3] = Mma<PR>::cvt(v.w);
+          }
+          if (OP == 1 && i < In) {
             Tji[(4 * c4 + 0) * ldI + i] = Mma<PR>::cvt(v.x);
             Tji[(4 * c4 + 1) * ldI + i] = Mma<PR>::cvt(v.y);
             Tji[(4 * c4 + 2) * ldI + i] = Mma<PR>::cvt(v.z);

@@ -196,7 +196,12 @@ __global__ __launch_bounds__(1024) void slab_pass_kernel(SlabArgs p) {
     __syncthreads();  // the previous slab's LDS reads are done
     // the slab into LDS as bf16, row-major
     {
+      // power step: the walk is restarted from values the compiler must treat as new each
+      // slab (left loop-invariant, the store addresses are hoisted and spill to scratch, read
+      // back every slab); the sketch step keeps them hoisted, its VALU time drawing the
+      // Gaussian blocks costs more than its small spill
       int i = st_i0, c = st_c0;
+      if constexpr (OP == 1) asm volatile("" : "+v"(i), "+v"(c));
 #pragma unroll
       for (int s = 0; s < LDN; ++s) {
         const int f = tid + nth * s;
