@@ -17,7 +17,7 @@
 // 16-byte loads while the current one is processed; the slab is stored in LDS as bf16 (round to
 // nearest even), row-major.  Wave w owns row strip w (rows 16w..16w+15: products contracting
 // over the columns, A fragments read as 16-byte rows) and column strip w (columns 16w..16w+15:
-// products contracting over the rows, fragments gathered from eight rows).  Products are
+// products contracting over the rows, fragments read with transposing LDS loads).  Products are
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation; each wave keeps its share of Y_{N-1} and
 // Y_N in accumulators across all its slabs and writes one partial per work-group, summed in a
 // fixed order by reduce_partials.
@@ -80,14 +80,24 @@ __device__ __forceinline__ f32x4 mma16(bf16x8 a, bf16x8 b, f32x4 c) {
 // 8 contiguous bf16 (16-byte aligned).
 __device__ __forceinline__ bf16x8 frag_row(const u16* p) { return *(const bf16x8*)p; }
 
-// 8 bf16 from 8 rows of one column (row pitch ld).
-__device__ __forceinline__ bf16x8 frag_col(const u16* p, int ld) {
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+
+// Column fragment of a row-major LDS tile: lane 16 g + m gets the 8 values of column m at rows
+// 8 g .. 8 g + 7, the MFMA operand layout, from two transposing reads (ds_read_b64_tr_b16).
+// Each lane names one 8-byte run of a row: within a 16-lane block, output lane 4 q + e receives
+// element e of the runs named by lanes q, q + 4, q + 8, q + 12 (in that order).  So lane
+// 16 g + r names row 8 g + (r >> 2) (+ 4 for the second read), columns 4 (r & 3) .. + 3;
+// ``p`` is that address for the first read (row pitch ld, a multiple of 4).
+__device__ __forceinline__ bf16x8 frag_col_tr(const u16* p, int ld) {
+  const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)p);
+  const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + 4 * ld));
   union {
-    u16 h[8];
+    s16x4 h[2];
     bf16x8 v;
   } u;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) u.h[j] = p[j * ld];
+  u.h[0] = lo;
+  u.h[1] = hi;
   return u.v;
 }
 
@@ -196,12 +206,11 @@ __global__ __launch_bounds__(1024) void slab_pass_kernel(SlabArgs p) {
     __syncthreads();  // the previous slab's LDS reads are done
     // the slab into LDS as bf16, row-major
     {
-      // power step: the walk is restarted from values the compiler must treat as new each
-      // slab (left loop-invariant, the store addresses are hoisted and spill to scratch, read
-      // back every slab); the sketch step keeps them hoisted, its VALU time drawing the
-      // Gaussian blocks costs more than its small spill
+      // the walk is restarted from values the compiler must treat as new each slab: left
+      // loop-invariant, the store addresses are hoisted and spill to scratch, read back every
+      // slab
       int i = st_i0, c = st_c0;
-      if constexpr (OP == 1) asm volatile("" : "+v"(i), "+v"(c));
+      asm volatile("" : "+v"(i), "+v"(c));
 #pragma unroll
       for (int s = 0; s < LDN; ++s) {
         const int f = tid + nth * s;
@@ -235,9 +244,9 @@ __global__ __launch_bounds__(1024) void slab_pass_kernel(SlabArgs p) {
         }
       }
       if (colW) {  // Y_N[strip cols] += S^T Mq   (contraction over i_p)
-        const u16* acol = Ss + (8 * g4) * ldS + 16 * wid + m16;
+        const u16* acol = Ss + (8 * g4 + (m16 >> 2)) * ldS + 16 * wid + 4 * (m16 & 3);
         for (int c = 0; c < ncp; ++c) {
-          const bf16x8 av = frag_col(acol + 32 * c * ldS, ldS);
+          const bf16x8 av = frag_col_tr(acol + 32 * c * ldS, ldS);
 #pragma unroll
           for (int t = 0; t < 2; ++t)
             if (t < KqT) accq[t] = mma16(av, frag_row(Mq + min(16 * t + m16, Kq - 1) * ldP + 32 * c + 8 * g4), accq[t]);
@@ -270,9 +279,9 @@ __global__ __launch_bounds__(1024) void slab_pass_kernel(SlabArgs p) {
       }
       if (colW) {
         f32x4 v[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-        const u16* acol = Ss + (8 * g4) * ldS + 16 * wid + m16;
+        const u16* acol = Ss + (8 * g4 + (m16 >> 2)) * ldS + 16 * wid + 4 * (m16 & 3);
         for (int c = 0; c < ncp; ++c) {
-          const bf16x8 av = frag_col(acol + 32 * c * ldS, ldS);
+          const bf16x8 av = frag_col_tr(acol + 32 * c * ldS, ldS);
 #pragma unroll
           for (int t = 0; t < 2; ++t)
             if (t < KpT) v[t] = mma16(av, frag_row(Ba + min(16 * t + m16, Kp - 1) * ldP + 32 * c + 8 * g4), v[t]);
@@ -298,9 +307,9 @@ __global__ __launch_bounds__(1024) void slab_pass_kernel(SlabArgs p) {
         }
       }
       if (colW) {
-        const u16* acol = Ss + (8 * g4) * ldS + 16 * wid + m16;
+        const u16* acol = Ss + (8 * g4 + (m16 >> 2)) * ldS + 16 * wid + 4 * (m16 & 3);
         for (int c = 0; c < ncp; ++c) {
-          const bf16x8 av = frag_col(acol + 32 * c * ldS, ldS);
+          const bf16x8 av = frag_col_tr(acol + 32 * c * ldS, ldS);
 #pragma unroll
           for (int t = 0; t < 2; ++t)
             if (t < KqT) accq[t] = mma16(av, frag_row(Bc + min(16 * t + m16, Kq - 1) * ldP + 32 * c + 8 * g4), accq[t]);
