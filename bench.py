@@ -24,9 +24,9 @@ HBM_PEAK_GBPS = 8000.0
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # (scaled by what the counters read for kernels of known traffic), valid only for the kernel
 # source they were taken on.
-TRAFFIC = {"power_fused": {"bytes_per_launch": 6408583630, "workload": "dense-200^4 bf16",
+TRAFFIC = {"power_fused": {"bytes_per_launch": 6408565302, "workload": "dense-200^4 bf16",
                            "source": "paper_1901_01652_amd/csrc/fastpass.hip",
-                           "sha256": "51443e23e5bbdcb476deda4e6e237cfba97c68df8d5e8095b84743fd0130a68e",
+                           "sha256": "da0d87f5c111a3dcca1a5aa77c44e52b45aedbf9bfb3bdb60d5f886dacadd4fc",
                            "profile": "profiles/dense200_hbm_traffic_counters.md"}}
 
 

@@ -76,14 +76,57 @@ struct PassLayout {
   __host__ __device__ PassLayout(int64_t In, int K, int ldT, int ldI) {
     const int a = 16 / (int)sizeof(T);
     auto up = [a](int v) { return (v + a - 1) / a * a; };
-    const int MTp = (int)((In + 15) / 16) * 16, KTp = ((K + 15) / 16) * 16;
+    // bf16 power step: no transposed copy (its products read the row-major tile with
+    // transposing loads), and the tile spans whole 32-row contraction chunks (zero rows)
+    constexpr bool tr = OP == 1 && PR == 1;
+    const int MTp = tr ? (int)((In + 31) / 32) * 32 : (int)((In + 15) / 16) * 16;
+    const int KTp = ((K + 15) / 16) * 16;
     oTij = 0;
     oOt = up(oTij + MTp * ldT);
     oTji = up(oOt + KTp * ldT);
-    oQt = up(oTji + (OP == 1 ? kFpTJ * ldI : 0));
+    oQt = up(oTji + (OP == 1 && !tr ? kFpTJ * ldI : 0));
     total = up(oQt + (OP == 1 ? KTp * ldI : 0));
   }
 };
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+
+// One 16 x 16 tile of W^T = Q^T T for the bf16 power step: A = rows of Q^T (contraction index
+// i contiguous, pitch ldq), B = column block jt of the row-major tile T [i][j] (pitch ldt, the
+// 8-column groups permuted as in swz_col when LD == 1), read with transposing LDS loads
+// (ds_read_b64_tr_b16) instead of from a transposed copy.  In each 16-lane block the load
+// gives lane 4 q + e element e of the 8-byte row runs named by lanes q, q + 4, q + 8, q + 12,
+// so lane 16 g + r names row 8 g + (r >> 2) (and + 4), columns 16 jt + 4 (r & 3) .. + 3, and
+// receives T[8 g .. 8 g + 7][16 jt + r], the B operand.  Blocks with g odd read their upper
+// four rows first: with a pitch of 36 words the eight rows of a 32-lane read then fall on
+// disjoint banks; their halves come back swapped and are put in order with a select.
+template <int LD>
+__device__ __forceinline__ f32x4 wt_tile_tr(const __bf16* Qt, int ldq, const __bf16* Tij, int ldt,
+                                            int jt, int kdim) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const bool up = (g & 1) != 0;
+  const __bf16* a = Qt + r * ldq + 8 * g;
+  const int r0 = 8 * g + (r >> 2) + (up ? 4 : 0), r1 = r0 + (up ? -4 : 4);
+  const int c = 16 * jt + 4 * (r & 3);
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < kdim; k += 32) {
+    const int ra = k + r0, rb = k + r1;
+    const int ca = LD == 1 ? swz_col(ra, c) : c, cb = LD == 1 ? swz_col(rb, c) : c;
+    const s16x4 x = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(Tij + ra * ldt + ca));
+    const s16x4 y = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(Tij + rb * ldt + cb));
+    union {
+      s16x4 h[2];
+      bf16x8 v;
+    } u;
+    u.h[0] = up ? y : x;
+    u.h[1] = up ? x : y;
+    const bf16x8 av = *(const bf16x8*)(a + k);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, u.v, acc, 0, 0, 0);
+  }
+  return acc;
+}
 
 // AQ: 16x16 output tiles of Y per wavefront (4 covers In <= 128 x K <= 64 or In <= 256 x
 // K <= 32, 8 the rest).  With the 16-byte loader and AQ = 4 the kernel is held to 128 VGPRs
@@ -172,26 +215,6 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
           const uint32_t p01 = (uint32_t)bf16_u16(v.x) | ((uint32_t)bf16_u16(v.y) << 16);
           const uint32_t p23 = (uint32_t)bf16_u16(v.z) | ((uint32_t)bf16_u16(v.w) << 16);
           if (i < In) *(uint2*)(Tij + i * ldT + 4 * c4) = make_uint2(p01, p23);
-          if constexpr (OP == 1) {
-            // T^T in bf16 pairs: rows i and i+1 of the tile sit in lanes l and l^16 (same
-            // columns); they swap half their values so that each writes two 32-bit words
-            // (columns 4c4, 4c4+1 from the even row's lane, 4c4+2, 4c4+3 from the odd one),
-            // half the stores of one 16-bit store per element and fewer of them per bank
-            const bool odd = (i & 1) != 0;
-            const uint32_t got = (uint32_t)__shfl_xor((int)(odd ? p01 : p23), 16);
-            const int ie = i & ~1;  // the pair's even row
-            if (ie < In) {
-              uint32_t* w0 = (uint32_t*)(Tji + (4 * c4 + (odd ? 2 : 0)) * ldI + ie);
-              uint32_t* w1 = (uint32_t*)(Tji + (4 * c4 + (odd ? 3 : 1)) * ldI + ie);
-              if (!odd) {
-                *w0 = (p01 & 0xFFFFu) | (got << 16);
-                *w1 = (p01 >> 16) | (got & 0xFFFF0000u);
-              } else {
-                *w0 = (got & 0xFFFFu) | (p23 << 16);
-                *w1 = (got >> 16) | (p23 & 0xFFFF0000u);
-              }
-            }
-          }
         } else {
           if (i < In) {
             T* d = Tij + i * ldT + 4 * c4;
@@ -221,7 +244,7 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
           Tij[(i + 1) * ldT + swz_col(i + 1, al)] = Mma<PR>::cvt(v.y);
           Tij[(i + 2) * ldT + swz_col(i + 2, al)] = Mma<PR>::cvt(v.z);
           Tij[(i + 3) * ldT + swz_col(i + 3, al)] = Mma<PR>::cvt(v.w);
-          if (OP == 1) {
+          if (OP == 1 && PR != 1) {
             T* d = Tji + al * ldI + i;
             d[0] = Mma<PR>::cvt(v.x);
             d[1] = Mma<PR>::cvt(v.y);
@@ -239,7 +262,7 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
           const float4 v4 = buf[s >> 2];
           const float v = (s & 3) == 0 ? v4.x : (s & 3) == 1 ? v4.y : (s & 3) == 2 ? v4.z : v4.w;
           Tij[i * ldT + jl] = Mma<PR>::cvt(v);
-          if (OP == 1) Tji[jl * ldI + i] = Mma<PR>::cvt(v);
+          if (OP == 1 && PR != 1) Tji[jl * ldI + i] = Mma<PR>::cvt(v);
         }
       }
     }
@@ -345,8 +368,12 @@ __global__ __launch_bounds__(kFpThreads, (LD == 0 && AQ == 4 ? 4 : 2)) void mode
         const int q = wid + 8 * s;
         if (q < NT * 4) {
           const int nt = q >> 2, jt = q & 3;
-          f32x4 w = tile_abt(Qt + nt * 16 * ldI, ldI, Tji + jt * 16 * ldI, ldI, p.kI,
-                             f32x4{0.f, 0.f, 0.f, 0.f});
+          f32x4 w;
+          if constexpr (PR == 1)
+            w = wt_tile_tr<LD>(Qt + nt * 16 * ldI, ldI, Tij, ldT, jt, p.kI);
+          else
+            w = tile_abt(Qt + nt * 16 * ldI, ldI, Tji + jt * 16 * ldI, ldI, p.kI,
+                         f32x4{0.f, 0.f, 0.f, 0.f});
           const int col = jt * 16 + (lane & 15);
 #pragma unroll
           for (int r = 0; r < 4; ++r) Ot[(nt * 16 + 4 * (lane >> 4) + r) * ldT + col] = Mma<PR>::cvt(w[r]);
