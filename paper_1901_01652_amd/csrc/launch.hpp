@@ -340,7 +340,8 @@ hipError_t launch_residual(bool f32, const void* X, int64_t IL, int64_t IR, int 
 
 // ---- svd.hip --------------------------------------------------------------------------
 constexpr int kSvdMaxDim = 512;  // largest Gram size min(m, n) of a TR-SVD step
-constexpr int kSvdLdsDim = 88;   // Gram sizes up to this are diagonalised in LDS
+constexpr int kSvdLdsDim = 96;   // Gram sizes up to this are diagonalised in LDS
+constexpr int kSvdLdsADim = 136; // up to this the Gram sits in LDS, its eigenvectors in HBM
 struct SvdState {                // device-resident shape and bookkeeping of the sequence
   int m, n, d, rows, r, capped;
   int ranks[8];

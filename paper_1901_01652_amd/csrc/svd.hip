@@ -102,30 +102,33 @@ __global__ __launch_bounds__(256) void svd_gram_kernel(const SvdState* __restric
 
 // Symmetric eigen-decomposition of the d x d Gram A (cyclic Jacobi, Golub & Van Loan
 // Alg. 8.5.2 / 8.5.3 with the parallel round-robin ordering), then the truncation of this
-// step.  SH: A and V held in LDS (d <= kSvdLdsDim), otherwise in the global workspace.
-template <bool SH>
+// step.  MODE 1: A and V held in LDS (d <= kSvdLdsDim); MODE 2: A in LDS, V in the global
+// workspace (d <= kSvdLdsADim); MODE 0: both in the global workspace.  The bookkeeping arrays
+// are sized for each mode's largest d, so that they leave the LDS to A and V.
+template <int MODE>
 __global__ __launch_bounds__(kEigThreads) void svd_eig_kernel(SvdState* __restrict__ st,
                                                               double* __restrict__ Ag,
                                                               double* __restrict__ Vg,
                                                               double* __restrict__ W,
                                                               double* __restrict__ sv,
                                                               SvdCaps caps, int step) {
+  constexpr int MAXD = MODE == 1 ? kSvdLdsDim : MODE == 2 ? kSvdLdsADim : kSvdMaxDim;
   extern __shared__ double smem[];
-  __shared__ int pr_p[kSvdMaxDim / 2], pr_q[kSvdMaxDim / 2];
-  __shared__ double pr_c[kSvdMaxDim / 2], pr_s[kSvdMaxDim / 2];
-  __shared__ double pr_dp[kSvdMaxDim / 2], pr_dq[kSvdMaxDim / 2];
-  __shared__ unsigned char pr_rot[kSvdMaxDim / 2];
-  __shared__ double lam[kSvdMaxDim], tail[kSvdMaxDim + 1];
-  __shared__ int perm[kSvdMaxDim];
+  __shared__ int pr_p[MAXD / 2], pr_q[MAXD / 2];
+  __shared__ double pr_c[MAXD / 2], pr_s[MAXD / 2];
+  __shared__ double pr_dp[MAXD / 2], pr_dq[MAXD / 2];
+  __shared__ unsigned char pr_rot[MAXD / 2];
+  __shared__ double lam[MAXD], tail[MAXD + 1];
+  __shared__ int perm[MAXD];
   __shared__ int s_any, s_r;
   __shared__ double s_abs;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int d = st->d;
-  double* A = SH ? smem : Ag;
-  double* V = SH ? smem + d * d : Vg;
+  double* A = MODE != 0 ? smem : Ag;
+  double* V = MODE == 1 ? smem + d * d : Vg;
   const int dd = d * d;
   for (int e = tid; e < dd; e += nth) {
-    if (SH) A[e] = Ag[e];
+    if (MODE != 0) A[e] = Ag[e];
     const int i = e / d, j = e - i * d;
     V[e] = (i == j) ? 1.0 : 0.0;
   }
@@ -434,14 +437,21 @@ hipError_t launch_svd_step(SvdState* st, const double* C, double* A, double* V, 
   prof_begin("svd_eig", s);
   if (dmax <= kSvdLdsDim) {
     const size_t lds = (size_t)2 * dmax * dmax * sizeof(double);
-    e = hipFuncSetAttribute((const void*)svd_eig_kernel<true>,
+    e = hipFuncSetAttribute((const void*)svd_eig_kernel<1>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(svd_eig_kernel<true>, dim3(1), dim3(kEigThreads), lds, s, st, A, V, W,
-                       sv, caps, step);
+    hipLaunchKernelGGL(svd_eig_kernel<1>, dim3(1), dim3(kEigThreads), lds, s, st, A, V, W, sv,
+                       caps, step);
+  } else if (dmax <= kSvdLdsADim) {
+    const size_t lds = (size_t)dmax * dmax * sizeof(double);
+    e = hipFuncSetAttribute((const void*)svd_eig_kernel<2>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(svd_eig_kernel<2>, dim3(1), dim3(kEigThreads), lds, s, st, A, V, W, sv,
+                       caps, step);
   } else {
-    hipLaunchKernelGGL(svd_eig_kernel<false>, dim3(1), dim3(kEigThreads), 0, s, st, A, V, W,
-                       sv, caps, step);
+    hipLaunchKernelGGL(svd_eig_kernel<0>, dim3(1), dim3(kEigThreads), 0, s, st, A, V, W, sv,
+                       caps, step);
   }
   prof_end(s);
   e = hipGetLastError();

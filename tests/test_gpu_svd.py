@@ -83,10 +83,14 @@ def test_tr_svd_matrix_is_eckart_young(h):
     assert abs(err - np.sqrt(np.sum(s[r:] ** 2)) / np.linalg.norm(P)) < 1e-12
 
 
-@pytest.mark.parametrize("dims,eps,caps", [((120, 200), 0.02, [128, 128]),
-                                           ((100, 150, 3), 0.01, [12, 12, 32])])
+@pytest.mark.parametrize("dims,eps,caps", [((96, 130), 0.02, [128, 128]),
+                                           ((120, 200), 0.02, [128, 128]),
+                                           ((100, 150, 3), 0.01, [12, 12, 32]),
+                                           ((150, 180), 0.02, [160, 160])])
 def test_tr_svd_large_gram(h, dims, eps, caps):
-    """Gram sizes above the LDS-resident limit run the eigen-solver from the workspace."""
+    """The eigen-solver's three homes: Gram and eigenvectors in LDS (d = 96, the largest),
+    the Gram in LDS and the eigenvectors in the workspace (d = 100, 120), both in the
+    workspace (d = 150)."""
     say("tr-svd large gram", dims, eps)
     P = low_rank_plus_noise(dims, 4, 0.2, seed=11)
     cores, ranks, err, bits = run(h, P, caps, eps)
