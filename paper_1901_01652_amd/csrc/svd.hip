@@ -102,40 +102,63 @@ __global__ __launch_bounds__(256) void svd_gram_kernel(const SvdState* __restric
 
 // Symmetric eigen-decomposition of the d x d Gram A (cyclic Jacobi, Golub & Van Loan
 // Alg. 8.5.2 / 8.5.3 with the parallel round-robin ordering), then the truncation of this
-// step.  MODE 1: A and V held in LDS (d <= kSvdLdsDim); MODE 2: A in LDS, V in the global
-// workspace (d <= kSvdLdsADim); MODE 0: both in the global workspace.  The bookkeeping arrays
-// are sized for each mode's largest d, so that they leave the LDS to A and V.
-template <int MODE>
+// step.  The homes of A and V follow the step's actual Gram size d (known on the device only):
+// both in LDS for d <= kSvdLdsDim, A in LDS and V in the global workspace for d <=
+// kSvdLdsADim, both in the workspace above that.  The rotation and ordering arrays follow A
+// and V in the same dynamic LDS block (svd_eig_lds bytes cover every case).
+__device__ __host__ inline size_t svd_eig_book(int d) {
+  const int np = (d + 1) / 2;
+  return (size_t)np * (4 * sizeof(double) + 2 * sizeof(int) + 1) + (size_t)(2 * d + 1) * sizeof(double) +
+         (size_t)d * sizeof(int);
+}
+
+static size_t svd_eig_lds(int dmax) {
+  auto both = [](int d) { return (size_t)(d * (d | 1) + d * d) * sizeof(double) + svd_eig_book(d); };
+  if (dmax <= kSvdLdsDim) return both(dmax);
+  const size_t a = (size_t)kSvdLdsADim * (kSvdLdsADim | 1) * sizeof(double) + svd_eig_book(kSvdLdsADim);
+  const size_t b = both(kSvdLdsDim);
+  return std::max(std::max(a, b), svd_eig_book(std::min(dmax, kSvdMaxDim)));
+}
+
 __global__ __launch_bounds__(kEigThreads) void svd_eig_kernel(SvdState* __restrict__ st,
                                                               double* __restrict__ Ag,
                                                               double* __restrict__ Vg,
                                                               double* __restrict__ W,
                                                               double* __restrict__ sv,
                                                               SvdCaps caps, int step) {
-  constexpr int MAXD = MODE == 1 ? kSvdLdsDim : MODE == 2 ? kSvdLdsADim : kSvdMaxDim;
   extern __shared__ double smem[];
-  __shared__ int pr_p[MAXD / 2], pr_q[MAXD / 2];
-  __shared__ double pr_c[MAXD / 2], pr_s[MAXD / 2];
-  __shared__ double pr_dp[MAXD / 2], pr_dq[MAXD / 2];
-  __shared__ unsigned char pr_rot[MAXD / 2];
-  __shared__ double lam[MAXD], tail[MAXD + 1];
-  __shared__ int perm[MAXD];
   __shared__ int s_any, s_r;
   __shared__ double s_abs;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int d = st->d;
-  double* A = MODE != 0 ? smem : Ag;
-  double* V = MODE == 1 ? smem + d * d : Vg;
+  const int mode = d <= kSvdLdsDim ? 1 : d <= kSvdLdsADim ? 2 : 0;
   const int dd = d * d;
+  // A in LDS with an odd pitch (in doubles), so that the column updates of lanes on
+  // consecutive rows fall on different banks; V kept transposed (Vt[p][i] = V[i][p]), so that
+  // its column updates are contiguous rows
+  const int lda = mode != 0 ? (d | 1) : d;
+  double* A = mode != 0 ? smem : Ag;
+  double* Vt = mode == 1 ? smem + d * lda : Vg;
+  const int nph = (d + 1) / 2;
+  double* pr_c = smem + (mode == 1 ? d * lda + dd : mode == 2 ? d * lda : 0);
+  double* pr_s = pr_c + nph;
+  double* pr_dp = pr_s + nph;
+  double* pr_dq = pr_dp + nph;
+  double* lam = pr_dq + nph;
+  double* tail = lam + d;
+  int* pr_p = (int*)(tail + d + 1);
+  int* pr_q = pr_p + nph;
+  int* perm = pr_q + nph;
+  unsigned char* pr_rot = (unsigned char*)(perm + d);
   for (int e = tid; e < dd; e += nth) {
-    if (MODE != 0) A[e] = Ag[e];
+    if (mode != 0) A[(e / d) * lda + e % d] = Ag[e];
     const int i = e / d, j = e - i * d;
-    V[e] = (i == j) ? 1.0 : 0.0;
+    Vt[e] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
   if (tid == 0) {
     double tr = 0.0;
-    for (int i = 0; i < d; ++i) tr += fabs(A[i * d + i]);
+    for (int i = 0; i < d; ++i) tr += fabs(A[i * lda + i]);
     s_abs = 1e-22 * tr;  // off-diagonal entries below this are negligible
   }
   __syncthreads();
@@ -159,7 +182,7 @@ __global__ __launch_bounds__(kEigThreads) void svd_eig_kernel(SvdState* __restri
         unsigned char rot = 0;
         double c = 1.0, s = 0.0, dpp = 0.0, dqq = 0.0;
         if (q < d) {
-          const double app = A[p * d + p], aqq = A[q * d + q], apq = A[p * d + q];
+          const double app = A[p * lda + p], aqq = A[q * lda + q], apq = A[p * lda + q];
           if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app * aqq)), abs_tol)) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
@@ -180,37 +203,42 @@ __global__ __launch_bounds__(kEigThreads) void svd_eig_kernel(SvdState* __restri
         pr_rot[tid] = rot;
       }
       __syncthreads();
-      // A <- J^T A: rows p and q of every rotation
-      for (int e = tid; e < npairs * d; e += nth) {
-        const int t = e / d, j = e - t * d;
-        if (!pr_rot[t]) continue;
-        const int p = pr_p[t], q = pr_q[t];
-        const double c = pr_c[t], s = pr_s[t];
-        const double apj = A[p * d + j], aqj = A[q * d + j];
-        A[p * d + j] = c * apj - s * aqj;
-        A[q * d + j] = s * apj + c * aqj;
+      // A <- J^T A J in one pass: the pairs partition the indices, so the 2 x 2 block of pair
+      // t's rows and pair u's columns becomes J_t^T M J_u from its own four entries (a pair
+      // left alone has c = 1, s = 0; the spare index of an odd d has no row or column).  The
+      // pivot blocks (t = u) are set exactly.  V <- V J on the rows of Vt in the same phase.
+      const int nb = npairs * npairs;
+      for (int e = tid; e < nb; e += nth) {
+        const int t = e / npairs, u = e - t * npairs;
+        const bool rt = pr_rot[t] != 0, ru = pr_rot[u] != 0;
+        if (!rt && !ru) continue;
+        const int p = pr_p[t], q = pr_q[t], pu = pr_p[u], qu = pr_q[u];
+        if (t == u) {
+          A[p * lda + p] = pr_dp[t];
+          A[q * lda + q] = pr_dq[t];
+          A[p * lda + q] = 0.0;
+          A[q * lda + p] = 0.0;
+          continue;
+        }
+        const bool hq = q < d, hqu = qu < d;
+        const double x = A[p * lda + pu], y = hqu ? A[p * lda + qu] : 0.0;
+        const double z = hq ? A[q * lda + pu] : 0.0, w = hq && hqu ? A[q * lda + qu] : 0.0;
+        const double ct = pr_c[t], st_ = pr_s[t], cu = pr_c[u], su = pr_s[u];
+        const double a1 = ct * x - st_ * z, b1 = ct * y - st_ * w;
+        const double a2 = st_ * x + ct * z, b2 = st_ * y + ct * w;
+        A[p * lda + pu] = cu * a1 - su * b1;
+        if (hqu) A[p * lda + qu] = su * a1 + cu * b1;
+        if (hq) A[q * lda + pu] = cu * a2 - su * b2;
+        if (hq && hqu) A[q * lda + qu] = su * a2 + cu * b2;
       }
-      __syncthreads();
-      // A <- A J and V <- V J: columns p and q; the 2 x 2 pivot block is set exactly
       for (int e = tid; e < npairs * d; e += nth) {
         const int t = e / d, i = e - t * d;
         if (!pr_rot[t]) continue;
         const int p = pr_p[t], q = pr_q[t];
         const double c = pr_c[t], s = pr_s[t];
-        const double aip = A[i * d + p], aiq = A[i * d + q];
-        double np = c * aip - s * aiq, nq = s * aip + c * aiq;
-        if (i == p) {
-          np = pr_dp[t];
-          nq = 0.0;
-        } else if (i == q) {
-          np = 0.0;
-          nq = pr_dq[t];
-        }
-        A[i * d + p] = np;
-        A[i * d + q] = nq;
-        const double vip = V[i * d + p], viq = V[i * d + q];
-        V[i * d + p] = c * vip - s * viq;
-        V[i * d + q] = s * vip + c * viq;
+        const double vip = Vt[p * d + i], viq = Vt[q * d + i];
+        Vt[p * d + i] = c * vip - s * viq;
+        Vt[q * d + i] = s * vip + c * viq;
       }
       __syncthreads();
     }
@@ -219,7 +247,7 @@ __global__ __launch_bounds__(kEigThreads) void svd_eig_kernel(SvdState* __restri
     if (!any) break;
   }
   // eigenvalues in descending order (ties by index)
-  for (int i = tid; i < d; i += nth) lam[i] = A[i * d + i];
+  for (int i = tid; i < d; i += nth) lam[i] = A[i * lda + i];
   __syncthreads();
   double lsorted = 0.0;
   int myrank = -1;
@@ -274,7 +302,7 @@ __global__ __launch_bounds__(kEigThreads) void svd_eig_kernel(SvdState* __restri
   const int r = s_r;
   for (int e = tid; e < d * r; e += nth) {
     const int i = e / r, c = e - i * r;
-    W[e] = V[i * d + perm[c]];
+    W[e] = Vt[perm[c] * d + i];
   }
   for (int c = tid; c < r; c += nth) sv[c] = sqrt(fmax(lam[c], 0.0));
 }
@@ -435,24 +463,12 @@ hipError_t launch_svd_step(SvdState* st, const double* C, double* A, double* V, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   prof_begin("svd_eig", s);
-  if (dmax <= kSvdLdsDim) {
-    const size_t lds = (size_t)2 * dmax * dmax * sizeof(double);
-    e = hipFuncSetAttribute((const void*)svd_eig_kernel<1>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(svd_eig_kernel<1>, dim3(1), dim3(kEigThreads), lds, s, st, A, V, W, sv,
-                       caps, step);
-  } else if (dmax <= kSvdLdsADim) {
-    const size_t lds = (size_t)dmax * dmax * sizeof(double);
-    e = hipFuncSetAttribute((const void*)svd_eig_kernel<2>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(svd_eig_kernel<2>, dim3(1), dim3(kEigThreads), lds, s, st, A, V, W, sv,
-                       caps, step);
-  } else {
-    hipLaunchKernelGGL(svd_eig_kernel<0>, dim3(1), dim3(kEigThreads), 0, s, st, A, V, W, sv,
-                       caps, step);
-  }
+  const size_t lds = svd_eig_lds(dmax);
+  e = hipFuncSetAttribute((const void*)svd_eig_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(svd_eig_kernel, dim3(1), dim3(kEigThreads), lds, s, st, A, V, W, sv, caps,
+                     step);
   prof_end(s);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
