@@ -21,18 +21,18 @@ constexpr int kTtmKLimit = 1024;
 template <int AR, typename Tin, int KC>
 __device__ __forceinline__ void ttm_thread(const Tin* __restrict__ in, int64_t A, int64_t In,
                                            int64_t B, int K, const double* __restrict__ Q,
-                                           double* __restrict__ out, int64_t g) {
+                                           double* __restrict__ out, int64_t p, int k0) {
   using Acc = typename std::conditional<AR == kF64, double, float>::type;
   const int64_t nfib = A * B;
-  const int64_t p = g % nfib;
-  const int k0 = (int)(g / nfib) * KC;
-  if (k0 >= K) return;
+  if (p >= nfib || k0 >= K) return;
   const int kn = K - k0 < KC ? K - k0 : KC;
   const int64_t a = p / B, b = p % B;
   const Tin* src = in + a * In * B + b;
   Acc acc[KC];
 #pragma unroll
   for (int k = 0; k < KC; ++k) acc[k] = 0;
+  // every k < KC accumulates (columns k >= kn read column k0, always in range, and are
+  // discarded at the store), so the uniform Q loads issue back to back without branches
   for (int64_t i = 0; i < In; ++i) {
     const double* q = Q + i * K + k0;
     if constexpr (AR == kBF16) {
@@ -41,18 +41,15 @@ __device__ __forceinline__ void ttm_thread(const Tin* __restrict__ in, int64_t A
       const float xl = bf16_round(x - xh);
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
-        if (k < kn) {
-          const float qf = (float)q[k];
-          const float qh = bf16_round(qf);
-          const float ql = bf16_round(qf - qh);
-          acc[k] += xh * qh + (xh * ql + xl * qh);
-        }
+        const float qf = (float)q[k < kn ? k : 0];
+        const float qh = bf16_round(qf);
+        const float ql = bf16_round(qf - qh);
+        acc[k] += xh * qh + (xh * ql + xl * qh);
       }
     } else {
       const Acc x = (Acc)src[i * B];
 #pragma unroll
-      for (int k = 0; k < KC; ++k)
-        if (k < kn) acc[k] += x * (Acc)q[k];
+      for (int k = 0; k < KC; ++k) acc[k] += x * (Acc)q[k < kn ? k : 0];
     }
   }
   double* dst = out + a * (int64_t)K * B + b;
@@ -61,12 +58,15 @@ __device__ __forceinline__ void ttm_thread(const Tin* __restrict__ in, int64_t A
     if (k < kn) dst[(int64_t)(k0 + k) * B] = (double)acc[k];
 }
 
+// Grid (fiber blocks, k-groups): the k-group is the block's y index, so every wavefront reads
+// the same row of Q and those loads go through the scalar cache.
 template <int AR, typename Tin, int KC>
 __global__ __launch_bounds__(256) void ttm_kernel(const Tin* __restrict__ in, int64_t A,
                                                   int64_t In, int64_t B, int K,
                                                   const double* __restrict__ Q,
                                                   double* __restrict__ out) {
-  ttm_thread<AR, Tin, KC>(in, A, In, B, K, Q, out, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  ttm_thread<AR, Tin, KC>(in, A, In, B, K, Q, out, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                          (int)blockIdx.y * KC);
 }
 
 // One mode product for many tensors in one launch (the batched compression).
@@ -76,8 +76,10 @@ __global__ __launch_bounds__(256) void ttm_list_kernel(const TtmJob* __restrict_
                                                        int njobs) {
   const int j = find_job(block_start, njobs, blockIdx.x);
   const TtmJob g = jobs[j];
-  ttm_thread<AR, Tin, KC>((const Tin*)g.in, g.A, g.In, g.B, g.K, g.Q, g.out,
-                          ((int64_t)blockIdx.x - block_start[j]) * 256 + threadIdx.x);
+  const int64_t t = ((int64_t)blockIdx.x - block_start[j]) * 256 + threadIdx.x;
+  const int64_t nfib = g.A * g.B;
+  ttm_thread<AR, Tin, KC>((const Tin*)g.in, g.A, g.In, g.B, g.K, g.Q, g.out, t % nfib,
+                          (int)(t / nfib) * KC);
 }
 
 int64_t ttm_job_blocks(const TtmJob& g, int kc) {
@@ -113,8 +115,7 @@ hipError_t launch_ttm_list(Arith ar, bool first, int kc, const TtmJob* jobs,
 template <int KC>
 static void launch_ttm_kc(Arith ar, bool first, const void* in, const ModeView& v, int K,
                           const double* Q, double* out, hipStream_t s) {
-  const int64_t n = v.A * v.B * ((K + KC - 1) / KC);
-  const unsigned blocks = (unsigned)((n + 255) / 256);
+  const dim3 blocks((unsigned)((v.A * v.B + 255) / 256), (unsigned)((K + KC - 1) / KC));
   if (!first || ar == kF64) {
     hipLaunchKernelGGL((ttm_kernel<kF64, double, KC>), dim3(blocks), dim3(256), 0, s,
                        (const double*)in, v.A, v.In, v.B, K, Q, out);
