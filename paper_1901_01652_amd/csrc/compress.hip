@@ -33,10 +33,10 @@ __device__ __forceinline__ void ttm_thread(const Tin* __restrict__ in, int64_t A
   for (int k = 0; k < KC; ++k) acc[k] = 0;
   // every k < KC accumulates (columns k >= kn read column k0, always in range, and are
   // discarded at the store), so the uniform Q loads issue back to back without branches
-  for (int64_t i = 0; i < In; ++i) {
+  auto step = [&](Tin xv, int64_t i) {
     const double* q = Q + i * K + k0;
     if constexpr (AR == kBF16) {
-      const float x = (float)src[i * B];
+      const float x = (float)xv;
       const float xh = bf16_round(x);
       const float xl = bf16_round(x - xh);
 #pragma unroll
@@ -47,11 +47,24 @@ __device__ __forceinline__ void ttm_thread(const Tin* __restrict__ in, int64_t A
         acc[k] += xh * qh + (xh * ql + xl * qh);
       }
     } else {
-      const Acc x = (Acc)src[i * B];
+      const Acc x = (Acc)xv;
 #pragma unroll
       for (int k = 0; k < KC; ++k) acc[k] += x * (Acc)q[k < kn ? k : 0];
     }
+  };
+  // elements i = 0, 1, ... in order; each of the two registers is reloaded right after its
+  // element is used, two elements ahead (indices clamped to the fiber), so a load is always
+  // in flight while the other element's sums run
+  const int64_t last = In - 1;
+  Tin xa = src[0], xb = src[(last < 1 ? last : 1) * B];
+  int64_t i = 0;
+  for (; i + 1 < In; i += 2) {
+    step(xa, i);
+    xa = src[(i + 2 < last ? i + 2 : last) * B];
+    step(xb, i + 1);
+    xb = src[(i + 3 < last ? i + 3 : last) * B];
   }
+  if (i < In) step(xa, i);
   double* dst = out + a * (int64_t)K * B + b;
 #pragma unroll
   for (int k = 0; k < KC; ++k)
