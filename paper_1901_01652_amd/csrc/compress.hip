@@ -52,19 +52,26 @@ __device__ __forceinline__ void ttm_thread(const Tin* __restrict__ in, int64_t A
       for (int k = 0; k < KC; ++k) acc[k] += x * (Acc)q[k < kn ? k : 0];
     }
   };
-  // elements i = 0, 1, ... in order; each of the two registers is reloaded right after its
-  // element is used, two elements ahead (indices clamped to the fiber), so a load is always
-  // in flight while the other element's sums run
+  // elements i = 0, 1, ... in order; each of the kAhead registers is reloaded right after its
+  // element is used, kAhead elements ahead (indices clamped to the fiber), so kAhead - 1 loads
+  // are in flight while an element's sums run
+  constexpr int kAhead = 4;
   const int64_t last = In - 1;
-  Tin xa = src[0], xb = src[(last < 1 ? last : 1) * B];
+  Tin xr[kAhead];
+#pragma unroll
+  for (int d = 0; d < kAhead; ++d) xr[d] = src[(d < last ? d : last) * B];
   int64_t i = 0;
-  for (; i + 1 < In; i += 2) {
-    step(xa, i);
-    xa = src[(i + 2 < last ? i + 2 : last) * B];
-    step(xb, i + 1);
-    xb = src[(i + 3 < last ? i + 3 : last) * B];
+  for (; i + kAhead <= In; i += kAhead) {
+#pragma unroll
+    for (int d = 0; d < kAhead; ++d) {
+      step(xr[d], i + d);
+      const int64_t nx = i + d + kAhead;
+      xr[d] = src[(nx < last ? nx : last) * B];
+    }
   }
-  if (i < In) step(xa, i);
+#pragma unroll
+  for (int d = 0; d < kAhead; ++d)
+    if (i + d < In) step(xr[d], i + d);
   double* dst = out + a * (int64_t)K * B + b;
 #pragma unroll
   for (int k = 0; k < KC; ++k)
