@@ -156,8 +156,10 @@ hipError_t launch_ttm(Arith ar, bool first, const void* in, const ModeView& v, i
   // enough threads to cover the GPU: split K when there are few fibers
   if (fibers >= (1 << 17))
     launch_ttm_kc<kTtmKMax>(ar, first, in, v, K, Q, out, s);
-  else
+  else if (fibers >= (1 << 14))
     launch_ttm_kc<4>(ar, first, in, v, K, Q, out, s);
+  else
+    launch_ttm_kc<1>(ar, first, in, v, K, Q, out, s);
   prof_end(s);
   return hipGetLastError();
 }
