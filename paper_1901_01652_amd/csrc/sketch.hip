@@ -366,8 +366,21 @@ __device__ __forceinline__ void reduce_block(const P* __restrict__ partial, int6
   const int64_t nout = In * K;
   const int64_t o = oblock * 64 + lane;
   double s = 0.0;
-  if (o < nout)
-    for (int64_t c = slice; c < chunks; c += 16) s += (double)partial[c * nout + o];
+  if (o < nout) {
+    // chunks slice, slice + 16, ... added in that order; four loads issued before their adds
+    int64_t c = slice;
+    for (; c + 48 < chunks; c += 64) {
+      const double v0 = (double)partial[c * nout + o];
+      const double v1 = (double)partial[(c + 16) * nout + o];
+      const double v2 = (double)partial[(c + 32) * nout + o];
+      const double v3 = (double)partial[(c + 48) * nout + o];
+      s += v0;
+      s += v1;
+      s += v2;
+      s += v3;
+    }
+    for (; c < chunks; c += 16) s += (double)partial[c * nout + o];
+  }
   part[slice][lane] = s;
   __syncthreads();
   if (slice == 0 && o < nout) {
